@@ -1,0 +1,211 @@
+"""Plain CPU oracle for random hyperbolic graph generation (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The product library never loads it, and it never loads
+the product library: the two share no code.  See ``rhg_oracle.c`` for what is
+computed and which passage of the paper each step follows.
+
+The binding is argument marshalling only (numpy arrays in, numpy arrays out);
+every step of the computation runs in the C file.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rhg_oracle.c")
+_BUILD = os.path.join(_HERE, "_build")
+_LIB_PATH = os.path.join(_BUILD, "librhg_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (binary64 + binary128, OpenMP)."""
+    os.makedirs(_BUILD, exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lquadmath", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = C.CDLL(_LIB_PATH)
+        d, i64, u64, i32 = C.c_double, C.c_int64, C.c_uint64, C.c_int
+        pd, pi64, pi32, pu32 = (C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_uint32))
+        lib.orc_philox4x32_10.argtypes = [pu32, pu32, pu32]
+        lib.orc_uniforms.argtypes = [u64, i64, pd, pd]
+        lib.orc_alpha.restype = d
+        lib.orc_alpha.argtypes = [d]
+        lib.orc_kbar_eq22.restype = d
+        lib.orc_kbar_eq22.argtypes = [d, d, d, i32]
+        lib.orc_kbar_minus.restype = d
+        lib.orc_kbar_minus.argtypes = [d, d, d, d]
+        lib.orc_solve_R.restype = i32
+        lib.orc_solve_R.argtypes = [d, d, d, pd, pd]
+        lib.orc_cosh.restype = d
+        lib.orc_cosh.argtypes = [d]
+        lib.orc_radius.restype = d
+        lib.orc_radius.argtypes = [d, d, d, C.POINTER(C.c_int)]
+        lib.orc_sample.restype = i64
+        lib.orc_sample.argtypes = [u64, d, d, i64, i64, pd, pd, i32]
+        lib.orc_is_edge.restype = i32
+        lib.orc_is_edge.argtypes = [d, d, d, d, d, pi64]
+        lib.orc_is_edge_quad.restype = i32
+        lib.orc_is_edge_quad.argtypes = [d, d, d, d, d]
+        lib.orc_degrees.argtypes = [i64, pd, pd, d, pi32, i32, pi64]
+        lib.orc_csr_fill.argtypes = [i64, pd, pd, d, pi64, pi32, i32]
+        lib.orc_rows.restype = i64
+        lib.orc_rows.argtypes = [i64, pd, pd, d, pi64, i64, pi64, pi32, i64, i32, pi64]
+        lib.orc_max_threads.restype = i32
+        _lib = lib
+        return lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: 4 counter words, 2 key words -> 4 output words."""
+    lib = _load()
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib.orc_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+    return out
+
+
+def uniforms(seed: int, i: int):
+    lib = _load()
+    a, b = C.c_double(), C.c_double()
+    lib.orc_uniforms(seed, i, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def alpha(gamma: float) -> float:
+    return float(_load().orc_alpha(gamma))
+
+
+def kbar_eq22(n: float, alpha_: float, R: float, literal: bool = False) -> float:
+    return float(_load().orc_kbar_eq22(float(n), alpha_, R, 1 if literal else 0))
+
+
+def kbar_minus(n: float, alpha_: float, R: float, target: float) -> float:
+    """Eq. (22) minus target, differenced in binary128."""
+    return float(_load().orc_kbar_minus(float(n), alpha_, R, target))
+
+
+def solve_R(n: int, kbar: float, gamma: float):
+    """Return (alpha, R) or raise ValueError when no root exists."""
+    lib = _load()
+    a, r = C.c_double(), C.c_double()
+    if lib.orc_solve_R(float(n), kbar, gamma, C.byref(a), C.byref(r)) != 0:
+        raise ValueError("no radius on the decreasing branch of Eq. (22)")
+    return a.value, r.value
+
+
+def cosh(x: float) -> float:
+    return float(_load().orc_cosh(x))
+
+
+def radius(u: float, alpha_: float, R: float):
+    """Correctly rounded inverse-CDF radius for one uniform: (r, near_midpoint)."""
+    h = C.c_int()
+    r = _load().orc_radius(u, alpha_, R, C.byref(h))
+    return float(r), bool(h.value)
+
+
+def sample(seed: int, alpha_: float, R: float, n: int, i0: int = 0, nthreads: int = 0):
+    """Points i0 .. i0+n-1: returns (r, theta, near_midpoint_count)."""
+    lib = _load()
+    r = np.empty(n, dtype=np.float64)
+    t = np.empty(n, dtype=np.float64)
+    hard = lib.orc_sample(seed, alpha_, R, i0, n, _p(r, C.c_double), _p(t, C.c_double), nthreads)
+    return r, t, int(hard)
+
+
+def is_edge(ri, ti, rj, tj, R):
+    st = np.zeros(2, dtype=np.int64)
+    e = _load().orc_is_edge(ri, ti, rj, tj, R, _p(st, C.c_int64))
+    return bool(e), int(st[0]), int(st[1])
+
+
+def is_edge_quad(ri, ti, rj, tj, R):
+    return bool(_load().orc_is_edge_quad(ri, ti, rj, tj, R))
+
+
+def degrees(r, theta, R, nthreads: int = 0):
+    """Degrees by brute force over all pairs; returns (deg, quad_fallbacks, ties)."""
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    n = r.shape[0]
+    deg = np.zeros(n, dtype=np.int32)
+    st = np.zeros(2, dtype=np.int64)
+    lib.orc_degrees(n, _p(r, C.c_double), _p(theta, C.c_double), R, _p(deg, C.c_int32),
+                    nthreads, _p(st, C.c_int64))
+    return deg, int(st[0]), int(st[1])
+
+
+def csr(r, theta, R, nthreads: int = 0):
+    """Symmetric CSR (int64 row_ptr, int32 col) with ascending rows, plus stats."""
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    deg, nq, nt = degrees(r, theta, R, nthreads)
+    n = r.shape[0]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    col = np.empty(int(row_ptr[-1]), dtype=np.int32)
+    lib.orc_csr_fill(n, _p(r, C.c_double), _p(theta, C.c_double), R, _p(row_ptr, C.c_int64),
+                     _p(col, C.c_int32), nthreads)
+    return row_ptr, col, nq, nt
+
+
+def rows(r, theta, R, which, nthreads: int = 0):
+    """Ascending neighbour lists of the vertices in ``which``, each tested
+    against all n points: returns (ptr, col, quad_fallbacks, ties)."""
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    which = np.ascontiguousarray(which, dtype=np.int64)
+    n = r.shape[0]
+    cap = 1 << 16
+    while True:
+        ptr = np.zeros(which.shape[0] + 1, dtype=np.int64)
+        col = np.empty(cap, dtype=np.int32)
+        st = np.zeros(2, dtype=np.int64)
+        tot = lib.orc_rows(n, _p(r, C.c_double), _p(theta, C.c_double), R, _p(which, C.c_int64),
+                           which.shape[0], _p(ptr, C.c_int64), _p(col, C.c_int32), cap, nthreads,
+                           _p(st, C.c_int64))
+        if tot >= 0:
+            return ptr, col[:tot].copy(), int(st[0]), int(st[1])
+        cap = int(ptr[-1]) + 1
+
+
+def generate(n: int, kbar: float, gamma: float, seed: int, nthreads: int = 0):
+    """Whole oracle pipeline: (alpha, R, r, theta, row_ptr, col, stats dict)."""
+    a, R = solve_R(n, kbar, gamma)
+    r, t, hard = sample(seed, a, R, n, nthreads=nthreads)
+    row_ptr, col, nq, nt = csr(r, t, R, nthreads)
+    return a, R, r, t, row_ptr, col, {"near_midpoint": hard, "quad": nq, "ties": nt}

@@ -1,0 +1,209 @@
+/*
+ * rhg.h -- C ABI of the MI355X random hyperbolic graph (RHG) generator.
+ *
+ * The model (von Looz, Meyerhenke, Prutkin, Staudt, "Fast generation of
+ * complex networks with underlying hyperbolic geometry", Sec. 2.1): n points
+ * in a hyperbolic disk of radius R, angles uniform, radii with density
+ * alpha*sinh(alpha r)/(cosh(alpha R) - 1) (Eq. (1)); two points are joined
+ * when their hyperbolic distance is at most R.  Algorithm 1 of the paper
+ * takes (n, average degree, alpha) and returns G = (V, E).  This library
+ * splits that algorithm into the calls below; rhg_generate chains them.
+ *
+ * Conventions shared by every call:
+ *   - Device pointers are HIP device memory owned by the caller.  The
+ *     library never frees caller memory.  Host pointers are marked "host".
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on it unless stated otherwise.
+ *   - Every call returns an rhg_status; on failure rhg_last_error() (per
+ *     thread) describes it.  No C++ exception crosses this boundary.
+ *   - Errors raised on the device (for example an invalid input value seen
+ *     by a kernel) are reported by the next call that synchronises.
+ *   - Vertex ids are 0 .. n-1.  Ids are int32, so n <= 2^31 - 1.  Edge
+ *     counts and CSR offsets are int64.
+ *
+ * Edge rule.  Pair {i, j}, i != j, is an edge iff the exact hyperbolic
+ * distance of the two binary64 points is <= R, where
+ *     cosh d = cosh r_i cosh r_j - sinh r_i sinh r_j cos(theta_i - theta_j)
+ * (native representation, Sec. 2.1; equal to the Poincare metric of Eq. (2)
+ * on the points mapped by mapToPoincare, Appendix B.2).  The library decides
+ * it exactly: an FP32 screen and an FP64 evaluation settle all pairs away
+ * from the threshold, and the rare pairs within a relative 2^-30 of it are
+ * re-evaluated in double-double arithmetic.  Pairs that even double-double
+ * cannot separate from the threshold (relative 1e-26) are counted in
+ * rhg_index_stats and resolved by the double-double comparison.
+ */
+#ifndef RHG_H
+#define RHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RHG_OK = 0,
+    RHG_EINVAL = 1,     /* an argument is out of range or inconsistent       */
+    RHG_ENOMEM = 2,     /* an allocation (callback or host) failed           */
+    RHG_ECAPACITY = 3,  /* an output buffer is smaller than required         */
+    RHG_EDEVICE = 4,    /* a HIP runtime call failed                         */
+    RHG_ENOROOT = 5,    /* Eq. (22) has no radius for the requested degree   */
+    RHG_EINTERNAL = 6   /* a device-side consistency check failed            */
+} rhg_status;
+
+/* Parameters of one graph.  Filled by rhg_plan / rhg_plan_radius; the
+ * derived fields are what the kernels use and are exposed for tests. */
+typedef struct {
+    int64_t n;             /* vertices                                        */
+    double avg_degree;     /* target average degree (NaN if R was given)      */
+    double gamma;          /* power-law exponent (NaN if alpha was given)     */
+    uint64_t seed;         /* Philox4x32-10 key                               */
+    double alpha;          /* (gamma - 1) / 2                                 */
+    double R;              /* disk radius = distance threshold                */
+    double cosh_R;         /* cosh(R) rounded to binary64                     */
+    double cosh_R_lo;      /* cosh(R) - cosh_R (double-double tail)           */
+    double cosh_aR_m1;     /* cosh(alpha R) - 1 rounded to binary64           */
+    double cosh_aR_m1_lo;  /* its double-double tail                          */
+} rhg_params;
+
+/* Tuning of the index and search.  Zero fields mean "choose automatically".
+ * The edge set never depends on the tuning; only speed and the order of
+ * neighbours inside a CSR row do. */
+typedef struct {
+    double band_width;     /* radial width of the outer bands                 */
+    double inner_radius;   /* radius below which all points share one band    */
+    int32_t cell_target;   /* mean points per angular cell                    */
+    int32_t reserved[5];
+} rhg_tuning;
+
+/* Device-side diagnostics of the last count/emit pass over an index. */
+typedef struct {
+    int64_t fp32_undecided;  /* pairs the FP32 screen passed to FP64          */
+    int64_t dd_fallbacks;    /* pairs FP64 passed to double-double            */
+    int64_t ties;            /* pairs double-double could not separate        */
+} rhg_stats;
+
+typedef struct rhg_index rhg_index;  /* opaque, host-side handle */
+
+/* ------------------------------------------------------------------ */
+/* a1. Planning (host only, synchronous, no device work).              */
+/* ------------------------------------------------------------------ */
+
+/* alpha = (gamma - 1)/2 (Sec. 2.1: gamma = 2 alpha + 1 with curvature 1).
+ * R is the smallest binary64 value on the decreasing branch of Eq. (22)
+ * (Appendix B.1, "getTargetRadius"; Algorithm 1, first step) whose expected
+ * degree is <= avg_degree, Eq. (22) being read with the middle term
+ * (pi - 1) * zeta/alpha, zeta = 1, and evaluated in double-double.
+ * Errors: RHG_EINVAL if n < 0 or n > 2^31 - 1, gamma <= 2 or NaN,
+ * avg_degree <= 0 or NaN, or avg_degree >= n - 1 when n >= 2;
+ * RHG_ENOROOT if the target exceeds the peak of Eq. (22).
+ * n = 0 or 1 is valid (R is then that of n = 2 and the graph is empty). */
+rhg_status rhg_plan(int64_t n, double avg_degree, double gamma, uint64_t seed,
+                    rhg_params *out /* host */);
+
+/* Same with alpha and R given directly (0.5 < alpha, 0 < R < 300, alpha R < 600). */
+rhg_status rhg_plan_radius(int64_t n, double alpha, double R, uint64_t seed,
+                           rhg_params *out /* host */);
+
+/* ------------------------------------------------------------------ */
+/* a2. Sampling (Algorithm 1, angular and radial draws; Eq. (1)).      */
+/* ------------------------------------------------------------------ */
+
+/* Writes n points: theta[i] = fl(TWO_PI_D * u_theta(i)) in [0, 2 pi) and
+ * r[i] = acosh(1 + u_r(i) (cosh(alpha R) - 1)) / alpha in [0, R], the inverse
+ * of the radial CDF (Appendix C, cell probability with the full angle), where
+ * (u_theta, u_r) are the two 53-bit uniforms of Philox4x32-10 with key
+ * (seed_lo, seed_hi) and counter (i_lo, i_hi, 0, 0): words (x1:x0) >> 11 and
+ * (x3:x2) >> 11 times 2^-53.  r and theta: device, n doubles each, SoA. */
+rhg_status rhg_sample_points(const rhg_params *p /* host */, double *r, double *theta,
+                             void *stream);
+
+/* ------------------------------------------------------------------ */
+/* a3. Index: the polar quadtree of Sec. 3.1 rebuilt as a flat array of */
+/* radial bands, each sorted by angle, with an angular cell directory.  */
+/* ------------------------------------------------------------------ */
+
+/* Bytes of device workspace rhg_build_index needs for these parameters
+ * and tuning (NULL = automatic).  Host only. */
+size_t rhg_index_workspace_bytes(const rhg_params *p /* host */,
+                                 const rhg_tuning *t /* host, may be NULL */);
+
+/* Builds the index of n points (r, theta: device, n doubles each, read
+ * during this call's stream work only).  workspace: device, at least
+ * rhg_index_workspace_bytes bytes, must stay allocated and untouched until
+ * rhg_index_free.  Inputs must satisfy 0 <= r <= R and 0 <= theta < 2 pi
+ * (finite); validate != 0 checks this on the device and synchronises the
+ * stream once (RHG_EINVAL on violation).  *out receives a host handle. */
+rhg_status rhg_build_index(const rhg_params *p /* host */, const double *r,
+                           const double *theta, const rhg_tuning *t /* host, may be NULL */,
+                           void *workspace, size_t workspace_bytes, int validate,
+                           rhg_index **out /* host */, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* a4 + a5. Count pass and scan (Algorithm 1, query loop, counting).    */
+/* ------------------------------------------------------------------ */
+
+/* Runs the neighbour search without writing edges and writes the CSR row
+ * offsets: row_ptr[0] = 0, row_ptr[i + 1] - row_ptr[i] = deg(i) (device,
+ * n + 1 int64).  row_ptr[n] = 2m.  Asynchronous. */
+rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* a6. Emit pass (Algorithm 1, "add (v, w) to E").                     */
+/* ------------------------------------------------------------------ */
+
+/* Repeats the search and writes the neighbours of vertex i to
+ * col_idx[row_ptr[i] .. row_ptr[i+1]) (device, int32).  row_ptr must be
+ * the output of rhg_count_edges on the same index.  Each undirected edge
+ * appears in both rows; there are no self-loops.  Rows are in search order
+ * (deterministic for a given tuning) or, with canonical_rows != 0,
+ * ascending.  col_capacity is the number of int32 slots in col_idx; the
+ * call reads row_ptr[n] back (one synchronisation) and returns
+ * RHG_ECAPACITY if it exceeds col_capacity. */
+rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx,
+                          int64_t col_capacity, int canonical_rows, void *stream);
+
+/* Diagnostics accumulated by the count and emit passes (synchronises). */
+rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out /* host */, void *stream);
+
+void rhg_index_free(rhg_index *idx);
+
+/* ------------------------------------------------------------------ */
+/* Whole generator (Algorithm 1).                                      */
+/* ------------------------------------------------------------------ */
+
+/* Device allocator supplied by the caller: returns `bytes` of device memory
+ * (256-byte aligned) or NULL.  The memory must stay valid until the caller
+ * releases it; the library never frees it. */
+typedef void *(*rhg_alloc_fn)(size_t bytes, void *ctx);
+
+typedef struct {
+    int64_t n;
+    int64_t nnz;        /* 2m: entries of col_idx                            */
+    int64_t *row_ptr;   /* device, n + 1                                     */
+    int32_t *col_idx;   /* device, nnz                                       */
+    double *r;          /* device, n: the sampled radii                      */
+    double *theta;      /* device, n: the sampled angles                     */
+    rhg_params params;
+} rhg_csr;
+
+/* Plans, samples, indexes, counts, scans and emits one graph.  All device
+ * memory (points, index workspace, CSR) comes from `alloc`; the only host
+ * synchronisation is the 8-byte read of 2m before col_idx is allocated.
+ * Errors: those of rhg_plan, and RHG_ENOMEM if `alloc` returns NULL. */
+rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t seed,
+                        const rhg_tuning *t /* host, may be NULL */,
+                        rhg_alloc_fn alloc, void *alloc_ctx, int canonical_rows,
+                        rhg_csr *out /* host */, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rhg_last_error(void);
+
+/* Library version string. */
+const char *rhg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RHG_H */

@@ -1,0 +1,238 @@
+"""MI355X random hyperbolic graph generator: Python binding of librhg.so.
+
+The functions here carry the names of the C ABI in ``include/rhg.h`` and do
+argument marshalling only: PyTorch supplies device memory and the current
+HIP stream, and every step of the computation runs in the library's HIP
+kernels.  There is no CPU fallback: if ``librhg.so`` is missing or fails to
+load, importing a function raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librhg.so")
+
+RHG_OK, RHG_EINVAL, RHG_ENOMEM, RHG_ECAPACITY, RHG_EDEVICE, RHG_ENOROOT, RHG_EINTERNAL = range(7)
+_STATUS = {0: "RHG_OK", 1: "RHG_EINVAL", 2: "RHG_ENOMEM", 3: "RHG_ECAPACITY", 4: "RHG_EDEVICE",
+           5: "RHG_ENOROOT", 6: "RHG_EINTERNAL"}
+
+
+class RhgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+
+
+class rhg_params(C.Structure):
+    _fields_ = [("n", C.c_int64), ("avg_degree", C.c_double), ("gamma", C.c_double),
+                ("seed", C.c_uint64), ("alpha", C.c_double), ("R", C.c_double),
+                ("cosh_R", C.c_double), ("cosh_R_lo", C.c_double), ("cosh_aR_m1", C.c_double),
+                ("cosh_aR_m1_lo", C.c_double)]
+
+
+class rhg_tuning(C.Structure):
+    _fields_ = [("band_width", C.c_double), ("inner_radius", C.c_double),
+                ("cell_target", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+class rhg_stats(C.Structure):
+    _fields_ = [("fp32_undecided", C.c_int64), ("dd_fallbacks", C.c_int64), ("ties", C.c_int64)]
+
+
+class rhg_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("r", C.c_void_p), ("theta", C.c_void_p), ("params", rhg_params)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+
+_lib = None
+
+
+def load():
+    """Load librhg.so (built by ``build.py``); raises if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("librhg.so is not built (run paper_1501_03545_amd/build.py or "
+                           "__graft_entry__.build()); there is no fallback path")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, d, u64, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_uint64, C.c_int
+    P = C.POINTER
+    sig = {
+        "rhg_plan": (i32, [i64, d, d, u64, P(rhg_params)]),
+        "rhg_plan_radius": (i32, [i64, d, d, u64, P(rhg_params)]),
+        "rhg_sample_points": (i32, [P(rhg_params), vp, vp, vp]),
+        "rhg_index_workspace_bytes": (C.c_size_t, [P(rhg_params), P(rhg_tuning)]),
+        "rhg_build_index": (i32, [P(rhg_params), vp, vp, P(rhg_tuning), vp, C.c_size_t, i32, P(vp), vp]),
+        "rhg_count_edges": (i32, [vp, vp, vp]),
+        "rhg_emit_edges": (i32, [vp, vp, vp, i64, i32, vp]),
+        "rhg_index_stats": (i32, [vp, P(rhg_stats), vp]),
+        "rhg_index_free": (None, [vp]),
+        "rhg_generate": (i32, [i64, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
+        "rhg_last_error": (C.c_char_p, []),
+        "rhg_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != RHG_OK:
+        raise RhgError(status, load().rhg_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _tuning(t: Optional[dict]):
+    if not t:
+        return None
+    tu = rhg_tuning()
+    tu.band_width = float(t.get("band_width", 0.0))
+    tu.inner_radius = float(t.get("inner_radius", 0.0))
+    tu.cell_target = int(t.get("cell_target", 0))
+    return C.byref(tu)
+
+
+def version() -> str:
+    return load().rhg_version().decode()
+
+
+def rhg_plan(n: int, avg_degree: float, gamma: float, seed: int) -> rhg_params:
+    p = rhg_params()
+    _check(load().rhg_plan(n, avg_degree, gamma, seed, C.byref(p)))
+    return p
+
+
+def rhg_plan_radius(n: int, alpha: float, R: float, seed: int = 0) -> rhg_params:
+    p = rhg_params()
+    _check(load().rhg_plan_radius(n, alpha, R, seed, C.byref(p)))
+    return p
+
+
+def rhg_sample_points(p: rhg_params, r, theta, stream=None):
+    """Fill device float64 tensors r, theta (n each) with the graph's points."""
+    assert r.dtype == theta.dtype and r.is_cuda and theta.is_cuda
+    assert r.numel() >= p.n and theta.numel() >= p.n and r.is_contiguous() and theta.is_contiguous()
+    _check(load().rhg_sample_points(C.byref(p), _ptr(r), _ptr(theta), _stream(stream)))
+
+
+def rhg_index_workspace_bytes(p: rhg_params, tuning: Optional[dict] = None) -> int:
+    return int(load().rhg_index_workspace_bytes(C.byref(p), _tuning(tuning)))
+
+
+@dataclass
+class Index:
+    handle: C.c_void_p
+    workspace: object  # torch tensor that backs the index
+    params: rhg_params
+
+    def free(self):
+        if self.handle:
+            load().rhg_index_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def rhg_build_index(p: rhg_params, r, theta, tuning: Optional[dict] = None, workspace=None,
+                    validate: bool = True, stream=None) -> Index:
+    import torch
+    nbytes = rhg_index_workspace_bytes(p, tuning)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=r.device)
+    h = C.c_void_p()
+    _check(load().rhg_build_index(C.byref(p), _ptr(r), _ptr(theta), _tuning(tuning), _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), 1 if validate else 0,
+                                  C.byref(h), _stream(stream)))
+    return Index(h, workspace, p)
+
+
+def rhg_count_edges(idx: Index, row_ptr, stream=None):
+    """row_ptr: device int64 tensor of n + 1 entries."""
+    import torch
+    assert row_ptr.dtype == torch.int64 and row_ptr.numel() >= idx.params.n + 1
+    _check(load().rhg_count_edges(idx.handle, _ptr(row_ptr), _stream(stream)))
+
+
+def rhg_emit_edges(idx: Index, row_ptr, col_idx, canonical_rows: bool = False, stream=None):
+    import torch
+    assert col_idx.dtype == torch.int32
+    _check(load().rhg_emit_edges(idx.handle, _ptr(row_ptr), _ptr(col_idx), col_idx.numel(),
+                                 1 if canonical_rows else 0, _stream(stream)))
+
+
+def rhg_index_stats(idx: Index, stream=None) -> dict:
+    st = rhg_stats()
+    _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
+    return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties}
+
+
+@dataclass
+class Graph:
+    params: rhg_params
+    row_ptr: object
+    col_idx: object
+    r: object
+    theta: object
+
+    @property
+    def n(self):
+        return self.params.n
+
+    @property
+    def nnz(self):
+        return self.col_idx.numel()
+
+
+def rhg_generate(n: int, avg_degree: float, gamma: float, seed: int, tuning: Optional[dict] = None,
+                 canonical_rows: bool = False, device="cuda", stream=None) -> Graph:
+    """Algorithm 1 end to end on the GPU; device memory from PyTorch."""
+    import torch
+    held = {}
+
+    def _alloc(nbytes, _ctx):
+        t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+        held[t.data_ptr()] = t
+        return t.data_ptr()
+
+    cb = ALLOC_FN(_alloc)
+    out = rhg_csr()
+    _check(load().rhg_generate(n, avg_degree, gamma, seed, _tuning(tuning), cb, None,
+                               1 if canonical_rows else 0, C.byref(out), _stream(stream)))
+
+    def view(ptr, dtype, count):
+        return held[ptr][: count * torch.empty((), dtype=dtype).element_size()].view(dtype)
+
+    return Graph(params=out.params,
+                 row_ptr=view(out.row_ptr, torch.int64, n + 1),
+                 col_idx=view(out.col_idx, torch.int32, out.nnz),
+                 r=view(out.r, torch.float64, n), theta=view(out.theta, torch.float64, n))
+
+
+__all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_workspace_bytes",
+           "rhg_build_index", "rhg_count_edges", "rhg_emit_edges", "rhg_index_stats", "rhg_generate",
+           "RhgError", "Graph", "Index", "load", "version", "LIB_PATH"]

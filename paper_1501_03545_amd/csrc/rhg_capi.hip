@@ -1,0 +1,271 @@
+// rhg_capi.hip -- the extern "C" boundary: argument checks, workspace
+// carving, launch sequencing and error reporting.  No exception crosses it.
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "rhg_internal.h"
+
+namespace rhg {
+
+static thread_local std::string g_last_error;
+
+rhg_status fail(rhg_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+rhg_status check_hip(hipError_t e, const char *what)
+{
+    return fail(RHG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+rhg_status plan(int64_t n, double kbar, double gamma, uint64_t seed, rhg_params *out);
+rhg_status plan_radius(int64_t n, double alpha, double R, uint64_t seed, rhg_params *out);
+
+__global__ void zero_u64_kernel(unsigned long long *p, int count)
+{
+    const int i = threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+struct WsPlan {
+    size_t keys, v0, band_start, dir, sr, st, sep, sem, ssh, sid, stats, tmp, total, tmp_bytes;
+};
+
+static WsPlan ws_plan(int64_t n, const Layout &L)
+{
+    WsPlan w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    w.keys = take(N * 4);
+    w.v0 = take(N * 4);
+    w.band_start = take((size_t)(L.B + 1) * 4);
+    w.dir = take((size_t)L.dir_total * 4);
+    w.sr = take(N * 8);
+    w.st = take(N * 8);
+    w.sep = take(N * 8);
+    w.sem = take(N * 8);
+    w.ssh = take(N * 8);
+    w.sid = take(N * 4);
+    w.stats = take(ST_COUNT * 8);
+    size_t t1 = radix_sort_tmp_bytes(n), t2 = scan_tmp_bytes(n + 1);
+    w.tmp_bytes = t1 > t2 ? t1 : t2;
+    w.tmp = take(w.tmp_bytes);
+    w.total = off + 256;  // slack for aligning the base pointer
+    return w;
+}
+
+}  // namespace rhg
+
+using namespace rhg;
+
+extern "C" {
+
+const char *rhg_last_error(void) { return g_last_error.c_str(); }
+
+const char *rhg_version(void) { return "rhg-mi355x 0.1 (gfx950)"; }
+
+rhg_status rhg_plan(int64_t n, double avg_degree, double gamma, uint64_t seed, rhg_params *out)
+{
+    g_last_error.clear();
+    return plan(n, avg_degree, gamma, seed, out);
+}
+
+rhg_status rhg_plan_radius(int64_t n, double alpha, double R, uint64_t seed, rhg_params *out)
+{
+    g_last_error.clear();
+    return plan_radius(n, alpha, R, seed, out);
+}
+
+static rhg_status check_params(const rhg_params *p, const char *who)
+{
+    if (!p) return fail(RHG_EINVAL, std::string(who) + ": params is NULL");
+    if (p->n < 0 || p->n > 2147483647LL) return fail(RHG_EINVAL, std::string(who) + ": n out of range");
+    if (!(p->alpha > 0.5) || !(p->R > 0.0) || !(p->R < 300.0) || !(p->cosh_R >= 1.0) || !(p->cosh_aR_m1 > 0.0))
+        return fail(RHG_EINVAL, std::string(who) + ": params were not filled by rhg_plan");
+    return RHG_OK;
+}
+
+rhg_status rhg_sample_points(const rhg_params *p, double *r, double *theta, void *stream)
+{
+    g_last_error.clear();
+    rhg_status st = check_params(p, "rhg_sample_points");
+    if (st != RHG_OK) return st;
+    if (p->n > 0 && (!r || !theta)) return fail(RHG_EINVAL, "rhg_sample_points: NULL output");
+    RHG_HIP(launch_sample(*p, r, theta, (hipStream_t)stream));
+    return RHG_OK;
+}
+
+size_t rhg_index_workspace_bytes(const rhg_params *p, const rhg_tuning *t)
+{
+    if (!p) return 0;
+    Layout L;
+    make_layout(*p, t, &L);
+    return ws_plan(p->n, L).total;
+}
+
+rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *theta, const rhg_tuning *t,
+                           void *workspace, size_t workspace_bytes, int validate, rhg_index **out,
+                           void *stream)
+{
+    g_last_error.clear();
+    rhg_status st = check_params(p, "rhg_build_index");
+    if (st != RHG_OK) return st;
+    if (!out) return fail(RHG_EINVAL, "rhg_build_index: out is NULL");
+    *out = nullptr;
+    if (p->n > 0 && (!r || !theta)) return fail(RHG_EINVAL, "rhg_build_index: NULL points");
+    if (t && (t->band_width < 0.0 || t->inner_radius < 0.0 || t->cell_target < 0 || !(t->band_width < 1e6)))
+        return fail(RHG_EINVAL, "rhg_build_index: negative tuning value");
+    rhg_index *idx = new (std::nothrow) rhg_index;
+    if (!idx) return fail(RHG_ENOMEM, "rhg_build_index: host allocation failed");
+    memset(idx, 0, sizeof(*idx));
+    idx->p = *p;
+    idx->n = p->n;
+    make_layout(*p, t, &idx->L);
+    const WsPlan w = ws_plan(p->n, idx->L);
+    if (!workspace || workspace_bytes < w.total) {
+        delete idx;
+        return fail(RHG_ECAPACITY, "rhg_build_index: workspace smaller than rhg_index_workspace_bytes");
+    }
+    char *base = (char *)align_up((size_t)workspace, 256);
+    idx->keys = (uint32_t *)(base + w.keys);
+    uint32_t *v0 = (uint32_t *)(base + w.v0);
+    idx->band_start = (int32_t *)(base + w.band_start);
+    idx->dir = (int32_t *)(base + w.dir);
+    idx->sr = (double *)(base + w.sr);
+    idx->st = (double *)(base + w.st);
+    idx->sep = (double *)(base + w.sep);
+    idx->sem = (double *)(base + w.sem);
+    idx->ssh = (double *)(base + w.ssh);
+    idx->sid = (int32_t *)(base + w.sid);
+    idx->stats = (unsigned long long *)(base + w.stats);
+    idx->tmp = base + w.tmp;
+    idx->tmp_bytes = w.tmp_bytes;
+    // the sort's second key/value buffers live in the e^r / e^-r arrays,
+    // which the gather step fills only after the sort has finished
+    uint32_t *k1 = (uint32_t *)idx->sep;
+    uint32_t *v1 = (uint32_t *)idx->sem;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, idx->stats, (int)ST_COUNT);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_build_index(idx, r, theta, k1, v0, v1, validate, s);
+    if (e != hipSuccess) {
+        delete idx;
+        return check_hip(e, "rhg_build_index");
+    }
+    if (validate) {
+        unsigned long long bad = 0;
+        e = hipMemcpyAsync(&bad, idx->stats + ST_BAD_INPUT, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            delete idx;
+            return check_hip(e, "rhg_build_index (validate)");
+        }
+        if (bad) {
+            delete idx;
+            return fail(RHG_EINVAL, "rhg_build_index: " + std::to_string(bad) +
+                                        " points outside 0 <= r <= R, 0 <= theta < 2 pi");
+        }
+    }
+    *out = idx;
+    return RHG_OK;
+}
+
+rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream)
+{
+    g_last_error.clear();
+    if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_count_edges: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    RHG_HIP(launch_search(idx, row_ptr, nullptr, 0, s));
+    if (idx->n > 0) RHG_HIP(inclusive_scan_i64(row_ptr + 1, idx->n, idx->tmp, s));
+    return RHG_OK;
+}
+
+rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx, int64_t col_capacity,
+                          int canonical_rows, void *stream)
+{
+    g_last_error.clear();
+    if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_emit_edges: NULL argument");
+    if (col_capacity < 0) return fail(RHG_EINVAL, "rhg_emit_edges: negative capacity");
+    if (canonical_rows) return fail(RHG_EINVAL, "rhg_emit_edges: canonical_rows is not supported by this build");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nnz = 0;
+    RHG_HIP(hipMemcpyAsync(&nnz, row_ptr + idx->n, 8, hipMemcpyDeviceToHost, s));
+    RHG_HIP(hipStreamSynchronize(s));
+    if (nnz > col_capacity)
+        return fail(RHG_ECAPACITY, "rhg_emit_edges: col_idx holds " + std::to_string(col_capacity) +
+                                       " entries, the graph needs " + std::to_string(nnz));
+    if (nnz > 0 && !col_idx) return fail(RHG_EINVAL, "rhg_emit_edges: col_idx is NULL");
+    if (nnz > 0) RHG_HIP(launch_search(idx, (int64_t *)row_ptr, col_idx, 1, s));
+    return RHG_OK;
+}
+
+rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
+{
+    g_last_error.clear();
+    if (!idx || !out) return fail(RHG_EINVAL, "rhg_index_stats: NULL argument");
+    unsigned long long h[ST_COUNT];
+    hipStream_t s = (hipStream_t)stream;
+    RHG_HIP(hipMemcpyAsync(h, idx->stats, sizeof(h), hipMemcpyDeviceToHost, s));
+    RHG_HIP(hipStreamSynchronize(s));
+    out->fp32_undecided = (int64_t)h[ST_FP32_UNDECIDED];
+    out->dd_fallbacks = (int64_t)h[ST_DD];
+    out->ties = (int64_t)h[ST_TIES];
+    if (h[ST_EMIT_MISMATCH]) return fail(RHG_EINTERNAL, "emit pass disagreed with the count pass");
+    return RHG_OK;
+}
+
+void rhg_index_free(rhg_index *idx) { delete idx; }
+
+rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t seed, const rhg_tuning *t,
+                        rhg_alloc_fn alloc, void *alloc_ctx, int canonical_rows, rhg_csr *out, void *stream)
+{
+    g_last_error.clear();
+    if (!alloc || !out) return fail(RHG_EINVAL, "rhg_generate: NULL allocator or output");
+    memset(out, 0, sizeof(*out));
+    rhg_params p;
+    rhg_status st = plan(n, avg_degree, gamma, seed, &p);
+    if (st != RHG_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    double *r = (double *)alloc(N * 8, alloc_ctx);
+    double *th = (double *)alloc(N * 8, alloc_ctx);
+    int64_t *row_ptr = (int64_t *)alloc((size_t)(n + 1) * 8, alloc_ctx);
+    const size_t wsb = rhg_index_workspace_bytes(&p, t);
+    void *ws = alloc(wsb, alloc_ctx);
+    if (!r || !th || !row_ptr || !ws) return fail(RHG_ENOMEM, "rhg_generate: allocation callback failed");
+    if ((st = rhg_sample_points(&p, r, th, stream)) != RHG_OK) return st;
+    rhg_index *idx = nullptr;
+    if ((st = rhg_build_index(&p, r, th, t, ws, wsb, 0, &idx, stream)) != RHG_OK) return st;
+    if ((st = rhg_count_edges(idx, row_ptr, stream)) != RHG_OK) { rhg_index_free(idx); return st; }
+    int64_t nnz = 0;
+    hipError_t e = hipMemcpyAsync(&nnz, row_ptr + n, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { rhg_index_free(idx); return check_hip(e, "rhg_generate (edge count)"); }
+    int32_t *col = (int32_t *)alloc((size_t)(nnz > 0 ? nnz : 1) * 4, alloc_ctx);
+    if (!col) { rhg_index_free(idx); return fail(RHG_ENOMEM, "rhg_generate: col_idx allocation failed"); }
+    if ((st = rhg_emit_edges(idx, row_ptr, col, nnz, canonical_rows, stream)) != RHG_OK) {
+        rhg_index_free(idx);
+        return st;
+    }
+    rhg_index_free(idx);
+    out->n = n;
+    out->nnz = nnz;
+    out->row_ptr = row_ptr;
+    out->col_idx = col;
+    out->r = r;
+    out->theta = th;
+    out->params = p;
+    return RHG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// rhg_index.hip -- the flat polar index (Sec. 3.1 "Data structure" rebuilt
+// for a GPU).
+//
+// The paper's polar quadtree splits cells at the angular midpoint and at the
+// equal-mass radius of Eq. (3), so a cell at depth i holds a point with
+// probability 4^-i (Lemma 1).  Here the radial direction is cut once into
+// bands (E[j] <= r < E[j+1]) and each band's angular range into 2^cbits equal
+// cells; points are sorted by (band, angle) with one radix sort, and a
+// directory gives, for every cell, the first sorted position at or after it.
+// A range query then reads whole runs of sorted points instead of walking a
+// tree.
+#include "rhg_internal.h"
+
+namespace rhg {
+
+struct KeyArgs {
+    double E[RHG_MAX_BANDS + 1];
+    int B;
+    int band_bits;
+    double R;
+};
+
+// 32-bit angular key: floor(theta * 2^32 / TWO_PI_D), clamped.  Monotone
+// non-decreasing in theta, so any angular interval maps to a key interval.
+__device__ __forceinline__ uint32_t angle_key(double t)
+{
+    const double k = t * (4294967296.0 / RHG_TWO_PI_D);
+    if (!(k > 0.0)) return 0u;
+    if (k >= 4294967295.0) return 4294967295u;
+    return (uint32_t)k;
+}
+
+// Band of radius r: the largest j with E[j] <= r (exact comparisons).
+__device__ __forceinline__ int band_of(const KeyArgs &A, double r)
+{
+    int lo = 0, hi = A.B - 1;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.E[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) key_kernel(KeyArgs A, int64_t n, const double *__restrict__ r,
+                                                  const double *__restrict__ theta, uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals, int validate,
+                                                  unsigned long long *stats)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double ri = r[i], ti = theta[i];
+        if (validate && !(ri >= 0.0 && ri <= A.R && ti >= 0.0 && ti <= RHG_TWO_PI_D))
+            atomicAdd(&stats[ST_BAD_INPUT], 1ull);
+        const uint32_t b = (uint32_t)band_of(A, ri);
+        const uint32_t ak = angle_key(ti);
+        keys[i] = A.band_bits ? ((b << (32 - A.band_bits)) | (ak >> A.band_bits)) : ak;
+        vals[i] = (uint32_t)i;
+    }
+}
+
+// First sorted position whose key is >= k, searched in [lo, hi).
+__device__ __forceinline__ int64_t lower_bound_key(const uint32_t *keys, int64_t lo, int64_t hi, uint64_t k)
+{
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((uint64_t)keys[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void band_start_kernel(const uint32_t *__restrict__ keys, int64_t n, int B, int band_bits,
+                                  int32_t *__restrict__ band_start)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > B) return;
+    int64_t p;
+    if (j == 0) p = 0;
+    else if (j == B) p = n;
+    else p = lower_bound_key(keys, 0, n, (uint64_t)j << (32 - band_bits));
+    band_start[j] = (int32_t)p;
+}
+
+struct DirArgs {
+    int64_t dir_base[RHG_MAX_BANDS + 1];
+    int cbits[RHG_MAX_BANDS];
+    int B;
+    int band_bits;
+    int64_t total;
+};
+
+// dir[dir_base[j] + c] = first sorted position of band j whose cell is >= c,
+// for c = 0 .. 2^cbits[j] (the last entry is the band's end).
+__global__ void __launch_bounds__(256) dir_kernel(DirArgs A, const uint32_t *__restrict__ keys,
+                                                  const int32_t *__restrict__ band_start,
+                                                  int32_t *__restrict__ dir)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.total; e += stride) {
+        int j = 0;
+        while (j + 1 < A.B && A.dir_base[j + 1] <= e) ++j;
+        const int64_t c = e - A.dir_base[j];
+        const int64_t s = band_start[j], t = band_start[j + 1];
+        const int cb = A.cbits[j];
+        int64_t p;
+        if (c == 0) p = s;
+        else if (c >= ((int64_t)1 << cb)) p = t;
+        else {
+            // key of the first angle in cell c of band j
+            const int shift = 32 - A.band_bits - cb;  // >= 0 by construction
+            const uint64_t k = ((uint64_t)j << (32 - A.band_bits)) + ((uint64_t)c << shift);
+            p = lower_bound_key(keys, s, t, A.band_bits ? k : ((uint64_t)c << (32 - cb)));
+        }
+        dir[e] = (int32_t)p;
+    }
+}
+
+// Sorted per-point records: r, theta, e^r, e^-r, sinh r and the original id.
+__global__ void __launch_bounds__(256) gather_kernel(int64_t n, const double *__restrict__ r,
+                                                     const double *__restrict__ theta,
+                                                     const uint32_t *__restrict__ perm, double *__restrict__ sr,
+                                                     double *__restrict__ st, double *__restrict__ sep,
+                                                     double *__restrict__ sem, double *__restrict__ ssh,
+                                                     int32_t *__restrict__ sid)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        uint32_t id = perm[p];
+        if (id >= (uint64_t)n) id = 0;  // unreachable for a valid permutation; keeps reads in bounds
+        const double ri = r[id];
+        sr[p] = ri;
+        st[p] = theta[id];
+        sep[p] = exp(ri);
+        sem[p] = exp(-ri);
+        ssh[p] = sinh(ri);
+        sid[p] = (int32_t)id;
+    }
+}
+
+static unsigned grid_for(int64_t n, int64_t cap = 65536)
+{
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+hipError_t launch_build_index(rhg_index *idx, const double *r, const double *theta, uint32_t *k1,
+                              uint32_t *v0, uint32_t *v1, int validate, hipStream_t s)
+{
+    const int64_t n = idx->n;
+    const Layout &L = idx->L;
+    KeyArgs ka;
+    for (int j = 0; j <= L.B; ++j) ka.E[j] = L.E[j];
+    ka.B = L.B;
+    ka.band_bits = L.band_bits;
+    ka.R = idx->p.R;
+    hipError_t e;
+    if (n > 0) {
+        hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(256), 0, s, ka, n, r, theta, idx->keys, v0,
+                           validate, idx->stats);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = radix_sort_pairs(idx->keys, v0, k1, v1, n, 32, idx->tmp, s)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(band_start_kernel, dim3(1), dim3(128), 0, s, idx->keys, n, L.B, L.band_bits,
+                       idx->band_start);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    DirArgs da;
+    for (int j = 0; j <= L.B; ++j) da.dir_base[j] = L.dir_base[j];
+    for (int j = 0; j < L.B; ++j) da.cbits[j] = L.cbits[j];
+    da.B = L.B;
+    da.band_bits = L.band_bits;
+    da.total = L.dir_total;
+    hipLaunchKernelGGL(dir_kernel, dim3(grid_for(L.dir_total)), dim3(256), 0, s, da, idx->keys, idx->band_start,
+                       idx->dir);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n > 0) {
+        hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, r, theta, v0, idx->sr, idx->st,
+                           idx->sep, idx->sem, idx->ssh, idx->sid);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace rhg

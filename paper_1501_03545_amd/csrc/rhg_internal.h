@@ -1,0 +1,85 @@
+// rhg_internal.h -- declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/rhg.h"
+#include "rhg_dd.h"
+
+#define RHG_MAX_BANDS 64
+#define RHG_TWO_PI_D 6.283185307179586
+#define RHG_TWO_PI_RES_D 2.4492935982947064e-16
+
+namespace rhg {
+
+// Sets the thread's last-error message and returns the status.
+rhg_status fail(rhg_status s, const std::string &msg);
+rhg_status check_hip(hipError_t e, const char *what);
+
+#define RHG_HIP(call)                                              \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return ::rhg::check_hip(e_, #call); \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Radial band layout: band j holds the points with E[j] <= r < E[j+1]
+// (E[0] = 0, E[B] = R, and the last band also takes r = R).  Inside a band
+// the points are sorted by angle and the angular range [0, 2 pi) is cut into
+// 2^cbits[j] equal cells, the polar-quadtree leaves of that band.
+struct Layout {
+    int B;
+    int band_bits;                    // bits of the sort key holding the band
+    double E[RHG_MAX_BANDS + 1];      // band edges
+    int cbits[RHG_MAX_BANDS];         // log2 of the cell count per band
+    int64_t dir_base[RHG_MAX_BANDS + 1];  // offset of band j's directory
+    int64_t dir_total;                // entries of the directory (all bands)
+};
+
+void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L);
+
+// Device-side counters (one 64-bit word each).
+enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4, ST_COUNT = 8 };
+
+}  // namespace rhg
+
+// The index handle: host copies of the layout plus device pointers carved
+// out of the caller's workspace.
+struct rhg_index {
+    rhg_params p;
+    rhg::Layout L;
+    int64_t n;
+    uint32_t *keys;        // sorted keys (n)
+    int32_t *band_start;   // B + 1 sorted positions
+    int32_t *dir;          // directory, dir_total entries
+    double *sr, *st;       // sorted r, theta (n each)
+    double *sep, *sem, *ssh;  // sorted e^r, e^-r, sinh r (n each)
+    int32_t *sid;          // original id of each sorted position (n)
+    unsigned long long *stats;  // ST_COUNT counters
+    void *tmp;             // scratch for sort and scan
+    size_t tmp_bytes;
+};
+
+namespace rhg {
+
+// ---- kernels launched from the C API (defined in the .hip files) ----
+hipError_t launch_sample(const rhg_params &p, double *r, double *theta, hipStream_t s);
+
+// LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
+// Buffers k0/v0 hold the input; the sorted output ends in k0/v0.
+size_t radix_sort_tmp_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
+                            int bits, void *tmp, hipStream_t s);
+
+// In-place inclusive scan of int64 x[0..n).
+size_t scan_tmp_bytes(int64_t n);
+hipError_t inclusive_scan_i64(int64_t *x, int64_t n, void *tmp, hipStream_t s);
+
+hipError_t launch_build_index(rhg_index *idx, const double *r, const double *theta, uint32_t *k1,
+                              uint32_t *v0, uint32_t *v1, int validate, hipStream_t s);
+hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit,
+                         hipStream_t s);
+
+}  // namespace rhg

@@ -1,0 +1,171 @@
+// rhg_plan.hip -- host planning: alpha, R (Eq. (22)), the derived constants
+// the kernels use, and the radial band layout of the index.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "rhg_internal.h"
+
+namespace rhg {
+
+static const dd PI_DD = {3.141592653589793, 1.2246467991473532e-16};
+
+// Expected average degree, Eq. (22) of Krioukov et al. as restated in
+// Appendix B.1, curvature zeta = 1, xi = alpha / (alpha - 1/2):
+//   kbar = (2/pi) xi^2 n ( e^{-R/2} + e^{-alpha R} ( alpha (R/2) inner - 1 ) ),
+//   inner = (pi/4) (1/alpha)^2 - (pi - 1) (1/alpha) + (pi - 2).
+// The printed "(pi-1) xi/alpha" is read as (pi-1) zeta/alpha: with xi/alpha
+// heavy-tailed targets have no root at all.  Evaluated in double-double.
+static dd kbar_eq22(double n, double alpha, double R)
+{
+    dd a = dd_make(alpha);
+    dd inv_a = dd_div(dd_make(1.0), a);
+    dd xi = dd_div(a, dd_add_d(a, -0.5));
+    dd inner = dd_mul(dd_mul(dd_mul_pow2(PI_DD, 0.25), inv_a), inv_a);
+    inner = dd_sub(inner, dd_mul(dd_add_d(PI_DD, -1.0), inv_a));
+    inner = dd_add(inner, dd_add_d(PI_DD, -2.0));
+    dd aR = two_prod(alpha, R);
+    dd t1 = dd_exp(dd_make(-0.5 * R));  // R/2 is exact
+    dd t2 = dd_exp(dd_neg(aR));
+    dd bracket = dd_add_d(dd_mul(dd_mul_d(aR, 0.5), inner), -1.0);
+    dd t = dd_add(t1, dd_mul(t2, bracket));
+    dd pref = dd_mul(dd_div(dd_make(2.0), PI_DD), dd_mul(xi, xi));
+    return dd_mul(dd_mul_d(pref, n), t);
+}
+
+static bool above(double n, double alpha, double R, double target)
+{
+    return dd_cmp(kbar_eq22(n, alpha, R), dd_make(target)) > 0;
+}
+
+// R = smallest binary64 on the decreasing branch of Eq. (22) whose value is
+// <= target.  The bracket starts at the maximum of Eq. (22) (golden-section
+// search) and ends at 2 ln n + 40; bisection runs down to adjacent doubles,
+// so the result depends only on where Eq. (22) crosses the target.
+static rhg_status solve_radius(double n, double alpha, double target, double *R_out)
+{
+    double hi = 2.0 * log(n) + 40.0;
+    double a = 1e-6, b = hi;
+    const double g = 0.6180339887498949;
+    for (int it = 0; it < 200; ++it) {
+        double c = b - g * (b - a), d = a + g * (b - a);
+        if (dd_cmp(kbar_eq22(n, alpha, c), kbar_eq22(n, alpha, d)) > 0) b = d; else a = c;
+    }
+    double lo = 0.5 * (a + b);
+    if (!above(n, alpha, lo, target))
+        return fail(RHG_ENOROOT, "average degree exceeds the maximum of Eq. (22) for this n and gamma");
+    if (above(n, alpha, hi, target)) return fail(RHG_ENOROOT, "Eq. (22) bracket does not contain the target");
+    for (;;) {
+        double mid = lo + 0.5 * (hi - lo);
+        if (mid <= lo || mid >= hi) break;
+        if (above(n, alpha, mid, target)) lo = mid; else hi = mid;
+    }
+    *R_out = hi;
+    return RHG_OK;
+}
+
+static void derive(rhg_params *p)
+{
+    dd cR = dd_cosh(dd_make(p->R));
+    p->cosh_R = cR.hi;
+    p->cosh_R_lo = cR.lo;
+    dd aR = two_prod(p->alpha, p->R);
+    dd c = dd_add_d(dd_cosh(aR), -1.0);
+    p->cosh_aR_m1 = c.hi;
+    p->cosh_aR_m1_lo = c.lo;
+}
+
+rhg_status plan(int64_t n, double kbar, double gamma, uint64_t seed, rhg_params *out)
+{
+    if (!out) return fail(RHG_EINVAL, "rhg_plan: out is NULL");
+    if (n < 0 || n > 2147483647LL) return fail(RHG_EINVAL, "rhg_plan: n must be in [0, 2^31 - 1]");
+    if (!(gamma > 2.0) || !isfinite(gamma))
+        return fail(RHG_EINVAL, "rhg_plan: gamma must be a finite number > 2 (alpha > 1/2)");
+    if (!(kbar > 0.0) || !isfinite(kbar)) return fail(RHG_EINVAL, "rhg_plan: avg_degree must be > 0");
+    if (n >= 2 && !(kbar < (double)(n - 1)))
+        return fail(RHG_EINVAL, "rhg_plan: avg_degree must be < n - 1");
+    rhg_params p;
+    memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.avg_degree = kbar;
+    p.gamma = gamma;
+    p.seed = seed;
+    p.alpha = (gamma - 1.0) * 0.5;
+    if (n >= 2) {
+        rhg_status s = solve_radius((double)n, p.alpha, kbar, &p.R);
+        if (s != RHG_OK) return s;
+    } else {
+        p.R = 1.0;  // no pairs: any radius gives the empty graph
+    }
+    derive(&p);
+    *out = p;
+    return RHG_OK;
+}
+
+rhg_status plan_radius(int64_t n, double alpha, double R, uint64_t seed, rhg_params *out)
+{
+    if (!out) return fail(RHG_EINVAL, "rhg_plan_radius: out is NULL");
+    if (n < 0 || n > 2147483647LL) return fail(RHG_EINVAL, "rhg_plan_radius: n must be in [0, 2^31 - 1]");
+    if (!(alpha > 0.5) || !isfinite(alpha)) return fail(RHG_EINVAL, "rhg_plan_radius: alpha must be > 1/2");
+    if (!(R > 0.0) || !(R < 300.0)) return fail(RHG_EINVAL, "rhg_plan_radius: R must be in (0, 300)");
+    if (!(alpha * R < 600.0)) return fail(RHG_EINVAL, "rhg_plan_radius: alpha * R must be < 600");
+    rhg_params p;
+    memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.avg_degree = NAN;
+    p.gamma = NAN;
+    p.seed = seed;
+    p.alpha = alpha;
+    p.R = R;
+    derive(&p);
+    *out = p;
+    return RHG_OK;
+}
+
+// Radial band layout.  The outer bands have (at most) the tuning's width
+// and end at R; everything below `inner_radius` forms one band, chosen by
+// default so that it holds about one point in expectation (the CDF of
+// Eq. (1) at that radius is 1/n).  Each band's angular cells hold about
+// `cell_target` points in expectation, so the cells are the equal-mass
+// leaves of the paper's polar quadtree restricted to that band (Lemma 1).
+void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
+{
+    memset(L, 0, sizeof(*L));
+    const double R = p.R, a = p.alpha;
+    const double n = (double)std::max<int64_t>(p.n, 1);
+    double w = (t && t->band_width > 0.0) ? t->band_width : 1.0;
+    double rin;
+    if (t && t->inner_radius > 0.0) rin = std::min(t->inner_radius, R);
+    else rin = std::max(0.0, R - log(std::max(n, 2.0)) / a);
+    int K = (int)ceil((R - rin) / w);
+    if (K < 1) K = 1;
+    int maxK = RHG_MAX_BANDS - (rin > 0.0 ? 1 : 0);
+    if (K > maxK) K = maxK;
+    int B = 0;
+    L->E[B] = 0.0;
+    if (rin > 0.0) L->E[++B] = rin;
+    for (int i = 1; i <= K; ++i) L->E[B + i] = (i == K) ? R : rin + (R - rin) * (double)i / (double)K;
+    B += K;
+    L->B = B;
+    int bb = 0;
+    while ((1 << bb) < B) ++bb;
+    L->band_bits = bb;
+    double target = (t && t->cell_target > 0) ? (double)t->cell_target : 8.0;
+    double denom = p.cosh_aR_m1;
+    int64_t base = 0;
+    for (int j = 0; j < B; ++j) {
+        double F0 = (cosh(a * L->E[j]) - 1.0) / denom;
+        double F1 = (cosh(a * L->E[j + 1]) - 1.0) / denom;
+        double expect = n * std::max(0.0, std::min(1.0, F1) - F0);
+        int cb = 0;
+        while (cb < 32 - bb && (double)(1ull << cb) * target < expect) ++cb;
+        L->cbits[j] = cb;
+        L->dir_base[j] = base;
+        base += (int64_t)(1ull << cb) + 1;
+    }
+    L->dir_base[B] = base;
+    L->dir_total = base;
+}
+
+}  // namespace rhg

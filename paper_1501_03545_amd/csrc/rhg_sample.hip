@@ -1,0 +1,58 @@
+// rhg_sample.hip -- point sampler (Algorithm 1, angular and radial draws).
+//
+// Vertex i draws its two uniforms from Philox4x32-10 (Salmon, Moraes, Dror,
+// Shaw, SC'11) with counter (i_lo, i_hi, 0, 0) and key (seed_lo, seed_hi):
+// one 128-bit block gives two 53-bit uniforms.  The angle is uniform on
+// [0, 2 pi) and the radius follows Eq. (1) by inverting its CDF
+// F(r) = (cosh(alpha r) - 1) / (cosh(alpha R) - 1) (Appendix C with the full
+// angular range): r = acosh(1 + u (cosh(alpha R) - 1)) / alpha, evaluated as
+// log1p(x + sqrt(x (x + 2))) / alpha with x = u (cosh(alpha R) - 1), which
+// keeps full relative accuracy for small u.
+#include "rhg_internal.h"
+
+namespace rhg {
+
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+}
+
+__global__ void __launch_bounds__(256) sample_kernel(int64_t n, uint32_t k0, uint32_t k1, double alpha,
+                                                     double R, double c, double *__restrict__ r,
+                                                     double *__restrict__ theta)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t x0 = (uint32_t)(uint64_t)i, x1 = (uint32_t)((uint64_t)i >> 32), x2 = 0u, x3 = 0u;
+        philox4x32_10(x0, x1, x2, x3, k0, k1);
+        const uint64_t a = ((uint64_t)x1 << 32) | x0;
+        const uint64_t b = ((uint64_t)x3 << 32) | x2;
+        const double ut = (double)(a >> 11) * 0x1p-53;
+        const double ur = (double)(b >> 11) * 0x1p-53;
+        theta[i] = RHG_TWO_PI_D * ut;
+        const double x = ur * c;
+        const double ri = log1p(x + sqrt(x * (x + 2.0))) / alpha;
+        r[i] = fmin(ri, R);  // the exact value is <= R; keep rounding inside
+    }
+}
+
+hipError_t launch_sample(const rhg_params &p, double *r, double *theta, hipStream_t s)
+{
+    if (p.n <= 0) return hipSuccess;
+    int64_t blocks = (p.n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p.n, (uint32_t)p.seed,
+                       (uint32_t)(p.seed >> 32), p.alpha, p.R, p.cosh_aR_m1, r, theta);
+    return hipGetLastError();
+}
+
+}  // namespace rhg

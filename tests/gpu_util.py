@@ -1,0 +1,61 @@
+"""Helpers shared by the GPU tests: run the library through its C ABI and
+compare CSR graphs with the oracle's."""
+import numpy as np
+
+import mpmath as mp
+
+
+def run_search(P, params, r_np, t_np, tuning=None, validate=True):
+    """build_index + count + emit on device for given host points; returns
+    (row_ptr, col, stats) as numpy arrays."""
+    import torch
+    n = int(params.n)
+    r = torch.from_numpy(np.ascontiguousarray(r_np, dtype=np.float64)).cuda()
+    t = torch.from_numpy(np.ascontiguousarray(t_np, dtype=np.float64)).cuda()
+    idx = P.rhg_build_index(params, r, t, tuning=tuning, validate=validate)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    P.rhg_count_edges(idx, row_ptr)
+    nnz = int(row_ptr[-1].item())
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+    P.rhg_emit_edges(idx, row_ptr, col[:nnz] if nnz else col[:0])
+    stats = P.rhg_index_stats(idx)
+    torch.cuda.synchronize()
+    out = row_ptr.cpu().numpy(), col[:nnz].cpu().numpy(), stats
+    idx.free()
+    return out
+
+
+def canonical(row_ptr, col):
+    """Rows sorted ascending (the oracle's order)."""
+    n = row_ptr.shape[0] - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    order = np.lexsort((col, src))
+    return col[order]
+
+
+def check_simple_symmetric(row_ptr, col):
+    n = row_ptr.shape[0] - 1
+    assert row_ptr[0] == 0 and np.all(np.diff(row_ptr) >= 0)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    assert not np.any(src == col), "self-loop"
+    fwd = np.sort(src * n + col)
+    assert np.all(np.diff(fwd) > 0), "duplicate edge"
+    bwd = np.sort(col.astype(np.int64) * n + src)
+    assert np.array_equal(fwd, bwd), "not symmetric"
+
+
+def near_threshold(r1, t1, r2, t2, R, rel=1e-12):
+    """True when cosh(d) of the two points is within `rel` of cosh(R), i.e.
+    an ulp-level change of a coordinate may legitimately flip the pair."""
+    mp.mp.dps = 60
+    r1, t1, r2, t2, R = (mp.mpf(float(x)) for x in (r1, t1, r2, t2, R))
+    L = mp.cosh(r1) * mp.cosh(r2) - mp.sinh(r1) * mp.sinh(r2) * mp.cos(t1 - t2)
+    return abs(L / mp.cosh(R) - 1) < rel
+
+
+def ulp_diff(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ia = a.view(np.int64)
+    ib = b.view(np.int64)
+    return np.abs(ia - ib)

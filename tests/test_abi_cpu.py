@@ -1,0 +1,99 @@
+"""The C-ABI library on a host without a GPU: it loads, exports every entry
+point include/rhg.h declares, and its host-only planning (row a1) agrees with
+the oracle bit for bit.  No device work is launched here."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1501_03545_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_entry_point():
+    hdr = open(os.path.join(ROOT, "include", "rhg.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = sorted(set(re.findall(r"\b(rhg_[a-z_0-9]+)\s*\(", hdr)) - {"rhg_alloc_fn"})
+    assert "rhg_generate" in names and "rhg_emit_edges" in names
+    lib = C.CDLL(P.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert P.version().startswith("rhg-mi355x")
+
+
+CFGS = [(10_000, 6.0, 3.0), (1_000_000, 10.0, 2.7), (100_000_000, 20.0, 2.2), (10_000_000, 16.0, 2.5),
+        (1000, 64.0, 2.1), (1_000_000, 4.0, 3.5), (2, 0.5, 2.5), (50, 3.0, 2.05)]
+
+
+@pytest.mark.parametrize("cfg", CFGS)
+def test_plan_matches_oracle_bitwise(cfg):
+    n, k, g = cfg
+    p = P.rhg_plan(n, k, g, 7)
+    a, R = O.solve_R(n, k, g)
+    assert p.alpha == a
+    assert p.R == R
+    assert p.cosh_R == O.cosh(R)
+    assert p.n == n and p.seed == 7
+
+
+def test_plan_matches_oracle_on_batch_parameter_draws():
+    rng = np.random.default_rng(4)
+    for _ in range(64):
+        n = int(round(10 ** (3 + 3 * rng.random())))
+        k = 4 + 60 * rng.random()
+        g = 2.1 + 1.4 * rng.random()
+        p = P.rhg_plan(n, k, g, 0)
+        assert (p.alpha, p.R) == O.solve_R(n, k, g)
+
+
+def test_plan_derived_constants():
+    import mpmath as mp
+    mp.mp.dps = 50
+    p = P.rhg_plan(100_000_000, 20.0, 2.2, 3)
+    cR = mp.cosh(mp.mpf(p.R))
+    assert abs((mp.mpf(p.cosh_R) + mp.mpf(p.cosh_R_lo)) / cR - 1) < 1e-30
+    c = mp.cosh(mp.mpf(p.alpha) * mp.mpf(p.R)) - 1
+    assert abs((mp.mpf(p.cosh_aR_m1) + mp.mpf(p.cosh_aR_m1_lo)) / c - 1) < 1e-30
+
+
+@pytest.mark.parametrize("args,status", [
+    ((-1, 6.0, 3.0), P.RHG_EINVAL), ((2**31, 6.0, 3.0), P.RHG_EINVAL), ((1000, 6.0, 2.0), P.RHG_EINVAL),
+    ((1000, 6.0, float("nan")), P.RHG_EINVAL), ((1000, 0.0, 3.0), P.RHG_EINVAL),
+    ((1000, 999.0, 3.0), P.RHG_EINVAL), ((1000, -3.0, 3.0), P.RHG_EINVAL)])
+def test_plan_rejects_invalid_arguments(args, status):
+    with pytest.raises(P.RhgError) as ei:
+        P.rhg_plan(*args, 1)
+    assert ei.value.status == status
+
+
+def test_plan_reports_unreachable_degree():
+    # gamma close to 3.5 at small n: Eq. (22) peaks below the target
+    a = O.alpha(3.5)
+    peak = max(O.kbar_eq22(200, a, x) for x in np.linspace(0.1, 60, 4000))
+    assert peak < 150
+    with pytest.raises(P.RhgError) as ei:
+        P.rhg_plan(200, 150.0, 3.5, 1)
+    assert ei.value.status == P.RHG_ENOROOT
+
+
+def test_plan_small_n_and_radius_form():
+    p0 = P.rhg_plan(0, 5.0, 2.5, 1)
+    p1 = P.rhg_plan(1, 5.0, 2.5, 1)
+    assert p0.n == 0 and p1.n == 1
+    q = P.rhg_plan_radius(1000, 0.8, 5.08, 9)
+    assert q.alpha == 0.8 and q.R == 5.08 and math.isnan(q.gamma)
+    for bad in [(1000, 0.5, 5.0), (1000, 0.8, 0.0), (1000, 0.8, 400.0), (-5, 0.8, 5.0)]:
+        with pytest.raises(P.RhgError):
+            P.rhg_plan_radius(*bad, 0)
+
+
+def test_workspace_size_is_host_only_and_grows_with_n():
+    small = P.rhg_index_workspace_bytes(P.rhg_plan(10_000, 6.0, 3.0, 1))
+    big = P.rhg_index_workspace_bytes(P.rhg_plan(1_000_000, 10.0, 2.7, 1))
+    assert 0 < small < big
+    assert big >= 52 * 1_000_000

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Edge sets are compared exactly (canonical rows), on the oracle's own points
+for the search (rows a3-a6) and on each side's own points for the whole
+pipeline (rows a1-a6)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1501_03545_amd as P
+from gpu_util import canonical, check_simple_symmetric, near_threshold, run_search, ulp_diff
+
+pytestmark = pytest.mark.gpu
+
+C1 = (10_000, 6.0, 3.0)
+C2 = (1_000_000, 10.0, 2.7)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def setup_module(_):
+    O.build(force=False)
+    P.load()
+
+
+def _params_for(n, k, g, seed):
+    if n >= 2:
+        a, R = O.solve_R(n, k, g)
+    else:
+        a, R = (g - 1) / 2, 5.0
+    return P.rhg_plan_radius(n, a, R, seed), a, R
+
+
+@pytest.mark.parametrize("cfg", [C1, (100_000, 20.0, 2.2)])
+def test_sampler_angles_bitexact_radii_within_ulps(cfg):
+    import torch
+    n, k, g = cfg
+    _say("sampler", cfg)
+    p = P.rhg_plan(n, k, g, 12345)
+    r = torch.empty(n, dtype=torch.float64, device="cuda")
+    t = torch.empty(n, dtype=torch.float64, device="cuda")
+    P.rhg_sample_points(p, r, t)
+    ro, to, hard = O.sample(12345, p.alpha, p.R, n)
+    assert hard == 0
+    tg, rg = t.cpu().numpy(), r.cpu().numpy()
+    assert np.array_equal(tg, to)  # Philox words and the angle product, bit for bit
+    d = ulp_diff(rg, ro)
+    _say("radius ulp differences: max", int(d.max()), "nonzero", int(np.count_nonzero(d)))
+    assert d.max() <= 4
+    assert rg.min() >= 0 and rg.max() <= p.R
+
+
+SMALL = [(2, 0.5, 2.5, 1), (3, 1.0, 2.5, 2), (17, 4.0, 2.5, 3), (1000, 64.0, 2.1, 4), (4097, 8.0, 3.5, 5),
+         (2000, 30.0, 2.3, 6), C1 + (1,)]
+
+
+@pytest.mark.parametrize("cfg", SMALL)
+def test_search_parity_on_oracle_points(cfg):
+    n, k, g, seed = cfg
+    _say("search parity", cfg)
+    params, a, R = _params_for(n, k, g, seed)
+    r, t, _ = O.sample(seed, a, R, n)
+    rp, col, stats = run_search(P, params, r, t)
+    orp, ocol, nq, nt = O.csr(r, t, R)
+    assert nt == 0 and stats["ties"] == 0
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(canonical(rp, col), ocol)
+
+
+def test_search_parity_independent_of_tuning():
+    n, k, g = C1
+    params, a, R = _params_for(n, k, g, 11)
+    r, t, _ = O.sample(11, a, R, n)
+    orp, ocol, _, _ = O.csr(r, t, R)
+    for tun in [None, {"band_width": 0.25}, {"band_width": 3.0, "cell_target": 1},
+                {"band_width": 0.5, "inner_radius": 12.0, "cell_target": 64}, {"cell_target": 2},
+                {"band_width": 100.0}]:
+        _say("tuning", tun)
+        rp, col, stats = run_search(P, params, r, t, tuning=tun)
+        assert np.array_equal(rp, orp)
+        assert np.array_equal(canonical(rp, col), ocol)
+
+
+def test_search_degenerate_inputs():
+    """Points at the origin, on the rim, sharing an angle, duplicated, and
+    straddling the 0 / 2 pi seam."""
+    n, k, g = 3000, 10.0, 2.5
+    params, a, R = _params_for(n, k, g, 21)
+    r, t, _ = O.sample(21, a, R, n)
+    r = r.copy(); t = t.copy()
+    r[0] = 0.0
+    r[1] = R
+    r[2], t[2] = r[3], t[3]                      # duplicate point
+    t[4:40] = t[40]                              # many equal angles
+    t[41] = 0.0
+    t[42] = np.nextafter(2 * np.pi, 0)           # largest double below 2 pi
+    t[43] = 1e-12
+    r[41:44] = R - 0.1
+    rp, col, stats = run_search(P, params, r, t)
+    orp, ocol, _, nt = O.csr(r, t, R)
+    # the origin and the rim point are exactly R apart: a true tie, which
+    # both sides must resolve as an edge (distance <= R)
+    assert nt > 0 and stats["ties"] > 0
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(canonical(rp, col), ocol)
+    assert rp[1] - rp[0] == n - 1  # the origin sees every vertex
+    assert 0 in col[rp[1]:rp[2]]
+
+
+def test_empty_and_tiny_graphs():
+    import torch
+    for n in [0, 1]:
+        p = P.rhg_plan(n, 5.0, 2.5, 1)
+        g = P.rhg_generate(n, 5.0, 2.5, 1)
+        assert g.nnz == 0
+        assert g.row_ptr.cpu().tolist() == [0] * (n + 1)
+
+
+def test_invalid_points_and_capacity_are_reported():
+    import torch
+    n = 100
+    params, a, R = _params_for(n, 5.0, 2.5, 1)
+    r, t, _ = O.sample(1, a, R, n)
+    bad = r.copy()
+    bad[7] = R * 1.5
+    with pytest.raises(P.RhgError) as ei:
+        run_search(P, params, bad, t)
+    assert ei.value.status == P.RHG_EINVAL
+    rt = torch.from_numpy(r).cuda()
+    tt = torch.from_numpy(t).cuda()
+    idx = P.rhg_build_index(params, rt, tt)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    P.rhg_count_edges(idx, row_ptr)
+    nnz = int(row_ptr[-1])
+    assert nnz > 0
+    small = torch.empty(nnz - 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(P.RhgError) as ei:
+        P.rhg_emit_edges(idx, row_ptr, small)
+    assert ei.value.status == P.RHG_ECAPACITY
+
+
+def _pipeline_compare(g, r_o, t_o, R, orp, ocol):
+    """GPU pipeline vs oracle pipeline: angles bit-exact, radii within ulps,
+    edges identical except pairs an ulp of radius can flip (none expected)."""
+    tg = g.theta.cpu().numpy()
+    rg = g.r.cpu().numpy()
+    assert np.array_equal(tg, t_o)
+    assert ulp_diff(rg, r_o).max() <= 4
+    rp = g.row_ptr.cpu().numpy()
+    col = g.col_idx.cpu().numpy()
+    check_simple_symmetric(rp, col)
+    n = rp.shape[0] - 1
+    a = set((np.repeat(np.arange(n), np.diff(rp)) * n + col).tolist())
+    b = set((np.repeat(np.arange(n), np.diff(orp)) * n + ocol).tolist())
+    diff = a ^ b
+    for key in list(diff)[:100]:
+        i, j = divmod(key, n)
+        assert near_threshold(r_o[i], t_o[i], r_o[j], t_o[j], R), (i, j)
+    return len(diff)
+
+
+def test_generate_pipeline_matches_oracle_c1():
+    n, k, g_ = C1
+    _say("generate C1")
+    g = P.rhg_generate(n, k, g_, 1)
+    a, R, r_o, t_o, orp, ocol, st = O.generate(n, k, g_, 1)
+    assert g.params.R == R and g.params.alpha == a
+    assert st["ties"] == 0
+    mism = _pipeline_compare(g, r_o, t_o, R, orp, ocol)
+    _say("pipeline mismatched pairs", mism)
+    assert mism == 0
+
+
+def test_c2_full_graph_invariants_and_sampled_rows():
+    n, k, g_ = C2
+    _say("generate C2")
+    g = P.rhg_generate(n, k, g_, 2)
+    rp = g.row_ptr.cpu().numpy()
+    col = g.col_idx.cpu().numpy()
+    check_simple_symmetric(rp, col)
+    deg = np.diff(rp)
+    _say("C2 edges", col.size // 2, "mean degree", deg.mean())
+    a, R = O.solve_R(n, k, g_)
+    r_o, t_o, hard = O.sample(2, a, R, n)
+    assert hard == 0
+    assert np.array_equal(g.theta.cpu().numpy(), t_o)
+    assert ulp_diff(g.r.cpu().numpy(), r_o).max() <= 4
+    # rows stratified by radius quantile, plus the 32 largest degrees
+    order = np.argsort(r_o)
+    strat = order[np.linspace(0, n - 1, 160).astype(np.int64)]
+    top = np.argsort(deg)[-32:]
+    which = np.unique(np.concatenate([strat, top]))
+    ptr, ocol, _, nt = O.rows(r_o, t_o, R, which)
+    assert nt == 0
+    for a_, i in enumerate(which):
+        mine = np.sort(col[rp[i]:rp[i + 1]])
+        ref = ocol[ptr[a_]:ptr[a_ + 1]]
+        if not np.array_equal(mine, ref):
+            for j in np.setxor1d(mine, ref):
+                assert near_threshold(r_o[i], t_o[i], r_o[j], t_o[j], R), (i, j)
+    # the GPU search on the oracle's own points is bit-exact on the same rows
+    rp2, col2, stats = run_search(P, P.rhg_plan_radius(n, a, R, 2), r_o, t_o)
+    assert stats["ties"] == 0
+    for a_, i in enumerate(which):
+        assert np.array_equal(np.sort(col2[rp2[i]:rp2[i + 1]]), ocol[ptr[a_]:ptr[a_ + 1]])

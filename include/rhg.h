@@ -74,7 +74,8 @@ typedef struct {
     double band_width;     /* radial width of the outer bands                 */
     double inner_radius;   /* radius below which all points share one band    */
     int32_t cell_target;   /* mean points per angular cell                    */
-    int32_t reserved[5];
+    int32_t heavy_points;  /* expected points searched one per workgroup      */
+    int32_t reserved[4];
 } rhg_tuning;
 
 /* Device-side diagnostics of the last count/emit pass over an index. */
@@ -102,7 +103,7 @@ typedef struct rhg_index rhg_index;  /* opaque, host-side handle */
 rhg_status rhg_plan(int64_t n, double avg_degree, double gamma, uint64_t seed,
                     rhg_params *out /* host */);
 
-/* Same with alpha and R given directly (0.5 < alpha, 0 < R < 300, alpha R < 600). */
+/* Same with alpha and R given directly (0.5 < alpha, 0 < R < 80). */
 rhg_status rhg_plan_radius(int64_t n, double alpha, double R, uint64_t seed,
                            rhg_params *out /* host */);
 
@@ -196,6 +197,25 @@ rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t see
                         const rhg_tuning *t /* host, may be NULL */,
                         rhg_alloc_fn alloc, void *alloc_ctx, int canonical_rows,
                         rhg_csr *out /* host */, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Phase timing (HIP events on the caller's stream).                   */
+/* ------------------------------------------------------------------ */
+
+/* Turns event timing of the library's phases on (1) or off (0) and clears
+ * the record ring (512 entries).  Turning it on creates the events once;
+ * call it outside any timed region.  Process-wide, not thread-safe. */
+rhg_status rhg_set_profiling(int on);
+
+/* Average duration in ms and number of recorded launches of each phase
+ * since profiling was last turned on (synchronises on the events).  Phases:
+ * 0 sample, 1 keys+sort, 2 index (band starts + directory), 3 gather,
+ * 4 count pass, 5 scan, 6 emit pass.  avg_ms, count: host arrays of at
+ * least 7 entries (cap). */
+rhg_status rhg_phase_times(double *avg_ms /* host */, int64_t *count /* host */, int cap);
+
+/* Name of a phase index ("" if out of range). */
+const char *rhg_phase_name(int phase);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *rhg_last_error(void);

@@ -9,7 +9,6 @@ load, importing a function raises.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 from dataclasses import dataclass
 from typing import Optional
@@ -37,7 +36,7 @@ class rhg_params(C.Structure):
 
 class rhg_tuning(C.Structure):
     _fields_ = [("band_width", C.c_double), ("inner_radius", C.c_double),
-                ("cell_target", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class rhg_stats(C.Structure):
@@ -76,6 +75,9 @@ def load():
         "rhg_index_stats": (i32, [vp, P(rhg_stats), vp]),
         "rhg_index_free": (None, [vp]),
         "rhg_generate": (i32, [i64, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
+        "rhg_set_profiling": (i32, [i32]),
+        "rhg_phase_times": (i32, [P(C.c_double), P(C.c_int64), i32]),
+        "rhg_phase_name": (C.c_char_p, [i32]),
         "rhg_last_error": (C.c_char_p, []),
         "rhg_version": (C.c_char_p, []),
     }
@@ -110,6 +112,7 @@ def _tuning(t: Optional[dict]):
     tu.band_width = float(t.get("band_width", 0.0))
     tu.inner_radius = float(t.get("inner_radius", 0.0))
     tu.cell_target = int(t.get("cell_target", 0))
+    tu.heavy_points = int(t.get("heavy_points", 0))
     return C.byref(tu)
 
 
@@ -191,6 +194,23 @@ def rhg_index_stats(idx: Index, stream=None) -> dict:
     return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties}
 
 
+PHASES = ["sample", "keys+sort", "index", "gather", "count", "scan", "emit"]
+
+
+def rhg_set_profiling(on: bool):
+    """Record HIP events around each library phase (see rhg_phase_times)."""
+    _check(load().rhg_set_profiling(1 if on else 0))
+
+
+def rhg_phase_times() -> dict:
+    """{phase name: (average ms per launch, launches)} since profiling was enabled."""
+    k = len(PHASES)
+    ms = (C.c_double * k)()
+    cnt = (C.c_int64 * k)()
+    _check(load().rhg_phase_times(ms, cnt, k))
+    return {load().rhg_phase_name(i).decode(): (ms[i], cnt[i]) for i in range(k)}
+
+
 @dataclass
 class Graph:
     params: rhg_params
@@ -235,4 +255,5 @@ def rhg_generate(n: int, avg_degree: float, gamma: float, seed: int, tuning: Opt
 
 __all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_workspace_bytes",
            "rhg_build_index", "rhg_count_edges", "rhg_emit_edges", "rhg_index_stats", "rhg_generate",
-           "RhgError", "Graph", "Index", "load", "version", "LIB_PATH"]
+           "rhg_set_profiling", "rhg_phase_times", "RhgError", "Graph", "Index", "load", "version",
+           "LIB_PATH", "PHASES"]

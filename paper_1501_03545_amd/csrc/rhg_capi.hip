@@ -32,8 +32,36 @@ __global__ void zero_u64_kernel(unsigned long long *p, int count)
     if (i < count) p[i] = 0ull;
 }
 
+// ---- optional phase timing: HIP events recorded on the caller's stream
+// around each kernel group, kept in a ring and averaged on request.
+static const char *kPhaseNames[RHG_PHASE_COUNT] = {"sample", "keys+sort", "index", "gather", "count",
+                                                   "scan", "emit"};
+struct ProfRec {
+    int phase;
+    hipEvent_t a, b;
+};
+static const int kProfRing = 512;
+static ProfRec g_prof[kProfRing];
+static int g_prof_on = 0, g_prof_next = 0, g_prof_used = 0, g_prof_ready = 0;
+
+void *phase_begin(int phase, hipStream_t s)
+{
+    if (!g_prof_on || !g_prof_ready) return nullptr;
+    ProfRec *rec = &g_prof[g_prof_next];
+    g_prof_next = (g_prof_next + 1) % kProfRing;
+    if (g_prof_used < kProfRing) ++g_prof_used;
+    rec->phase = phase;
+    hipEventRecord(rec->a, s);
+    return rec;
+}
+
+void phase_end(void *rec, hipStream_t s)
+{
+    if (rec) hipEventRecord(((ProfRec *)rec)->b, s);
+}
+
 struct WsPlan {
-    size_t keys, v0, band_start, dir, sr, st, sep, sem, ssh, sid, stats, tmp, total, tmp_bytes;
+    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, heavy_cnt, stats, tmp, total, tmp_bytes;
 };
 
 static WsPlan ws_plan(int64_t n, const Layout &L)
@@ -52,10 +80,9 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.dir = take((size_t)L.dir_total * 4);
     w.sr = take(N * 8);
     w.st = take(N * 8);
-    w.sep = take(N * 8);
-    w.sem = take(N * 8);
-    w.ssh = take(N * 8);
-    w.sid = take(N * 4);
+    w.rec = take(N * 16);
+    w.heavy_end = take(16);
+    w.heavy_cnt = take((size_t)(L.heavy_cap > 0 ? L.heavy_cap : 1) * L.B * 4);
     w.stats = take(ST_COUNT * 8);
     size_t t1 = radix_sort_tmp_bytes(n), t2 = scan_tmp_bytes(n + 1);
     w.tmp_bytes = t1 > t2 ? t1 : t2;
@@ -73,6 +100,44 @@ extern "C" {
 const char *rhg_last_error(void) { return g_last_error.c_str(); }
 
 const char *rhg_version(void) { return "rhg-mi355x 0.1 (gfx950)"; }
+
+rhg_status rhg_set_profiling(int on)
+{
+    g_last_error.clear();
+    if (on && !g_prof_ready) {
+        for (int i = 0; i < kProfRing; ++i) {
+            RHG_HIP(hipEventCreate(&g_prof[i].a));
+            RHG_HIP(hipEventCreate(&g_prof[i].b));
+        }
+        g_prof_ready = 1;
+    }
+    g_prof_on = on ? 1 : 0;
+    g_prof_next = 0;
+    g_prof_used = 0;
+    return RHG_OK;
+}
+
+rhg_status rhg_phase_times(double *avg_ms, int64_t *count, int cap)
+{
+    g_last_error.clear();
+    if (!avg_ms || !count || cap < RHG_PHASE_COUNT) return fail(RHG_EINVAL, "rhg_phase_times: bad buffers");
+    for (int k = 0; k < RHG_PHASE_COUNT; ++k) { avg_ms[k] = 0.0; count[k] = 0; }
+    for (int i = 0; i < g_prof_used; ++i) {
+        RHG_HIP(hipEventSynchronize(g_prof[i].b));
+        float ms = 0.f;
+        RHG_HIP(hipEventElapsedTime(&ms, g_prof[i].a, g_prof[i].b));
+        avg_ms[g_prof[i].phase] += ms;
+        count[g_prof[i].phase] += 1;
+    }
+    for (int k = 0; k < RHG_PHASE_COUNT; ++k)
+        if (count[k]) avg_ms[k] /= (double)count[k];
+    return RHG_OK;
+}
+
+const char *rhg_phase_name(int phase)
+{
+    return (phase >= 0 && phase < RHG_PHASE_COUNT) ? kPhaseNames[phase] : "";
+}
 
 rhg_status rhg_plan(int64_t n, double avg_degree, double gamma, uint64_t seed, rhg_params *out)
 {
@@ -101,6 +166,7 @@ rhg_status rhg_sample_points(const rhg_params *p, double *r, double *theta, void
     rhg_status st = check_params(p, "rhg_sample_points");
     if (st != RHG_OK) return st;
     if (p->n > 0 && (!r || !theta)) return fail(RHG_EINVAL, "rhg_sample_points: NULL output");
+    PhaseScope ps(RHG_PHASE_SAMPLE, (hipStream_t)stream);
     RHG_HIP(launch_sample(*p, r, theta, (hipStream_t)stream));
     return RHG_OK;
 }
@@ -123,7 +189,8 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     if (!out) return fail(RHG_EINVAL, "rhg_build_index: out is NULL");
     *out = nullptr;
     if (p->n > 0 && (!r || !theta)) return fail(RHG_EINVAL, "rhg_build_index: NULL points");
-    if (t && (t->band_width < 0.0 || t->inner_radius < 0.0 || t->cell_target < 0 || !(t->band_width < 1e6)))
+    if (t && (t->band_width < 0.0 || t->inner_radius < 0.0 || t->cell_target < 0 || t->heavy_points < 0 ||
+              !(t->band_width < 1e6)))
         return fail(RHG_EINVAL, "rhg_build_index: negative tuning value");
     rhg_index *idx = new (std::nothrow) rhg_index;
     if (!idx) return fail(RHG_ENOMEM, "rhg_build_index: host allocation failed");
@@ -143,17 +210,17 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->dir = (int32_t *)(base + w.dir);
     idx->sr = (double *)(base + w.sr);
     idx->st = (double *)(base + w.st);
-    idx->sep = (double *)(base + w.sep);
-    idx->sem = (double *)(base + w.sem);
-    idx->ssh = (double *)(base + w.ssh);
-    idx->sid = (int32_t *)(base + w.sid);
+    idx->rec = (float4 *)(base + w.rec);
+    idx->heavy_end = (int32_t *)(base + w.heavy_end);
+    idx->heavy_cnt = (int32_t *)(base + w.heavy_cnt);
+    idx->heavy_cap = idx->L.heavy_cap;
     idx->stats = (unsigned long long *)(base + w.stats);
     idx->tmp = base + w.tmp;
     idx->tmp_bytes = w.tmp_bytes;
-    // the sort's second key/value buffers live in the e^r / e^-r arrays,
+    // the sort's second key/value buffers live in the FP32 record array,
     // which the gather step fills only after the sort has finished
-    uint32_t *k1 = (uint32_t *)idx->sep;
-    uint32_t *v1 = (uint32_t *)idx->sem;
+    uint32_t *k1 = (uint32_t *)idx->rec;
+    uint32_t *v1 = k1 + (p->n > 0 ? p->n : 1);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, idx->stats, (int)ST_COUNT);
     hipError_t e = hipGetLastError();
@@ -185,8 +252,14 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream)
     g_last_error.clear();
     if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_count_edges: NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    RHG_HIP(launch_search(idx, row_ptr, nullptr, 0, s));
-    if (idx->n > 0) RHG_HIP(inclusive_scan_i64(row_ptr + 1, idx->n, idx->tmp, s));
+    {
+        PhaseScope ps(RHG_PHASE_COUNT_PASS, s);
+        RHG_HIP(launch_search(idx, row_ptr, nullptr, 0, s));
+    }
+    if (idx->n > 0) {
+        PhaseScope ps(RHG_PHASE_SCAN, s);
+        RHG_HIP(inclusive_scan_i64(row_ptr + 1, idx->n, idx->tmp, s));
+    }
     return RHG_OK;
 }
 
@@ -205,7 +278,10 @@ rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_i
         return fail(RHG_ECAPACITY, "rhg_emit_edges: col_idx holds " + std::to_string(col_capacity) +
                                        " entries, the graph needs " + std::to_string(nnz));
     if (nnz > 0 && !col_idx) return fail(RHG_EINVAL, "rhg_emit_edges: col_idx is NULL");
-    if (nnz > 0) RHG_HIP(launch_search(idx, (int64_t *)row_ptr, col_idx, 1, s));
+    if (nnz > 0) {
+        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
+        RHG_HIP(launch_search(idx, (int64_t *)row_ptr, col_idx, 1, s));
+    }
     return RHG_OK;
 }
 

@@ -114,13 +114,14 @@ __global__ void __launch_bounds__(256) dir_kernel(DirArgs A, const uint32_t *__r
     }
 }
 
-// Sorted per-point records: r, theta, e^r, e^-r, sinh r and the original id.
+// Sorted per-point records: r, theta (binary64) and the FP32 screen record
+// (e^r / sqrt(2 cosh R), e^-r / sqrt(2 cosh R), sinh r sqrt(2 / cosh R),
+// original id as raw bits).
 __global__ void __launch_bounds__(256) gather_kernel(int64_t n, const double *__restrict__ r,
                                                      const double *__restrict__ theta,
-                                                     const uint32_t *__restrict__ perm, double *__restrict__ sr,
-                                                     double *__restrict__ st, double *__restrict__ sep,
-                                                     double *__restrict__ sem, double *__restrict__ ssh,
-                                                     int32_t *__restrict__ sid)
+                                                     const uint32_t *__restrict__ perm, double inv, double sc,
+                                                     double *__restrict__ sr, double *__restrict__ st,
+                                                     float4 *__restrict__ rec)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
@@ -129,10 +130,8 @@ __global__ void __launch_bounds__(256) gather_kernel(int64_t n, const double *__
         const double ri = r[id];
         sr[p] = ri;
         st[p] = theta[id];
-        sep[p] = exp(ri);
-        sem[p] = exp(-ri);
-        ssh[p] = sinh(ri);
-        sid[p] = (int32_t)id;
+        rec[p] = make_float4((float)(exp(ri) * inv), (float)(exp(-ri) * inv), (float)(sinh(ri) * sc),
+                             __int_as_float((int)id));
     }
 }
 
@@ -156,11 +155,13 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
     ka.R = idx->p.R;
     hipError_t e;
     if (n > 0) {
+        PhaseScope ps(RHG_PHASE_SORT, s);
         hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(256), 0, s, ka, n, r, theta, idx->keys, v0,
                            validate, idx->stats);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = radix_sort_pairs(idx->keys, v0, k1, v1, n, 32, idx->tmp, s)) != hipSuccess) return e;
     }
+    PhaseScope ps_index(RHG_PHASE_INDEX, s);
     hipLaunchKernelGGL(band_start_kernel, dim3(1), dim3(128), 0, s, idx->keys, n, L.B, L.band_bits,
                        idx->band_start);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -173,9 +174,13 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
     hipLaunchKernelGGL(dir_kernel, dim3(grid_for(L.dir_total)), dim3(256), 0, s, da, idx->keys, idx->band_start,
                        idx->dir);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    phase_end(ps_index.rec, s);
+    ps_index.rec = nullptr;
     if (n > 0) {
-        hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, r, theta, v0, idx->sr, idx->st,
-                           idx->sep, idx->sem, idx->ssh, idx->sid);
+        PhaseScope ps(RHG_PHASE_GATHER, s);
+        const double inv = 1.0 / sqrt(2.0 * idx->p.cosh_R), sc = sqrt(2.0 / idx->p.cosh_R);
+        hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, r, theta, v0, inv, sc, idx->sr,
+                           idx->st, idx->rec);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

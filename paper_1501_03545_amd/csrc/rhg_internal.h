@@ -36,9 +36,25 @@ struct Layout {
     int cbits[RHG_MAX_BANDS];         // log2 of the cell count per band
     int64_t dir_base[RHG_MAX_BANDS + 1];  // offset of band j's directory
     int64_t dir_total;                // entries of the directory (all bands)
+    int heavy_band;                   // bands [0, heavy_band) hold the heavy queries
+    int64_t heavy_cap;                // at most this many heavy queries
 };
 
 void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L);
+
+// Timed phases (rhg_phase_times).
+enum { RHG_PHASE_SAMPLE = 0, RHG_PHASE_SORT = 1, RHG_PHASE_INDEX = 2, RHG_PHASE_GATHER = 3,
+       RHG_PHASE_COUNT_PASS = 4, RHG_PHASE_SCAN = 5, RHG_PHASE_EMIT_PASS = 6, RHG_PHASE_COUNT = 7 };
+
+// Brackets a phase with HIP events on stream s when profiling is on.
+void *phase_begin(int phase, hipStream_t s);
+void phase_end(void *rec, hipStream_t s);
+struct PhaseScope {
+    void *rec;
+    hipStream_t s;
+    PhaseScope(int phase, hipStream_t st) : rec(phase_begin(phase, st)), s(st) {}
+    ~PhaseScope() { phase_end(rec, s); }
+};
 
 // Device-side counters (one 64-bit word each).
 enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4, ST_COUNT = 8 };
@@ -55,8 +71,10 @@ struct rhg_index {
     int32_t *band_start;   // B + 1 sorted positions
     int32_t *dir;          // directory, dir_total entries
     double *sr, *st;       // sorted r, theta (n each)
-    double *sep, *sem, *ssh;  // sorted e^r, e^-r, sinh r (n each)
-    int32_t *sid;          // original id of each sorted position (n)
+    float4 *rec;           // sorted (e^r, e^-r, sinh r) normalised by cosh R, and the id (n)
+    int32_t *heavy_end;    // first light position (device scalar)
+    int32_t *heavy_cnt;    // heavy_cap * B per-item counts, then offsets
+    int64_t heavy_cap;
     unsigned long long *stats;  // ST_COUNT counters
     void *tmp;             // scratch for sort and scan
     size_t tmp_bytes;

@@ -108,7 +108,7 @@ rhg_status plan_radius(int64_t n, double alpha, double R, uint64_t seed, rhg_par
     if (!out) return fail(RHG_EINVAL, "rhg_plan_radius: out is NULL");
     if (n < 0 || n > 2147483647LL) return fail(RHG_EINVAL, "rhg_plan_radius: n must be in [0, 2^31 - 1]");
     if (!(alpha > 0.5) || !isfinite(alpha)) return fail(RHG_EINVAL, "rhg_plan_radius: alpha must be > 1/2");
-    if (!(R > 0.0) || !(R < 300.0)) return fail(RHG_EINVAL, "rhg_plan_radius: R must be in (0, 300)");
+    if (!(R > 0.0) || !(R < 80.0)) return fail(RHG_EINVAL, "rhg_plan_radius: R must be in (0, 80)");
     if (!(alpha * R < 600.0)) return fail(RHG_EINVAL, "rhg_plan_radius: alpha * R must be < 600");
     rhg_params p;
     memset(&p, 0, sizeof(p));
@@ -166,6 +166,16 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     }
     L->dir_base[B] = base;
     L->dir_total = base;
+    // Heavy queries: the innermost bands, holding about `heavy_points` points
+    // in expectation (those with the largest degrees, about 5e3 and more at
+    // n = 1e8).  The cap leaves room for the statistical excess.
+    const double hp = (t && t->heavy_points > 0) ? (double)t->heavy_points : 16384.0;
+    int jh = 0;
+    while (jh < B && n * ((cosh(a * L->E[jh + 1]) - 1.0) / denom) <= hp) ++jh;
+    if (jh >= B) jh = B - 1;
+    L->heavy_band = jh;
+    const double cap = 1.25 * hp + 1024.0;
+    L->heavy_cap = jh > 0 ? (int64_t)std::min(cap, n) : 0;
 }
 
 }  // namespace rhg

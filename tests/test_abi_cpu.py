@@ -87,7 +87,7 @@ def test_plan_small_n_and_radius_form():
     assert p0.n == 0 and p1.n == 1
     q = P.rhg_plan_radius(1000, 0.8, 5.08, 9)
     assert q.alpha == 0.8 and q.R == 5.08 and math.isnan(q.gamma)
-    for bad in [(1000, 0.5, 5.0), (1000, 0.8, 0.0), (1000, 0.8, 400.0), (-5, 0.8, 5.0)]:
+    for bad in [(1000, 0.5, 5.0), (1000, 0.8, 0.0), (1000, 0.8, 90.0), (-5, 0.8, 5.0)]:
         with pytest.raises(P.RhgError):
             P.rhg_plan_radius(*bad, 0)
 
@@ -96,4 +96,4 @@ def test_workspace_size_is_host_only_and_grows_with_n():
     small = P.rhg_index_workspace_bytes(P.rhg_plan(10_000, 6.0, 3.0, 1))
     big = P.rhg_index_workspace_bytes(P.rhg_plan(1_000_000, 10.0, 2.7, 1))
     assert 0 < small < big
-    assert big >= 52 * 1_000_000
+    assert big >= 40 * 1_000_000

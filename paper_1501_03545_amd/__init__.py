@@ -61,6 +61,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("librhg.so is not built (run paper_1501_03545_amd/build.py or "
                            "__graft_entry__.build()); there is no fallback path")
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one.  Loading torch first makes librhg.so bind to that same runtime, so
+    # that torch's streams and allocations are valid handles for the library.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i64, d, u64, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_uint64, C.c_int
     P = C.POINTER

@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -61,7 +62,8 @@ void phase_end(void *rec, hipStream_t s)
 }
 
 struct WsPlan {
-    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, heavy_cnt, stats, tmp, total, tmp_bytes;
+    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcnt, hitem, hscal, stats, tmp, total, tmp_bytes;
+    int64_t max_chunks;
 };
 
 static WsPlan ws_plan(int64_t n, const Layout &L)
@@ -82,10 +84,16 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.st = take(N * 8);
     w.rec = take(N * 16);
     w.heavy_end = take(16);
-    w.heavy_cnt = take((size_t)(L.heavy_cap > 0 ? L.heavy_cap : 1) * L.B * 4);
+    const int64_t items = L.heavy_cap * L.B;
+    w.max_chunks = items > 0 ? items + RHG_HEAVY_EXTRA_CHUNKS : 1;
+    w.hplan = take((size_t)(items > 0 ? items : 1) * 8);
+    w.hcnt = take((size_t)w.max_chunks * 8);
+    w.hitem = take((size_t)w.max_chunks * 4);
+    w.hscal = take(64);
     w.stats = take(ST_COUNT * 8);
     size_t t1 = radix_sort_tmp_bytes(n), t2 = scan_tmp_bytes(n + 1);
-    w.tmp_bytes = t1 > t2 ? t1 : t2;
+    size_t t3 = scan_tmp_bytes(w.max_chunks), t4 = scan_tmp_bytes(items > 0 ? items : 1);
+    w.tmp_bytes = std::max(std::max(t1, t2), std::max(t3, t4));
     w.tmp = take(w.tmp_bytes);
     w.total = off + 256;  // slack for aligning the base pointer
     return w;
@@ -212,8 +220,12 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->st = (double *)(base + w.st);
     idx->rec = (float4 *)(base + w.rec);
     idx->heavy_end = (int32_t *)(base + w.heavy_end);
-    idx->heavy_cnt = (int32_t *)(base + w.heavy_cnt);
+    idx->hplan = (int64_t *)(base + w.hplan);
+    idx->hcnt = (int64_t *)(base + w.hcnt);
+    idx->hitem = (int32_t *)(base + w.hitem);
+    idx->hscal = (int64_t *)(base + w.hscal);
     idx->heavy_cap = idx->L.heavy_cap;
+    idx->max_chunks = w.max_chunks;
     idx->stats = (unsigned long long *)(base + w.stats);
     idx->tmp = base + w.tmp;
     idx->tmp_bytes = w.tmp_bytes;

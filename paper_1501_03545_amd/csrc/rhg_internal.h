@@ -10,6 +10,9 @@
 #define RHG_MAX_BANDS 64
 #define RHG_TWO_PI_D 6.283185307179586
 #define RHG_TWO_PI_RES_D 2.4492935982947064e-16
+#define RHG_HEAVY_CHUNK 8192      // candidates per heavy chunk (at least)
+#define RHG_HEAVY_BLOCKS 2048     // workgroups striding over the heavy chunks
+#define RHG_HEAVY_EXTRA_CHUNKS (1 << 20)
 
 namespace rhg {
 
@@ -73,8 +76,12 @@ struct rhg_index {
     double *sr, *st;       // sorted r, theta (n each)
     float4 *rec;           // sorted (e^r, e^-r, sinh r) normalised by cosh R, and the id (n)
     int32_t *heavy_end;    // first light position (device scalar)
-    int32_t *heavy_cnt;    // heavy_cap * B per-item counts, then offsets
+    int64_t *hplan;        // heavy_cap * B items: candidates, chunks, prefix of chunks
+    int64_t *hcnt;         // max_chunks heavy chunks: counts, then their prefix
+    int32_t *hitem;        // max_chunks heavy chunks: the item of each
+    int64_t *hscal;        // heavy plan scalars
     int64_t heavy_cap;
+    int64_t max_chunks;
     unsigned long long *stats;  // ST_COUNT counters
     void *tmp;             // scratch for sort and scan
     size_t tmp_bytes;

@@ -134,7 +134,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     memset(L, 0, sizeof(*L));
     const double R = p.R, a = p.alpha;
     const double n = (double)std::max<int64_t>(p.n, 1);
-    double w = (t && t->band_width > 0.0) ? t->band_width : 1.0;
+    double w = (t && t->band_width > 0.0) ? t->band_width : 2.0;
     double rin;
     if (t && t->inner_radius > 0.0) rin = std::min(t->inner_radius, R);
     else rin = std::max(0.0, R - log(std::max(n, 2.0)) / a);
@@ -151,7 +151,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     int bb = 0;
     while ((1 << bb) < B) ++bb;
     L->band_bits = bb;
-    double target = (t && t->cell_target > 0) ? (double)t->cell_target : 8.0;
+    double target = (t && t->cell_target > 0) ? (double)t->cell_target : 1.0;
     double denom = p.cosh_aR_m1;
     int64_t base = 0;
     for (int j = 0; j < B; ++j) {
@@ -169,7 +169,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // Heavy queries: the innermost bands, holding about `heavy_points` points
     // in expectation (those with the largest degrees, about 5e3 and more at
     // n = 1e8).  The cap leaves room for the statistical excess.
-    const double hp = (t && t->heavy_points > 0) ? (double)t->heavy_points : 16384.0;
+    const double hp = (t && t->heavy_points > 0) ? (double)t->heavy_points : 65536.0;
     int jh = 0;
     while (jh < B && n * ((cosh(a * L->E[jh + 1]) - 1.0) / denom) <= hp) ++jh;
     if (jh >= B) jh = B - 1;

@@ -40,20 +40,28 @@ struct SearchArgs {
     float ep_lo[RHG_MAX_BANDS];       // e'(E[j]), m'(E[j]), s'(E[j])
     float em_lo[RHG_MAX_BANDS];
     float sh_lo[RHG_MAX_BANDS];
+    float rs_lo[RHG_MAX_BANDS];       // 1 / sqrt(s'(E[j])) (0 for E[j] = 0)
     int64_t dir_base[RHG_MAX_BANDS + 1];
     int cbits[RHG_MAX_BANDS];
     int B;
     int64_t n;
     int64_t heavy_cap;                // heavy queries at most
+    int64_t max_chunks;               // capacity of the heavy chunk table
+    int heavy_blocks;                 // workgroups striding over heavy chunks
     double R;
     double C, C_lo;                   // cosh R as double-double
     int use_p32;                      // FP32 screen valid (R small enough)
+    int band_bits;                    // top bits of a sort key holding the band
+    const uint32_t *keys;             // sorted keys: band, then the top angle bits
     const int32_t *band_start;
     const int32_t *dir;
     const double *sr, *st;
     const float4 *rec;                // (e', m', s', id bits)
     const int32_t *heavy_end;         // first light position
-    int32_t *heavy_cnt;               // per (heavy query, band): count, then offset
+    int64_t *hplan;                   // per heavy item: candidates, then chunks, then their prefix
+    int64_t *hcnt;                    // per heavy chunk: count, then its prefix
+    int32_t *hitem;                   // per heavy chunk: its item
+    int64_t *hscal;                   // [0] candidate total, [1] chunk size
     unsigned long long *stats;
 };
 
@@ -235,132 +243,155 @@ __device__ __forceinline__ int64_t uni64(int64_t v)
 }
 
 // ------------------------------------------------------------ heavy path
+//
+// Every (heavy query, band) pair is an item whose candidates form at most two
+// position runs (one window, possibly wrapping round 0 / 2 pi), or the whole
+// band when the band lies inside the query's circle.  A planning pass sizes
+// each item, then splits it into chunks of at most CH candidates (CH grows
+// only if the chunk table would overflow); chunks are numbered in (query,
+// band, chunk) order and a fixed pool of workgroups strides over them.  The
+// count pass records each chunk's count; their prefix sum places every
+// chunk's output inside its row in the emit pass.
 
-// One (heavy query, band) item per workgroup iteration.  Count pass: the
-// item's count goes to heavy_cnt; emit pass: heavy_cnt holds the item's
-// offset inside the row, and the workgroup writes its accepted candidates in
-// position order (block-wide ballot prefix).
-template <bool EMIT>
-__device__ void heavy_item(const SearchArgs &A, int64_t q, int j, const int64_t *row_ptr, int32_t *col)
+struct ItemRuns {
+    int64_t a0, b0, a1, b1;  // runs [a0, b0) and [a1, b1)
+    int inside;              // whole band, no tests
+    int full_poly;
+    double w;
+};
+
+__device__ __forceinline__ ItemRuns item_runs(const SearchArgs &A, int64_t q, int j)
 {
-    __shared__ int wave_cnt[4];
-    __shared__ int64_t running_sh;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t s = uni64(A.band_start[j]), e = uni64(A.band_start[j + 1]);
-    const double rq = A.sr[q], tq = A.st[q];
+    ItemRuns it;
+    it.a0 = it.b0 = it.a1 = it.b1 = 0;
+    it.inside = 0;
+    it.full_poly = 1;
+    it.w = 4.0;
+    const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+    if (s == e) return it;
+    if (band_inside(A, A.sr[q], j)) {
+        it.a0 = s; it.b0 = e; it.inside = 1;
+        return it;
+    }
     const float4 fq = A.rec[q];
-    const int32_t id = __float_as_int(fq.w);
-    int64_t out_base = 0, row_end = 0;
-    if (EMIT) {
-        out_base = row_ptr[id] + A.heavy_cnt[q * A.B + j];
-        row_end = row_ptr[id + 1];
-    }
-    int64_t total = 0;
-    if (s == e) {
-        if (!EMIT && threadIdx.x == 0) A.heavy_cnt[q * A.B + j] = 0;
-        return;
-    }
-    if (__builtin_amdgcn_readfirstlane((int)band_inside(A, rq, j))) {
-        const bool self_in = (q >= s && q < e);
-        if (EMIT) {
-            for (int64_t c = s + threadIdx.x; c < e; c += 256) {
-                if (c == q) continue;
-                const int64_t k = (self_in && c > q) ? c - s - 1 : c - s;
-                if (out_base + k < row_end) col[out_base + k] = __float_as_int(A.rec[c].w);
-            }
-        } else if (threadIdx.x == 0) {
-            A.heavy_cnt[q * A.B + j] = (int32_t)((e - s) - (self_in ? 1 : 0));
-        }
-        return;
-    }
+    const double tq = A.st[q];
     const double w = window_w(A, fq.x, fq.y, fq.z, j);
+    it.w = w;
     int64_t ra[2], rb[2];
     int nr;
     if (w >= 3.0) { ra[0] = s; rb[0] = e; nr = 1; }
     else nr = window_runs(A, j, tq - w, tq + w, s, e, ra, rb);
-    nr = __builtin_amdgcn_readfirstlane(nr);
-    const bool full_poly = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-    if (threadIdx.x == 0) running_sh = 0;
-    __syncthreads();
-    for (int k = 0; k < nr; ++k) {
-        const int64_t lo_k = uni64(ra[k]), hi_k = uni64(rb[k]);
-        for (int64_t base = lo_k; base < hi_k; base += 256) {
-            const int64_t c = base + threadIdx.x;
-            int acc = 0;
-            float4 fc = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < hi_k && c != q) {
-                fc = A.rec[c];
-                acc = decide(A, rq, tq, fq.x, fq.y, fq.z, c, A.st[c], fc.x, fc.y, fc.z, full_poly);
-            }
-            const uint64_t bal = __ballot(acc);
-            if (lane == 0) wave_cnt[wave] = __popcll(bal);
-            __syncthreads();
-            int before = 0, blk = 0;
-#pragma unroll
-            for (int w2 = 0; w2 < 4; ++w2) {
-                const int v = wave_cnt[w2];
-                if (w2 < wave) before += v;
-                blk += v;
-            }
-            if (EMIT && acc) {
-                const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-                const int64_t o = out_base + running_sh + before + __popcll(bal & lt);
-                if (o < row_end) col[o] = __float_as_int(fc.w);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) running_sh += blk;
-            total += blk;
-            __syncthreads();
+    it.a0 = ra[0]; it.b0 = rb[0];
+    if (nr == 2) { it.a1 = ra[1]; it.b1 = rb[1]; }
+    it.full_poly = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+    return it;
+}
+
+// Plan, step 1: candidates of every heavy item (0 past the heavy queries).
+__global__ void __launch_bounds__(256) heavy_plan_len(SearchArgs A)
+{
+    __shared__ long long part[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    long long len = 0;
+    if (i < A.heavy_cap * A.B) {
+        const int64_t q = i / A.B;
+        const int j = (int)(i % A.B);
+        if (q < *A.heavy_end) {
+            const ItemRuns it = item_runs(A, q, j);
+            len = (it.b0 - it.a0) + (it.b1 - it.a1);
         }
+        A.hplan[i] = len;
     }
-    if (!EMIT && threadIdx.x == 0) A.heavy_cnt[q * A.B + j] = (int32_t)total;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len += __shfl_xor(len, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = len;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd((unsigned long long *)&A.hscal[0], (unsigned long long)t);
+    }
+}
+
+// Plan, step 2: chunks per item, with CH chosen so the table cannot overflow.
+__global__ void __launch_bounds__(256) heavy_plan_chunks(SearchArgs A)
+{
+    const int64_t items = A.heavy_cap * A.B;
+    const int64_t room = A.max_chunks - items;  // > 0 by construction
+    const int64_t total = A.hscal[0];
+    int64_t ch = RHG_HEAVY_CHUNK;
+    if (total / ch >= room) ch = total / room + 1;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) A.hscal[1] = ch;
+    if (i < items) {
+        const int64_t len = A.hplan[i];
+        A.hplan[i] = len ? (len + ch - 1) / ch : 0;
+    }
+}
+
+template <bool EMIT>
+__device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
+{
+    __shared__ int wave_cnt[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t item = uni64(A.hitem[c]);  // the item holding chunk c
+    const int64_t first = item ? uni64(A.hplan[item - 1]) : 0;
+    const int64_t q = item / A.B;
+    const int j = (int)(item % A.B);
+    const int64_t ch = uni64(A.hscal[1]);
+    const ItemRuns it = item_runs(A, q, j);
+    const int64_t a0 = uni64(it.a0), b0 = uni64(it.b0), a1 = uni64(it.a1), b1 = uni64(it.b1);
+    const int inside = __builtin_amdgcn_readfirstlane(it.inside);
+    const bool full_poly = __builtin_amdgcn_readfirstlane(it.full_poly) != 0;
+    const int64_t len0 = b0 - a0, len = len0 + (b1 - a1);
+    const int64_t v0 = (c - first) * ch, v1 = min(len, v0 + ch);
+    const double rq = A.sr[q], tq = A.st[q];
+    const float4 fq = A.rec[q];
+    const int32_t id = __float_as_int(fq.w);
+    int64_t out = 0, row_end = 0;
+    if (EMIT) {
+        // output of this chunk = row start + counts of the row's earlier chunks
+        const int64_t qfirst = q ? uni64(A.hplan[q * A.B - 1]) : 0;
+        const int64_t base_c = c ? uni64(A.hcnt[c - 1]) : 0;
+        const int64_t base_q = qfirst ? uni64(A.hcnt[qfirst - 1]) : 0;
+        out = row_ptr[id] + (base_c - base_q);
+        row_end = row_ptr[id + 1];
+    }
+    int64_t total = 0;
+    for (int64_t vb = v0; vb < v1; vb += 256) {
+        const int64_t v = vb + threadIdx.x;
+        const int64_t pos = (v < len0) ? a0 + v : a1 + (v - len0);
+        int acc = 0;
+        int32_t cid = 0;
+        if (v < v1 && pos != q) {
+            const float4 fc = A.rec[pos];
+            cid = __float_as_int(fc.w);
+            acc = inside ? 1 : decide(A, rq, tq, fq.x, fq.y, fq.z, pos, A.st[pos], fc.x, fc.y, fc.z, full_poly);
+        }
+        const uint64_t bal = __ballot(acc);
+        if (lane == 0) wave_cnt[wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0, blk = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2) {
+            const int x = wave_cnt[w2];
+            if (w2 < wave) before += x;
+            blk += x;
+        }
+        __syncthreads();
+        if (EMIT && acc) {
+            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+            const int64_t o = out + total + before + __popcll(bal & lt);
+            if (o < row_end) col[o] = cid;
+        }
+        total += blk;
+    }
+    if (!EMIT && threadIdx.x == 0) A.hcnt[c] = total;
 }
 
 // ------------------------------------------------------------ light path
 
-// Test candidate runs [ra, rb) against the lane's query, every lane seeing
-// every candidate: each lane loads one candidate per 64-step, and the step
-// broadcasts them lane by lane through scalar registers.
-template <bool EMIT>
-__device__ __forceinline__ void shared_runs(const SearchArgs &A, int nr, const int64_t *ra, const int64_t *rb,
-                                            bool need, int64_t p, double rq, double tq, float4 fq, bool full_poly,
-                                            int64_t &cnt, int32_t *out, int64_t lim)
-{
-    const int lane = threadIdx.x & 63;
-    for (int k = 0; k < nr; ++k) {
-        for (int64_t base = ra[k]; base < rb[k]; base += 64) {
-            const int64_t c = base + lane;
-            double tcl = 0.0;
-            float4 fcl = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < rb[k]) {
-                tcl = A.st[c];
-                fcl = A.rec[c];
-            }
-            const int m = (int)min((int64_t)64, rb[k] - base);
-            const int tlo = __double2loint(tcl), thi = __double2hiint(tcl);
-            const int ex = __float_as_int(fcl.x), mx = __float_as_int(fcl.y), sx = __float_as_int(fcl.z);
-            const int idx = __float_as_int(fcl.w);
-            for (int t = 0; t < m; ++t) {
-                const double tc = __hiloint2double(__builtin_amdgcn_readlane(thi, t),
-                                                   __builtin_amdgcn_readlane(tlo, t));
-                const float ec = __int_as_float(__builtin_amdgcn_readlane(ex, t));
-                const float mc = __int_as_float(__builtin_amdgcn_readlane(mx, t));
-                const float sc = __int_as_float(__builtin_amdgcn_readlane(sx, t));
-                const int idt = EMIT ? __builtin_amdgcn_readlane(idx, t) : 0;
-                const int64_t ct = base + t;
-                if (need && ct != p) {
-                    if (decide(A, rq, tq, fq.x, fq.y, fq.z, ct, tc, ec, mc, sc, full_poly)) {
-                        if (EMIT && cnt < lim) out[cnt] = idt;
-                        ++cnt;
-                    }
-                }
-            }
-        }
-    }
-}
-
-// The lane's own window: candidates loaded by each lane from memory.
+// The lane's own window over band j's cells: candidates loaded by each lane
+// from memory (used when the wave's staged list would overflow).
 template <bool EMIT>
 __device__ __forceinline__ void lane_runs(const SearchArgs &A, int j, int64_t s, int64_t e, int64_t p, double rq,
                                           double tq, float4 fq, int64_t &cnt, int32_t *out, int64_t lim)
@@ -375,8 +406,13 @@ __device__ __forceinline__ void lane_runs(const SearchArgs &A, int j, int64_t s,
     for (int k = 0; k < nr; ++k) {
         for (int64_t c = ra[k]; c < rb[k]; ++c) {
             if (c == p) continue;
+            // boundary cells reach past the window; w bounds the band's
+            // angular reach with a relative pad far above the 2^-52 error of
+            // the angle, so points beyond it are not neighbours
+            const double tc = A.st[c];
+            if (short_angle(tq, tc) > w) continue;
             const float4 fc = A.rec[c];
-            if (decide(A, rq, tq, fq.x, fq.y, fq.z, c, A.st[c], fc.x, fc.y, fc.z, full_poly)) {
+            if (decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, full_poly)) {
                 if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
                 ++cnt;
             }
@@ -396,17 +432,98 @@ __device__ __forceinline__ double wave_max(double v)
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
+__device__ __forceinline__ int wave_excl_sum(int v, int lane, int *total)
+{
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
 
+// Largest j in [0, nb) with pre[j] <= g (pre ascending, pre[0] = 0).
+__device__ __forceinline__ int find_band(const int32_t *pre, int nb, int g)
+{
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// First index in [a, b) of the staged keys with key >= k.
+__device__ __forceinline__ int lds_lower_bound(const uint32_t *key, int a, int b, uint32_t k)
+{
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (key[mid] < k) a = mid + 1; else b = mid;
+    }
+    return a;
+}
+
+// Upper bound of band j's window for a query with normalised record
+// (e', m', s'): dropping the non-negative cosh(r_q - E[j]) / cosh R term
+// gives X <= 1 / (s'_q s'(E[j])), so sqrt X <= rs_q * rs_j with the reciprocal
+// square roots computed once per query and per band.  Above X = 1/4 it falls
+// back to window_w.
+__device__ __forceinline__ double window_fast(const SearchArgs &A, float rsq, float eq, float mq, float sq, int j)
+{
+    if (A.rs_lo[j] == 0.0f || A.E[j] < 0.25) return window_w(A, eq, mq, sq, j);
+    const float sx = rsq * A.rs_lo[j];
+    const float X = sx * sx;
+    if (!(X < 0.25f)) return window_w(A, eq, mq, sq, j);
+    return (double)(2.0f * sx * fmaf(X, 0.2f, 1.0f)) * (1.0 + 0x1p-12) + 0x1p-40;
+}
+
+// Lane l's value, as a wave-uniform scalar.
+__device__ __forceinline__ int64_t uni_lane64(int64_t v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double lane_double(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float lane_float(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+constexpr int STAGE = 384;  // staged candidates per wavefront
+
+struct WaveStage {
+    uint32_t key[STAGE];   // staged band key bits (the sort order inside a band)
+    double th[STAGE];      // staged angles
+};
+
+// Light queries: a wavefront of 64 consecutive sorted positions.  Lane j
+// first builds band j's entry of the wave's band table: the union of the
+// lanes' windows (the window of the innermost lane, stretched over the
+// lanes' angle range) as at most two position runs.  Bands whose lane
+// windows overlap ("shared") are tested exhaustively, every lane against
+// every candidate, their runs concatenated and read 64 at a time from LDS.
+// For the other bands the runs' keys and angles are staged in LDS and each
+// lane binary searches its own window, then tests what lies inside.
 template <bool EMIT>
 __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, int32_t *col)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ WaveStage stg[4];
+    __shared__ int32_t stage_pre[4][2][RHG_MAX_BANDS + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    WaveStage &S = stg[wv];
     const int64_t p = base + lane;
-    const int64_t hend = *A.heavy_end;
+    const int64_t hend = uni64(*A.heavy_end);
     const bool active = p < A.n && p >= hend;
     if (__ballot(active) == 0) return;
     double rq = 0.0, tq = 0.0;
-    float4 fq = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 fq = make_float4(0.f, 0.f, 0.f, 1.f);
     if (active) {
         rq = A.sr[p];
         tq = A.st[p];
@@ -419,6 +536,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         out = col + row_ptr[id];
         lim = row_ptr[id + 1] - row_ptr[id];
     }
+    const int B = A.B;
     // the innermost query of the wave has the widest windows
     const double rmin = wave_min(active ? rq : 1e300);
     const uint64_t is_min = __ballot(active && rq == rmin);
@@ -427,13 +545,16 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     const float mqm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fq.y), lmin));
     const float sqm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fq.z), lmin));
     const double tmin = wave_min(active ? tq : 1e300), tmax = wave_max(active ? tq : -1e300);
+    const double span = tmax - tmin;
+
+    // bands lying wholly inside this lane's circle: taken without tests
+    uint64_t full = 0;
     int64_t cnt = 0;
-    for (int j = 0; j < A.B; ++j) {
-        const int64_t s = A.band_start[j], e = A.band_start[j + 1];
-        if (s == e) continue;
-        const bool full = active && band_inside(A, rq, j);
-        if (full) {
-            const bool self_in = (p >= s && p < e);
+    if (active) {
+        for (int j = 0; j < B; ++j) {
+            const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+            if (s == e || !band_inside(A, rq, j)) continue;
+            full |= 1ull << j;
             if (EMIT) {
                 for (int64_t c = s; c < e; ++c) {
                     if (c == p) continue;
@@ -441,21 +562,224 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     ++cnt;
                 }
             } else {
-                cnt += (e - s) - (self_in ? 1 : 0);
+                cnt += (e - s) - ((p >= s && p < e) ? 1 : 0);
             }
         }
-        const bool need = active && !full;
-        if (__ballot(need) == 0) continue;
-        const double W = window_w(A, eqm, mqm, sqm, j);
-        if (W >= 3.0 || 2.0 * W >= tmax - tmin) {
-            int64_t ra[2], rb[2];
-            int nr;
-            if (W >= 3.0) { ra[0] = s; rb[0] = e; nr = 1; }
-            else nr = window_runs(A, j, tmin - W, tmax + W, s, e, ra, rb);
-            const bool full_poly = !(W + (tmax - tmin) + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-            shared_runs<EMIT>(A, nr, ra, rb, need, p, rq, tq, fq, full_poly, cnt, out, lim);
-        } else if (need) {
-            lane_runs<EMIT>(A, j, s, e, p, rq, tq, fq, cnt, out, lim);
+    }
+
+    // band table: lane j describes band j
+    int mode = 0;  // 0 nothing, 1 shared, 2 staged, 3 cooperative per query
+    int32_t a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    bool fpoly = true;
+    double W_band = 4.0;
+    if (lane < B) {
+        const int j = lane;
+        const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+        if (s < e) {
+            const double W = window_w(A, eqm, mqm, sqm, j);
+            W_band = W;
+            if (W >= 3.0) {
+                a0 = (int32_t)s; b0 = (int32_t)e;
+                mode = 1;
+            } else {
+                int64_t ra[2], rb[2];
+                const int nr = window_runs(A, j, tmin - W, tmax + W, s, e, ra, rb);
+                a0 = (int32_t)ra[0]; b0 = (int32_t)rb[0];
+                if (nr == 2) { a1 = (int32_t)ra[1]; b1 = (int32_t)rb[1]; }
+                mode = (2.0 * W >= span) ? 1 : 2;
+                fpoly = !(W + span + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+            }
+        }
+    }
+    // a band every active lane takes whole needs no tests
+    {
+        uint64_t f = active ? full : ~0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) f &= (uint64_t)__shfl_xor((long long)f, o, 64);
+        if (lane < B && ((f >> lane) & 1ull)) mode = 0;
+    }
+    const int U = (b0 - a0) + (b1 - a1);
+    if (U == 0) mode = 0;
+    // per-lane windows: a lane's window holds about U 2W / (span + 2W)
+    // candidates; large windows go to the cooperative mode (the whole wave
+    // on one query at a time), small ones to the staged binary searches
+    if (mode == 2 && (double)U * (2.0 * W_band) >= 16.0 * (span + 2.0 * W_band)) mode = 3;
+    int tot2;
+    int off2 = wave_excl_sum(mode == 2 ? U : 0, lane, &tot2);
+    if (mode == 2 && off2 + U > STAGE) mode = 3;  // would overflow the stage
+    off2 = wave_excl_sum(mode == 2 ? U : 0, lane, &tot2);
+    int tot1;
+    const int off1 = wave_excl_sum(mode == 1 ? U : 0, lane, &tot1);
+    if (lane <= B) {
+        stage_pre[wv][0][lane] = lane < B ? off1 : tot1;
+        stage_pre[wv][1][lane] = lane < B ? off2 : tot2;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // shared bands: every lane tests every candidate, 64 staged at a time
+    uint32_t *spos = S.key;                         // position | band << 26 (n < 2^31, B <= 64)
+    float4 *srec = (float4 *)&S.th[64];             // records of the chunk
+    for (int g0 = 0; g0 < tot1; g0 += 64) {
+        const int g = g0 + lane;
+        const int bj = find_band(stage_pre[wv][0], B, g < tot1 ? g : tot1 - 1);
+        const int pa0 = __shfl(a0, bj, 64), pb0 = __shfl(b0, bj, 64), pa1 = __shfl(a1, bj, 64);
+        const int fpb = __shfl((int)fpoly, bj, 64);
+        if (g < tot1) {
+            const int o = g - stage_pre[wv][0][bj];
+            const int64_t pos = (o < pb0 - pa0) ? (int64_t)pa0 + o : (int64_t)pa1 + (o - (pb0 - pa0));
+            S.th[lane] = A.st[pos];
+            srec[lane] = A.rec[pos];
+            spos[lane] = (uint32_t)pos;
+            spos[64 + lane] = (uint32_t)bj | ((uint32_t)fpb << 8);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int m = min(64, tot1 - g0);
+        for (int t = 0; t < m; ++t) {
+            const double tc = S.th[t];
+            const float4 fc = srec[t];
+            const int64_t ct = spos[t];
+            const uint32_t meta = spos[64 + t];
+            const int bt = (int)(meta & 255u);
+            if (active && ct != p && !((full >> bt) & 1ull)) {
+                if (decide(A, rq, tq, fq.x, fq.y, fq.z, ct, tc, fc.x, fc.y, fc.z, (meta >> 8) != 0)) {
+                    if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
+                    ++cnt;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // staged bands: band keys and angles of the runs in LDS; the index is
+    // sorted by the top 32 - band_bits bits of the angle key inside a band,
+    // so those bits (not the full key) are searched
+    const int kshift = A.band_bits;
+    const uint32_t kmask = kshift ? ((1u << (32 - kshift)) - 1u) : 0xffffffffu;
+    // (the trip count is uniform: cross-lane reads from lanes that have left
+    // a loop would return garbage)
+    for (int g0 = 0; g0 < tot2; g0 += 64) {
+        const int g = g0 + lane;
+        const int bj = find_band(stage_pre[wv][1], B, g < tot2 ? g : tot2 - 1);
+        const int pa0 = __shfl(a0, bj, 64), pb0 = __shfl(b0, bj, 64), pa1 = __shfl(a1, bj, 64);
+        if (g < tot2) {
+            const int o = g - stage_pre[wv][1][bj];
+            const int64_t pos = (o < pb0 - pa0) ? (int64_t)pa0 + o : (int64_t)pa1 + (o - (pb0 - pa0));
+            S.key[g] = A.keys[pos] & kmask;
+            S.th[g] = A.st[pos];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t staged = __ballot(lane < B && mode == 2);
+    const uint64_t percell = __ballot(lane < B && mode == 3);
+    const float rsq = active && fq.z > 0.0f ? rsqrtf(fq.z) : 0.0f;
+    for (uint64_t mk = staged; mk; mk &= mk - 1) {
+        const int j = __ffsll((unsigned long long)mk) - 1;
+        const int ja0 = __builtin_amdgcn_readlane(a0, j), jb0 = __builtin_amdgcn_readlane(b0, j);
+        const int ja1 = __builtin_amdgcn_readlane(a1, j), jb1 = __builtin_amdgcn_readlane(b1, j);
+        const int seg0 = stage_pre[wv][1][j];
+        const int seg1 = seg0 + (jb0 - ja0);
+        const int seg2 = seg1 + (jb1 - ja1);
+        if (!active || ((full >> j) & 1ull)) continue;
+        const double w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
+        const bool fp = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+        const double lo = tq - w, hi = tq + w;
+        uint32_t k0[2], k1[2];
+        int nk;
+        if (hi - lo >= RHG_TWO_PI_D) {  // the whole band (disjoint ranges below need w < pi)
+            k0[0] = 0u; k1[0] = kmask;
+            nk = 1;
+        } else if (lo < 0.0) {
+            k0[0] = 0u; k1[0] = angle_key_s(hi) >> kshift;
+            k0[1] = angle_key_s(lo + RHG_TWO_PI_D) >> kshift; k1[1] = kmask;
+            nk = 2;
+        } else if (hi >= RHG_TWO_PI_D) {
+            k0[0] = 0u; k1[0] = angle_key_s(hi - RHG_TWO_PI_D) >> kshift;
+            k0[1] = angle_key_s(lo) >> kshift; k1[1] = kmask;
+            nk = 2;
+        } else {
+            k0[0] = angle_key_s(lo) >> kshift; k1[0] = angle_key_s(hi) >> kshift;
+            nk = 1;
+        }
+        for (int r = 0; r < nk; ++r) {
+            for (int sg = 0; sg < 2; ++sg) {
+                const int sa = sg ? seg1 : seg0, sb = sg ? seg2 : seg1;
+                if (sa == sb) continue;
+                const int64_t run0 = sg ? ja1 : ja0;
+                for (int i = lds_lower_bound(S.key, sa, sb, k0[r]); i < sb && S.key[i] <= k1[r]; ++i) {
+                    const double tc = S.th[i];
+                    // keys bucket angles: skip what lies past the window (w
+                    // carries a relative pad far above the angle's rounding,
+                    // so these are not neighbours)
+                    if (short_angle(tq, tc) > w) continue;
+                    const int64_t c = run0 + (i - sa);
+                    if (c == p) continue;
+                    const float4 fc = A.rec[c];
+                    if (decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp)) {
+                        if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    // large per-lane windows: each lane finds its own runs in band j, then
+    // the whole wave works through one lane's runs at a time, 64 consecutive
+    // candidates per step (coalesced loads; in the emit pass contiguous,
+    // ordered writes from a ballot prefix)
+    for (uint64_t mk = percell; mk; mk &= mk - 1) {
+        const int j = __ffsll((unsigned long long)mk) - 1;
+        const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+        int64_t ra[2] = {0, 0}, rb[2] = {0, 0};
+        double w = 0.0;
+        const bool mine = active && !((full >> j) & 1ull);
+        if (mine) {
+            w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
+            if (w >= 3.0) { ra[0] = s; rb[0] = e; }
+            else window_runs(A, j, tq - w, tq + w, s, e, ra, rb);
+        }
+        const int64_t len0 = rb[0] - ra[0], len = len0 + (rb[1] - ra[1]);
+        const bool fpl = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+        int32_t *outc = out + cnt;  // this lane's next output slot
+        for (uint64_t lm = __ballot(mine && len > 0); lm; lm &= lm - 1) {
+            const int l = __ffsll((unsigned long long)lm) - 1;
+            const int64_t la0 = uni_lane64(ra[0], l), lb0 = uni_lane64(rb[0], l), la1 = uni_lane64(ra[1], l);
+            const int64_t llen0 = lb0 - la0, llen = uni_lane64(len, l);
+            const int64_t lp = uni_lane64(p, l);
+            const double lr = lane_double(rq, l), lt = lane_double(tq, l), lw = lane_double(w, l);
+            const float le = lane_float(fq.x, l), lmq = lane_float(fq.y, l), ls = lane_float(fq.z, l);
+            const bool lfp = __builtin_amdgcn_readlane((int)fpl, l) != 0;
+            int32_t *lout = EMIT ? (int32_t *)uni_lane64((int64_t)outc, l) : nullptr;
+            const int64_t llim = EMIT ? uni_lane64(lim - cnt, l) : 0;
+            int64_t got = 0;
+            for (int64_t vb = 0; vb < llen; vb += 64) {
+                const int64_t v = vb + lane;
+                int acc = 0, cid = 0;
+                if (v < llen) {
+                    const int64_t c = (v < llen0) ? la0 + v : la1 + (v - llen0);
+                    const double tc = A.st[c];
+                    if (c != lp && !(short_angle(lt, tc) > lw)) {
+                        const float4 fc = A.rec[c];
+                        cid = __float_as_int(fc.w);
+                        acc = decide(A, lr, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp);
+                    }
+                }
+                const uint64_t bal = __ballot(acc);
+                if (EMIT && acc) {
+                    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+                    const int64_t o = got + __popcll(bal & lt_mask);
+                    if (o < llim) lout[o] = cid;
+                }
+                got += __popcll(bal);
+            }
+            if (lane == l) cnt += got;
         }
     }
     if (!active) return;
@@ -472,46 +796,55 @@ template <bool EMIT>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
                                                      int32_t *__restrict__ col_idx)
 {
-    // blocks [0, heavy_cap * B): one (heavy query, band) item each, in query
-    // order so the hubs start first; the rest: 256 light queries each
-    const int64_t nhb = A.heavy_cap * A.B;
-    if ((int64_t)blockIdx.x < nhb) {
-        const int64_t hend = uni64(*A.heavy_end);
-        const int64_t q = (int64_t)blockIdx.x / A.B;
-        if (q >= hend) return;
-        heavy_item<EMIT>(A, q, (int)((int64_t)blockIdx.x % A.B), row_ptr, col_idx);
+    // blocks [0, heavy_blocks): a pool striding over the heavy chunks in
+    // (query, band, chunk) order, hubs first; the rest: 256 light queries each
+    if ((int)blockIdx.x < A.heavy_blocks) {
+        const int64_t nch = A.heavy_cap > 0 ? uni64(A.hplan[A.heavy_cap * A.B - 1]) : 0;
+        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<EMIT>(A, c, row_ptr, col_idx);
         return;
     }
-    const int64_t base = ((int64_t)blockIdx.x - nhb) * 256 + (threadIdx.x & ~63);
+    const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
     light_wave<EMIT>(A, base, row_ptr, col_idx);
 }
 
 // Before the count pass: heavy_end = the first light position (the end of
-// the heavy bands, capped).
-__global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_t *row_ptr, int emit)
+// the heavy bands, capped); zero the plan's candidate total.
+__global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_t *row_ptr)
 {
     if (threadIdx.x == 0) {
-        if (!emit) {
-            int64_t h = jh > 0 ? (int64_t)A.band_start[jh] : 0;
-            if (h > A.heavy_cap) h = A.heavy_cap;
-            *heavy_end = (int32_t)h;
-            row_ptr[0] = 0;
-        }
+        int64_t h = jh > 0 ? (int64_t)A.band_start[jh] : 0;
+        if (h > A.heavy_cap) h = A.heavy_cap;
+        *heavy_end = (int32_t)h;
+        row_ptr[0] = 0;
+        A.hscal[0] = 0;
     }
 }
 
-// After the count pass: heavy row degrees and per-item offsets.
-__global__ void heavy_finalize(SearchArgs A, int64_t *__restrict__ row_ptr)
+// Chunk -> item table: after the scan, item i owns chunks
+// [hplan[i-1], hplan[i]).
+__global__ void __launch_bounds__(256) heavy_chunk_items(SearchArgs A)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.heavy_cap * A.B) return;
+    const int64_t b = i ? A.hplan[i - 1] : 0, e = A.hplan[i];
+    for (int64_t c = b; c < e; ++c) A.hitem[c] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(256) zero_i64(int64_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// After the count pass (and the scan of the chunk counts): heavy degrees.
+__global__ void __launch_bounds__(256) heavy_degrees(SearchArgs A, int64_t *__restrict__ row_ptr)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= *A.heavy_end) return;
-    int64_t run = 0;
-    for (int j = 0; j < A.B; ++j) {
-        const int32_t c = A.heavy_cnt[q * A.B + j];
-        A.heavy_cnt[q * A.B + j] = (int32_t)run;
-        run += c;
-    }
-    row_ptr[__float_as_int(A.rec[q].w) + 1] = run;
+    const int64_t f = q ? A.hplan[q * A.B - 1] : 0;   // first chunk of q
+    const int64_t l = A.hplan[q * A.B + A.B - 1];     // one past its last chunk
+    const int64_t hi = l ? A.hcnt[l - 1] : 0, lo = f ? A.hcnt[f - 1] : 0;
+    row_ptr[__float_as_int(A.rec[q].w) + 1] = hi - lo;
 }
 
 hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s)
@@ -529,11 +862,16 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         A.ep_lo[j] = (float)(exp(L.E[j]) * inv);
         A.em_lo[j] = (float)(exp(-L.E[j]) * inv);
         A.sh_lo[j] = (float)(sinh(L.E[j]) * sc);
+        A.rs_lo[j] = A.sh_lo[j] > 0.0f ? (float)(1.0 / sqrt((double)A.sh_lo[j])) * (1.0f + 0x1p-20f) : 0.0f;
         A.cbits[j] = L.cbits[j];
     }
     A.B = L.B;
+    A.band_bits = L.band_bits;
+    A.keys = idx->keys;
     A.n = idx->n;
     A.heavy_cap = idx->heavy_cap;
+    A.max_chunks = idx->max_chunks;
+    A.heavy_blocks = idx->heavy_cap > 0 ? RHG_HEAVY_BLOCKS : 0;
     A.R = p.R;
     A.C = p.cosh_R;
     A.C_lo = p.cosh_R_lo;
@@ -544,20 +882,41 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.st = idx->st;
     A.rec = idx->rec;
     A.heavy_end = idx->heavy_end;
-    A.heavy_cnt = idx->heavy_cnt;
+    A.hplan = idx->hplan;
+    A.hcnt = idx->hcnt;
+    A.hitem = idx->hitem;
+    A.hscal = idx->hscal;
     A.stats = idx->stats;
     const int64_t n = idx->n;
-    hipLaunchKernelGGL(search_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr, emit);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n <= 0) return e;
-    const int64_t blocks = idx->heavy_cap * L.B + (n + 255) / 256;
+    const int64_t items = idx->heavy_cap * L.B;
+    hipError_t e;
+    if (!emit) {
+        hipLaunchKernelGGL(search_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (n <= 0) return hipSuccess;
+        if (items > 0) {
+            const unsigned g = (unsigned)((items + 255) / 256);
+            hipLaunchKernelGGL(heavy_plan_len, dim3(g), dim3(256), 0, s, A);
+            hipLaunchKernelGGL(heavy_plan_chunks, dim3(g), dim3(256), 0, s, A);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = inclusive_scan_i64(idx->hplan, items, idx->tmp, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(heavy_chunk_items, dim3(g), dim3(256), 0, s, A);
+            hipLaunchKernelGGL(zero_i64, dim3((unsigned)((idx->max_chunks + 255) / 256)), dim3(256), 0, s, idx->hcnt,
+                               idx->max_chunks);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    } else if (n <= 0) {
+        return hipSuccess;
+    }
+    const int64_t blocks = A.heavy_blocks + (n + 255) / 256;
     if (emit)
         hipLaunchKernelGGL(search_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, A, row_ptr, col_idx);
     else
         hipLaunchKernelGGL(search_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, A, row_ptr, col_idx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (!emit && idx->heavy_cap > 0) {
-        hipLaunchKernelGGL(heavy_finalize, dim3((unsigned)((idx->heavy_cap + 255) / 256)), dim3(256), 0, s, A,
+    if (!emit && items > 0) {
+        if ((e = inclusive_scan_i64(idx->hcnt, idx->max_chunks, idx->tmp, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(heavy_degrees, dim3((unsigned)((idx->heavy_cap + 255) / 256)), dim3(256), 0, s, A,
                            row_ptr);
         e = hipGetLastError();
     }

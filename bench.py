@@ -29,6 +29,11 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "undirected edges/sec at n=1e8 on 1 MI355X (% HBM roofline); p50/p99 request latency"
 
 
+def _log(*a):
+    """Progress lines on stderr (stdout carries only the JSON line)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def _source_sha() -> str:
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1501_03545_amd", "csrc", "*"))):
@@ -104,6 +109,101 @@ def run_gpu(cfg, steps, warmup, tuning=None):
                 params=p)
 
 
+def run_batch(count, reps, tuned=True, n_streams=16):
+    """The batch workload: `count` uneven graphs as one captured launch
+    (autotuned per class when a tuning cache exists), against the plain
+    per-graph loop over the same graphs (one stream, default tuning,
+    preallocated buffers), and against rhg_generate per graph (allocation
+    and one 8-byte readback per graph).  Edges/s over the whole batch."""
+    import torch
+    import paper_1501_03545_amd as P
+    from paper_1501_03545_amd import autotune as A
+    from paper_1501_03545_amd import workloads as W
+
+    draws = W.batch_params(count=count)
+    plans = [P.rhg_plan(d["n"], d["avg_degree"], d["gamma"], d["seed"]) for d in draws]
+    tunings = [A.tuning_for(d["n"], d["avg_degree"], d["gamma"]) if tuned else None for d in draws]
+    bufs = [P.GraphBuffers(p, t) for p, t in zip(plans, tunings)]
+    batch = P.Batch(bufs, n_streams=n_streams)
+    stream = torch.cuda.current_stream()
+    batch.launch(stream)
+    torch.cuda.synchronize()
+    fixed = batch.fix_overflows()
+    torch.cuda.synchronize()
+    m = sum(int(b.row_ptr[-1].item()) for b in bufs) // 2
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_batch = timed(lambda: batch.launch(stream))
+    batch.destroy()
+    tuned_names = sorted({A.class_of(d["n"], d["avg_degree"], d["gamma"]) for d, t in zip(draws, tunings) if t})
+    del bufs, batch
+    torch.cuda.empty_cache()
+    # the plain loop: same library, one graph after another, default tuning
+    plain = [P.GraphBuffers(p, None) for p in plans]
+    flags = torch.zeros(count, dtype=torch.int32, device="cuda")
+
+    def loop():
+        for g, b in enumerate(plain):
+            P.rhg_generate_async(b.params, b.r, b.theta, b.ws, b.row_ptr, b.col, flags[g:g + 1], None, stream)
+
+    t_loop = timed(loop)
+    assert int(flags.sum().item()) == 0 or fixed, "plain loop overflowed"
+    m_loop = sum(int(b.row_ptr[-1].item()) for b in plain) // 2
+    del plain
+    torch.cuda.empty_cache()
+
+    def gen_loop():
+        for d in draws:
+            P.rhg_generate(d["n"], d["avg_degree"], d["gamma"], d["seed"], stream=stream)
+
+    t_gen = timed(gen_loop)
+    torch.cuda.empty_cache()
+    return {"workload": "%d graphs: n log-uniform in [1e3, 1e6], avg degree uniform in [4, 64], "
+                        "gamma uniform in [2.1, 3.5], seeds 0x5EED0000 + g" % count,
+            "graphs": count, "sum_n": sum(d["n"] for d in draws), "undirected_edges": m,
+            "edges_match_plain_loop": m == m_loop,
+            "batched": {"ms": t_batch * 1e3, "edges_per_s": m / t_batch, "streams": n_streams,
+                        "form": "one captured HIP graph launch", "tuned_classes": tuned_names},
+            "plain_loop": {"ms": t_loop * 1e3, "edges_per_s": m / t_loop,
+                           "form": "rhg_generate_async per graph, one stream, default tuning"},
+            "generate_loop": {"ms": t_gen * 1e3, "edges_per_s": m / t_gen,
+                              "form": "rhg_generate per graph (allocates, reads back 2m)"},
+            "speedup_vs_plain_loop": t_loop / t_batch, "overflow_refills": len(fixed), "reps": reps}
+
+
+def run_serve(duration_s, rate_hz=200.0, slots=16, budget=200e9, hold_s=1.0):
+    """The serving workload: Poisson arrivals, admission by memory budget and
+    free slot, results held on the device for hold_s."""
+    import torch
+    from paper_1501_03545_amd import autotune as A
+    from paper_1501_03545_amd import serve as S
+    from paper_1501_03545_amd import workloads as W
+
+    warm = S.GpuExecutor(slots=slots, tuning_fn=A.tuning_for)
+    S.Server(warm, slots=slots, budget_bytes=budget, hold_s=0.0).run(
+        W.serve_stream(duration_s=0.5, rate_hz=rate_hz, seed=99))
+    torch.cuda.synchronize()
+    stream = W.serve_stream(duration_s=duration_s, rate_hz=rate_hz, seed=5)
+    ex = S.GpuExecutor(slots=slots, tuning_fn=A.tuning_for)
+    srv = S.Server(ex, slots=slots, budget_bytes=budget, hold_s=hold_s)
+    st = srv.run(stream)
+    torch.cuda.synchronize()
+    offered = sum(p["n"] * p["avg_degree"] / 2 for _, p in stream) / duration_s
+    st.update({"workload": "Poisson arrivals at %g req/s for %g s: 98%% drawn like the batch, 2%% at "
+                           "n=1e7 avg degree 16 gamma 2.5" % (rate_hz, duration_s),
+               "budget_bytes": budget, "hold_s": hold_s, "offered_edges_per_s": offered,
+               "overflow_refills": ex.retries})
+    return st
+
+
 def cpu_baseline(cfg, params, m_edges, sample_pts):
     """Oracle pair-test rate on all pairs among the first `sample_pts`
     points of the same graph, scaled to the oracle's full job
@@ -133,8 +233,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="large", choices=["small", "medium", "large"])
-    ap.add_argument("--cpu-sample", type=int, default=60_000)
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=512, help="graphs in the batch workload (0: skip)")
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the serving run (0: skip)")
     ap.add_argument("--band-width", type=float, default=0.0)
     ap.add_argument("--cell-target", type=int, default=0)
     args = ap.parse_args()
@@ -147,7 +250,10 @@ def main():
     tuning = None
     if args.band_width or args.cell_target:
         tuning = {"band_width": args.band_width, "cell_target": args.cell_target}
+    _log("single graph", cfg)
     res = run_gpu(cfg, args.steps, args.warmup, tuning)
+    _log("single graph done: %.3f ms/step" % res["ms_per_step"])
+    params = res["params"]
     n = cfg["n"]
     m = res["nnz"] // 2
     sec = res["ms_per_step"] / 1000.0
@@ -185,8 +291,21 @@ def main():
         "pipeline_floor_frac": (56 * n + 8 * m) / sec / 1e9 / HBM_PEAK_GBS,
         "search_stats": res["stats"],
     }
+    if args.batch > 0:
+        import torch
+        del res
+        torch.cuda.empty_cache()
+        _log("batch of", args.batch)
+        out["batch"] = run_batch(args.batch, args.batch_reps)
+        _log("batch done: %.2f ms batched, %.2f ms plain loop" % (out["batch"]["batched"]["ms"],
+                                                                  out["batch"]["plain_loop"]["ms"]))
+    if args.serve_seconds > 0:
+        _log("serving for %g s" % args.serve_seconds)
+        out["serve"] = run_serve(args.serve_seconds)
+        _log("serve done: p50 %.2f ms p99 %.2f ms" % (out["serve"]["p50_ms"], out["serve"]["p99_ms"]))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, res["params"], m, min(args.cpu_sample, n))
+        _log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(cfg, params, m, min(args.cpu_sample, n))
     print(json.dumps(out), flush=True)
 
 

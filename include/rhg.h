@@ -88,7 +88,7 @@ typedef struct {
 typedef struct rhg_index rhg_index;  /* opaque, host-side handle */
 
 /* ------------------------------------------------------------------ */
-/* a1. Planning (host only, synchronous, no device work).              */
+/* Planning (host only, synchronous, no device work).                  */
 /* ------------------------------------------------------------------ */
 
 /* alpha = (gamma - 1)/2 (Sec. 2.1: gamma = 2 alpha + 1 with curvature 1).
@@ -108,7 +108,7 @@ rhg_status rhg_plan_radius(int64_t n, double alpha, double R, uint64_t seed,
                            rhg_params *out /* host */);
 
 /* ------------------------------------------------------------------ */
-/* a2. Sampling (Algorithm 1, angular and radial draws; Eq. (1)).      */
+/* Sampling (Algorithm 1, angular and radial draws; Eq. (1)).          */
 /* ------------------------------------------------------------------ */
 
 /* Writes n points: theta[i] = fl(TWO_PI_D * u_theta(i)) in [0, 2 pi) and
@@ -121,7 +121,7 @@ rhg_status rhg_sample_points(const rhg_params *p /* host */, double *r, double *
                              void *stream);
 
 /* ------------------------------------------------------------------ */
-/* a3. Index: the polar quadtree of Sec. 3.1 rebuilt as a flat array of */
+/* Index: the polar quadtree of Sec. 3.1 rebuilt as a flat array of     */
 /* radial bands, each sorted by angle, with an angular cell directory.  */
 /* ------------------------------------------------------------------ */
 
@@ -142,7 +142,7 @@ rhg_status rhg_build_index(const rhg_params *p /* host */, const double *r,
                            rhg_index **out /* host */, void *stream);
 
 /* ------------------------------------------------------------------ */
-/* a4 + a5. Count pass and scan (Algorithm 1, query loop, counting).    */
+/* Count pass and scan (Algorithm 1, query loop, counting).            */
 /* ------------------------------------------------------------------ */
 
 /* Runs the neighbour search without writing edges and writes the CSR row
@@ -151,7 +151,7 @@ rhg_status rhg_build_index(const rhg_params *p /* host */, const double *r,
 rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
 
 /* ------------------------------------------------------------------ */
-/* a6. Emit pass (Algorithm 1, "add (v, w) to E").                     */
+/* Emit pass (Algorithm 1, edge insertion for each query).             */
 /* ------------------------------------------------------------------ */
 
 /* Repeats the search and writes the neighbours of vertex i to
@@ -216,6 +216,47 @@ rhg_status rhg_phase_times(double *avg_ms /* host */, int64_t *count /* host */,
 
 /* Name of a phase index ("" if out of range). */
 const char *rhg_phase_name(int phase);
+
+/* ------------------------------------------------------------------ */
+/* Batches: many graphs, one launch.                                   */
+/* ------------------------------------------------------------------ */
+
+/* The whole pipeline of one graph (sample, index, count, scan, emit) into
+ * caller buffers, fully asynchronous on `stream`: no allocation, no host
+ * synchronisation, no memset, so it can be captured into a HIP graph.
+ * r, theta: n doubles; workspace: rhg_index_workspace_bytes(p, t) bytes;
+ * row_ptr: n + 1 int64; col_idx: col_capacity int32 slots.  *overflow
+ * (device int32) is set to 1 when 2m > col_capacity -- then row_ptr is
+ * valid but col_idx is left unwritten, and the caller can emit again into a
+ * buffer of row_ptr[n] slots -- and to 0 otherwise. */
+rhg_status rhg_generate_async(const rhg_params *p /* host */, const rhg_tuning *t /* host, may be NULL */,
+                              double *r, double *theta, void *workspace, size_t workspace_bytes,
+                              int64_t *row_ptr, int32_t *col_idx, int64_t col_capacity,
+                              int32_t *overflow, void *stream);
+
+typedef struct rhg_batch rhg_batch;  /* opaque, host-side handle */
+
+/* Captures rhg_generate_async for `count` graphs into one HIP graph (one
+ * submission for the whole batch).  The graphs are spread over n_streams
+ * capture streams (1..64), largest expected work first, so independent
+ * graphs run concurrently.  All arrays are host arrays of `count` entries
+ * (ts may be NULL; a zero field of ts[g] takes the default); the device
+ * buffers they point to must stay allocated while the batch exists;
+ * overflow: device, count int32 flags, flag g set on each launch to whether
+ * graph g's 2m exceeded col_capacity[g] (its emit then writes nothing).
+ * Errors: RHG_EINVAL for count < 1, a NULL array or any graph's invalid
+ * arguments (no batch is created, *out stays NULL); RHG_EDEVICE if capture
+ * or instantiation fails.  Creation allocates host objects and the
+ * executable graph; it launches no work. */
+rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *ts, double *const *r,
+                            double *const *theta, void *const *workspace, const size_t *workspace_bytes,
+                            int64_t *const *row_ptr, int32_t *const *col_idx, const int64_t *col_capacity,
+                            int32_t *overflow, int n_streams, rhg_batch **out /* host */);
+
+/* Launches the captured batch on `stream` (asynchronous; replayable). */
+rhg_status rhg_batch_launch(rhg_batch *b, void *stream);
+
+void rhg_batch_destroy(rhg_batch *b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *rhg_last_error(void);

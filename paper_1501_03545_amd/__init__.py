@@ -79,6 +79,11 @@ def load():
         "rhg_index_stats": (i32, [vp, P(rhg_stats), vp]),
         "rhg_index_free": (None, [vp]),
         "rhg_generate": (i32, [i64, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
+        "rhg_generate_async": (i32, [P(rhg_params), P(rhg_tuning), vp, vp, vp, C.c_size_t, vp, vp, i64, vp, vp]),
+        "rhg_batch_create": (i32, [i32, P(rhg_params), P(rhg_tuning), P(vp), P(vp), P(vp), P(C.c_size_t), P(vp),
+                                   P(vp), P(i64), vp, i32, P(vp)]),
+        "rhg_batch_launch": (i32, [vp, vp]),
+        "rhg_batch_destroy": (None, [vp]),
         "rhg_set_profiling": (i32, [i32]),
         "rhg_phase_times": (i32, [P(C.c_double), P(C.c_int64), i32]),
         "rhg_phase_name": (C.c_char_p, [i32]),
@@ -257,7 +262,101 @@ def rhg_generate(n: int, avg_degree: float, gamma: float, seed: int, tuning: Opt
                  r=view(out.r, torch.float64, n), theta=view(out.theta, torch.float64, n))
 
 
+def rhg_generate_async(p: rhg_params, r, theta, workspace, row_ptr, col_idx, overflow, tuning=None, stream=None):
+    """Whole pipeline into caller buffers; asynchronous and capturable."""
+    _check(load().rhg_generate_async(C.byref(p), _tuning(tuning), _ptr(r), _ptr(theta), _ptr(workspace),
+                                     workspace.numel(), _ptr(row_ptr), _ptr(col_idx), col_idx.numel(),
+                                     _ptr(overflow), _stream(stream)))
+
+
+def expected_col_capacity(p: rhg_params, slack: float = 1.3) -> int:
+    """int32 slots to reserve for col_idx before counting: 2m in expectation
+    (the target degree times n), with slack for the spread of the degree."""
+    k = p.avg_degree if p.avg_degree == p.avg_degree else 16.0
+    return int(p.n * k * slack) + 4096
+
+
+class GraphBuffers:
+    """Device buffers of one graph for rhg_generate_async / batches."""
+
+    def __init__(self, p: rhg_params, tuning=None, col_capacity=None, device="cuda"):
+        import torch
+        n = max(int(p.n), 1)
+        self.params = p
+        self.tuning = tuning
+        self.r = torch.empty(n, dtype=torch.float64, device=device)
+        self.theta = torch.empty(n, dtype=torch.float64, device=device)
+        self.ws = torch.empty(rhg_index_workspace_bytes(p, tuning), dtype=torch.uint8, device=device)
+        self.row_ptr = torch.empty(int(p.n) + 1, dtype=torch.int64, device=device)
+        cap = expected_col_capacity(p) if col_capacity is None else int(col_capacity)
+        self.col = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+
+    def graph(self) -> "Graph":
+        nnz = int(self.row_ptr[-1].item())
+        return Graph(params=self.params, row_ptr=self.row_ptr, col_idx=self.col[:nnz], r=self.r[:self.params.n],
+                     theta=self.theta[:self.params.n])
+
+
+class Batch:
+    """Many graphs captured into one HIP graph (rhg_batch_create); launch()
+    runs the whole batch as one submission."""
+
+    def __init__(self, bufs, n_streams: int = 16):
+        import torch
+        self.bufs = bufs
+        k = len(bufs)
+        self.overflow = torch.zeros(max(k, 1), dtype=torch.int32, device=bufs[0].r.device if k else "cuda")
+        ps = (rhg_params * k)(*[b.params for b in bufs])
+        tus = (rhg_tuning * k)()
+        for i, b in enumerate(bufs):
+            if b.tuning:
+                t = _tuning(b.tuning)._obj
+                tus[i] = t
+        arr = lambda vals, T: (T * k)(*vals)
+        # the captured graph holds raw pointers: keep every buffer it writes
+        # alive for the batch's lifetime, also after fix_overflows swaps col
+        self._keep = (ps, tus, [(b.r, b.theta, b.ws, b.row_ptr, b.col) for b in bufs])
+        self.capacity = [b.col.numel() for b in bufs]  # col_idx slots the graph was captured with
+        h = C.c_void_p()
+        _check(load().rhg_batch_create(
+            k, ps, tus, arr([b.r.data_ptr() for b in bufs], C.c_void_p),
+            arr([b.theta.data_ptr() for b in bufs], C.c_void_p), arr([b.ws.data_ptr() for b in bufs], C.c_void_p),
+            arr([b.ws.numel() for b in bufs], C.c_size_t), arr([b.row_ptr.data_ptr() for b in bufs], C.c_void_p),
+            arr([b.col.data_ptr() for b in bufs], C.c_void_p), arr([b.col.numel() for b in bufs], C.c_int64),
+            _ptr(self.overflow), n_streams, C.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(load().rhg_batch_launch(self.handle, _stream(stream)))
+
+    def fix_overflows(self, stream=None):
+        """Re-run, with exact capacity, any graph whose col_idx was too small
+        (its flag is set; its row_ptr is complete).  The graph keeps writing
+        the original buffer on later launches, so call this after each."""
+        import torch
+        torch.cuda.synchronize()
+        bad = torch.nonzero(self.overflow[:len(self.bufs)]).flatten().tolist()
+        for i in bad:
+            b = self.bufs[i]
+            b.col = torch.empty(int(b.row_ptr[-1].item()), dtype=torch.int32, device=b.r.device)
+            flag = torch.zeros(1, dtype=torch.int32, device=b.r.device)
+            rhg_generate_async(b.params, b.r, b.theta, b.ws, b.row_ptr, b.col, flag, tuning=b.tuning, stream=stream)
+        return bad
+
+    def destroy(self):
+        if self.handle:
+            load().rhg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 __all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_workspace_bytes",
            "rhg_build_index", "rhg_count_edges", "rhg_emit_edges", "rhg_index_stats", "rhg_generate",
-           "rhg_set_profiling", "rhg_phase_times", "RhgError", "Graph", "Index", "load", "version",
+           "rhg_set_profiling", "rhg_phase_times", "rhg_generate_async", "GraphBuffers", "Batch",
+           "expected_col_capacity", "RhgError", "Graph", "Index", "load", "version",
            "LIB_PATH", "PHASES"]

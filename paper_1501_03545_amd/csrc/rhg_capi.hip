@@ -3,9 +3,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <math.h>
+
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "rhg_internal.h"
 
@@ -85,7 +88,11 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.rec = take(N * 16);
     w.heavy_end = take(16);
     const int64_t items = L.heavy_cap * L.B;
-    w.max_chunks = items > 0 ? items + RHG_HEAVY_EXTRA_CHUNKS : 1;
+    // Each heavy query's windows cover at most the n points once, so the
+    // chunk count stays below items + heavy_cap * n / RHG_HEAVY_CHUNK + 1;
+    // past RHG_HEAVY_EXTRA_CHUNKS the planner widens the chunks instead.
+    const int64_t extra = std::min<int64_t>(RHG_HEAVY_EXTRA_CHUNKS, L.heavy_cap * (n / RHG_HEAVY_CHUNK + 1) + 1);
+    w.max_chunks = items > 0 ? items + extra : 1;
     w.hplan = take((size_t)(items > 0 ? items : 1) * 8);
     w.hcnt = take((size_t)w.max_chunks * 8);
     w.hitem = take((size_t)w.max_chunks * 4);
@@ -313,6 +320,130 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
 }
 
 void rhg_index_free(rhg_index *idx) { delete idx; }
+
+rhg_status rhg_generate_async(const rhg_params *p, const rhg_tuning *t, double *r, double *theta, void *workspace,
+                              size_t workspace_bytes, int64_t *row_ptr, int32_t *col_idx, int64_t col_capacity,
+                              int32_t *overflow, void *stream)
+{
+    g_last_error.clear();
+    rhg_status st = check_params(p, "rhg_generate_async");
+    if (st != RHG_OK) return st;
+    if (!row_ptr || !overflow || col_capacity < 0 || (col_capacity > 0 && !col_idx))
+        return fail(RHG_EINVAL, "rhg_generate_async: NULL buffer or negative capacity");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = rhg_sample_points(p, r, theta, stream)) != RHG_OK) return st;
+    rhg_index *idx = nullptr;
+    if ((st = rhg_build_index(p, r, theta, t, workspace, workspace_bytes, 0, &idx, stream)) != RHG_OK) return st;
+    if ((st = rhg_count_edges(idx, row_ptr, stream)) != RHG_OK) { rhg_index_free(idx); return st; }
+    {
+        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
+        const hipError_t e = launch_search(idx, row_ptr, col_idx, 1, s, col_capacity, overflow);
+        if (e != hipSuccess) { rhg_index_free(idx); return check_hip(e, "rhg_generate_async (emit)"); }
+    }
+    rhg_index_free(idx);  // the launches hold their arguments by value
+    return RHG_OK;
+}
+
+struct rhg_batch {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int count, streams;
+};
+
+rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *ts, double *const *r,
+                            double *const *theta, void *const *ws, const size_t *ws_bytes, int64_t *const *row_ptr,
+                            int32_t *const *col, const int64_t *col_cap, int32_t *overflow, int n_streams,
+                            rhg_batch **out)
+{
+    g_last_error.clear();
+    if (!out || !ps || !r || !theta || !ws || !ws_bytes || !row_ptr || !col || !col_cap || !overflow)
+        return fail(RHG_EINVAL, "rhg_batch_create: NULL argument");
+    if (count < 1) return fail(RHG_EINVAL, "rhg_batch_create: a batch holds at least one graph");
+    *out = nullptr;
+    if (n_streams < 1) n_streams = 1;
+    if (n_streams > 64) n_streams = 64;
+    // longest-processing-time-first assignment of graphs to capture streams,
+    // by expected work (points plus expected edges)
+    std::vector<int> order(count), owner(count);
+    std::vector<double> work(count), load(n_streams, 0.0);
+    for (int g = 0; g < count; ++g) {
+        order[g] = g;
+        const double k = std::isnan(ps[g].avg_degree) ? 10.0 : ps[g].avg_degree;
+        work[g] = (double)ps[g].n * (4.0 + k);
+    }
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    for (int g : order) {
+        int best = 0;
+        for (int k = 1; k < n_streams; ++k)
+            if (load[k] < load[best]) best = k;
+        owner[g] = best;
+        load[best] += work[g];
+    }
+    std::vector<hipStream_t> st(n_streams);
+    std::vector<hipEvent_t> ev(n_streams + 1);
+    hipStream_t origin;
+    RHG_HIP(hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
+    for (int k = 0; k < n_streams; ++k) RHG_HIP(hipStreamCreateWithFlags(&st[k], hipStreamNonBlocking));
+    for (int k = 0; k <= n_streams; ++k) RHG_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+    rhg_batch *b = new (std::nothrow) rhg_batch;
+    if (!b) return fail(RHG_ENOMEM, "rhg_batch_create: host allocation failed");
+    b->count = count;
+    b->streams = n_streams;
+    rhg_status status = RHG_OK;
+    const int prof = g_prof_on;
+    g_prof_on = 0;  // no event records inside the captured graph
+    hipError_t e = hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        hipEventRecord(ev[n_streams], origin);
+        for (int k = 0; k < n_streams; ++k) hipStreamWaitEvent(st[k], ev[n_streams], 0);
+        for (int g : order) {
+            if (status != RHG_OK) break;
+            status = rhg_generate_async(&ps[g], ts ? &ts[g] : nullptr, r[g], theta[g], ws[g], ws_bytes[g], row_ptr[g],
+                                        col[g], col_cap[g], overflow + g, st[owner[g]]);
+        }
+        for (int k = 0; k < n_streams; ++k) {
+            hipEventRecord(ev[k], st[k]);
+            hipStreamWaitEvent(origin, ev[k], 0);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(origin, &graph);
+        b->graph = graph;
+        if (status == RHG_OK && e2 != hipSuccess) status = check_hip(e2, "rhg_batch_create (capture)");
+        if (status == RHG_OK) {
+            const hipError_t e3 = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            if (e3 != hipSuccess) status = check_hip(e3, "rhg_batch_create (instantiate)");
+        }
+    } else {
+        status = check_hip(e, "rhg_batch_create (begin capture)");
+    }
+    g_prof_on = prof;
+    for (int k = 0; k <= n_streams; ++k) hipEventDestroy(ev[k]);
+    for (int k = 0; k < n_streams; ++k) hipStreamDestroy(st[k]);
+    hipStreamDestroy(origin);
+    if (status != RHG_OK) {
+        if (b->graph) hipGraphDestroy(b->graph);
+        delete b;
+        return status;
+    }
+    *out = b;
+    return RHG_OK;
+}
+
+rhg_status rhg_batch_launch(rhg_batch *b, void *stream)
+{
+    g_last_error.clear();
+    if (!b) return fail(RHG_EINVAL, "rhg_batch_launch: NULL batch");
+    RHG_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return RHG_OK;
+}
+
+void rhg_batch_destroy(rhg_batch *b)
+{
+    if (!b) return;
+    hipGraphExecDestroy(b->exec);
+    hipGraphDestroy(b->graph);
+    delete b;
+}
 
 rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t seed, const rhg_tuning *t,
                         rhg_alloc_fn alloc, void *alloc_ctx, int canonical_rows, rhg_csr *out, void *stream)

@@ -104,7 +104,7 @@ hipError_t inclusive_scan_i64(int64_t *x, int64_t n, void *tmp, hipStream_t s);
 
 hipError_t launch_build_index(rhg_index *idx, const double *r, const double *theta, uint32_t *k1,
                               uint32_t *v0, uint32_t *v1, int validate, hipStream_t s);
-hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit,
-                         hipStream_t s);
+hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
+                         int64_t col_cap = -1, int32_t *overflow = nullptr);
 
 }  // namespace rhg

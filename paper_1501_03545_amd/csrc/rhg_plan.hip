@@ -39,25 +39,58 @@ static bool above(double n, double alpha, double R, double target)
     return dd_cmp(kbar_eq22(n, alpha, R), dd_make(target)) > 0;
 }
 
+// Eq. (22) in plain binary64: only used to find the peak and to place a
+// narrow bracket around the crossing; every decision that fixes R is taken
+// by the double-double evaluation above.
+static double kbar_eq22_d(double n, double alpha, double R)
+{
+    const double pi = 3.141592653589793;
+    const double ia = 1.0 / alpha, xi = alpha / (alpha - 0.5);
+    const double inner = 0.25 * pi * ia * ia - (pi - 1.0) * ia + (pi - 2.0);
+    return (2.0 / pi) * xi * xi * n * (exp(-0.5 * R) + exp(-alpha * R) * (alpha * 0.5 * R * inner - 1.0));
+}
+
 // R = smallest binary64 on the decreasing branch of Eq. (22) whose value is
-// <= target.  The bracket starts at the maximum of Eq. (22) (golden-section
-// search) and ends at 2 ln n + 40; bisection runs down to adjacent doubles,
-// so the result depends only on where Eq. (22) crosses the target.
+// <= target.  The branch starts at the maximum of Eq. (22) (golden-section
+// search) and the search ends at 2 ln n + 40.  A binary64 bisection places
+// the crossing to a few ulps; the bracket is then widened until the
+// double-double predicate holds at its ends and bisected down to adjacent
+// doubles, so the result depends only on where Eq. (22) crosses the target.
 static rhg_status solve_radius(double n, double alpha, double target, double *R_out)
 {
-    double hi = 2.0 * log(n) + 40.0;
-    double a = 1e-6, b = hi;
+    const double top = 2.0 * log(n) + 40.0;
+    double a = 1e-6, b = top;
     const double g = 0.6180339887498949;
-    for (int it = 0; it < 200; ++it) {
-        double c = b - g * (b - a), d = a + g * (b - a);
-        if (dd_cmp(kbar_eq22(n, alpha, c), kbar_eq22(n, alpha, d)) > 0) b = d; else a = c;
+    for (int it = 0; it < 100 && b - a > 1e-12 * b; ++it) {
+        const double c = b - g * (b - a), d = a + g * (b - a);
+        if (kbar_eq22_d(n, alpha, c) > kbar_eq22_d(n, alpha, d)) b = d; else a = c;
     }
-    double lo = 0.5 * (a + b);
-    if (!above(n, alpha, lo, target))
+    const double peak = 0.5 * (a + b);
+    if (!above(n, alpha, peak, target))
         return fail(RHG_ENOROOT, "average degree exceeds the maximum of Eq. (22) for this n and gamma");
-    if (above(n, alpha, hi, target)) return fail(RHG_ENOROOT, "Eq. (22) bracket does not contain the target");
+    if (above(n, alpha, top, target)) return fail(RHG_ENOROOT, "Eq. (22) bracket does not contain the target");
+    double lo = peak, hi = top;
+    for (int it = 0; it < 200; ++it) {  // binary64 estimate of the crossing
+        const double mid = lo + 0.5 * (hi - lo);
+        if (mid <= lo || mid >= hi) break;
+        if (kbar_eq22_d(n, alpha, mid) > target) lo = mid; else hi = mid;
+    }
+    // widen [lo, hi] geometrically until the exact predicate brackets it
+    double step = 4.0 * (nextafter(hi, INFINITY) - hi);
+    double L = std::max(peak, lo - step), H = std::min(top, hi + step);
+    while (L > peak && !above(n, alpha, L, target)) {
+        step *= 8.0;
+        L = std::max(peak, lo - step);
+    }
+    step = 4.0 * (nextafter(hi, INFINITY) - hi);
+    while (H < top && above(n, alpha, H, target)) {
+        step *= 8.0;
+        H = std::min(top, hi + step);
+    }
+    lo = L;
+    hi = H;
     for (;;) {
-        double mid = lo + 0.5 * (hi - lo);
+        const double mid = lo + 0.5 * (hi - lo);
         if (mid <= lo || mid >= hi) break;
         if (above(n, alpha, mid, target)) lo = mid; else hi = mid;
     }

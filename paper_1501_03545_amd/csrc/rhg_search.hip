@@ -63,6 +63,8 @@ struct SearchArgs {
     int32_t *hitem;                   // per heavy chunk: its item
     int64_t *hscal;                   // [0] candidate total, [1] chunk size
     unsigned long long *stats;
+    int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
+    int32_t *overflow;                // emit pass: set to 1 when 2m > col_cap
 };
 
 constexpr float P32_ACC = 1.0f - 0x1p-18f;
@@ -796,6 +798,9 @@ template <bool EMIT>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
                                                      int32_t *__restrict__ col_idx)
 {
+    // emit pass into a buffer too small for the graph: write nothing (the
+    // prologue has raised the overflow flag)
+    if (EMIT && A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
     // blocks [0, heavy_blocks): a pool striding over the heavy chunks in
     // (query, band, chunk) order, hubs first; the rest: 256 light queries each
     if ((int)blockIdx.x < A.heavy_blocks) {
@@ -830,6 +835,12 @@ __global__ void __launch_bounds__(256) heavy_chunk_items(SearchArgs A)
     for (int64_t c = b; c < e; ++c) A.hitem[c] = (int32_t)i;
 }
 
+// Before the emit pass: flag a col_idx buffer smaller than the graph.
+__global__ void emit_prologue(const int64_t *row_ptr, int64_t n, int64_t cap, int32_t *overflow)
+{
+    if (threadIdx.x == 0 && overflow) *overflow = (cap >= 0 && row_ptr[n] > cap) ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(256) zero_i64(int64_t *p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -847,7 +858,8 @@ __global__ void __launch_bounds__(256) heavy_degrees(SearchArgs A, int64_t *__re
     row_ptr[__float_as_int(A.rec[q].w) + 1] = hi - lo;
 }
 
-hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s)
+hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
+                         int64_t col_cap, int32_t *overflow)
 {
     const Layout &L = idx->L;
     const rhg_params &p = idx->p;
@@ -887,6 +899,8 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.hitem = idx->hitem;
     A.hscal = idx->hscal;
     A.stats = idx->stats;
+    A.col_cap = col_cap;
+    A.overflow = overflow;
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
     hipError_t e;
@@ -905,8 +919,12 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
                                idx->max_chunks);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-    } else if (n <= 0) {
-        return hipSuccess;
+    } else {
+        if (overflow) {
+            hipLaunchKernelGGL(emit_prologue, dim3(1), dim3(64), 0, s, row_ptr, n, col_cap, overflow);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (n <= 0) return hipSuccess;
     }
     const int64_t blocks = A.heavy_blocks + (n + 255) / 256;
     if (emit)

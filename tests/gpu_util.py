@@ -59,3 +59,23 @@ def ulp_diff(a, b):
     ia = a.view(np.int64)
     ib = b.view(np.int64)
     return np.abs(ia - ib)
+
+
+def pipeline_compare(g, r_o, t_o, R, orp, ocol):
+    """GPU pipeline vs oracle pipeline: angles bit-exact, radii within ulps,
+    edges identical except pairs an ulp of radius can flip (none expected)."""
+    tg = g.theta.cpu().numpy()
+    rg = g.r.cpu().numpy()
+    assert np.array_equal(tg, t_o)
+    assert ulp_diff(rg, r_o).max() <= 4
+    rp = g.row_ptr.cpu().numpy()
+    col = g.col_idx.cpu().numpy()
+    check_simple_symmetric(rp, col)
+    n = rp.shape[0] - 1
+    a = set((np.repeat(np.arange(n), np.diff(rp)) * n + col).tolist())
+    b = set((np.repeat(np.arange(n), np.diff(orp)) * n + ocol).tolist())
+    diff = a ^ b
+    for key in list(diff)[:100]:
+        i, j = divmod(key, n)
+        assert near_threshold(r_o[i], t_o[i], r_o[j], t_o[j], R), (i, j)
+    return len(diff)

@@ -1,5 +1,5 @@
 """The C-ABI library on a host without a GPU: it loads, exports every entry
-point include/rhg.h declares, and its host-only planning (row a1) agrees with
+point include/rhg.h declares, and its host-only planning agrees with
 the oracle bit for bit.  No device work is launched here."""
 import ctypes as C
 import math

@@ -1,8 +1,8 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
 Edge sets are compared exactly (canonical rows), on the oracle's own points
-for the search (rows a3-a6) and on each side's own points for the whole
-pipeline (rows a1-a6)."""
+for the search (index, count, scan, emit) and on each side's own points for
+the whole pipeline (plan, sample and search)."""
 import math
 import sys
 
@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import paper_1501_03545_amd as P
-from gpu_util import canonical, check_simple_symmetric, near_threshold, run_search, ulp_diff
+from gpu_util import canonical, check_simple_symmetric, near_threshold, pipeline_compare, run_search, ulp_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -145,26 +145,6 @@ def test_invalid_points_and_capacity_are_reported():
     assert ei.value.status == P.RHG_ECAPACITY
 
 
-def _pipeline_compare(g, r_o, t_o, R, orp, ocol):
-    """GPU pipeline vs oracle pipeline: angles bit-exact, radii within ulps,
-    edges identical except pairs an ulp of radius can flip (none expected)."""
-    tg = g.theta.cpu().numpy()
-    rg = g.r.cpu().numpy()
-    assert np.array_equal(tg, t_o)
-    assert ulp_diff(rg, r_o).max() <= 4
-    rp = g.row_ptr.cpu().numpy()
-    col = g.col_idx.cpu().numpy()
-    check_simple_symmetric(rp, col)
-    n = rp.shape[0] - 1
-    a = set((np.repeat(np.arange(n), np.diff(rp)) * n + col).tolist())
-    b = set((np.repeat(np.arange(n), np.diff(orp)) * n + ocol).tolist())
-    diff = a ^ b
-    for key in list(diff)[:100]:
-        i, j = divmod(key, n)
-        assert near_threshold(r_o[i], t_o[i], r_o[j], t_o[j], R), (i, j)
-    return len(diff)
-
-
 def test_generate_pipeline_matches_oracle_c1():
     n, k, g_ = C1
     _say("generate C1")
@@ -172,7 +152,7 @@ def test_generate_pipeline_matches_oracle_c1():
     a, R, r_o, t_o, orp, ocol, st = O.generate(n, k, g_, 1)
     assert g.params.R == R and g.params.alpha == a
     assert st["ties"] == 0
-    mism = _pipeline_compare(g, r_o, t_o, R, orp, ocol)
+    mism = pipeline_compare(g, r_o, t_o, R, orp, ocol)
     _say("pipeline mismatched pairs", mism)
     assert mism == 0
 

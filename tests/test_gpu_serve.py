@@ -1,0 +1,76 @@
+"""Serving on the GPU: requests that overlap on the device give the same
+graph, bit for bit, as the same request generated alone; a short Poisson
+stream completes with sane latency statistics."""
+import sys
+
+import pytest
+
+import paper_1501_03545_amd as P
+from paper_1501_03545_amd import serve as S
+from paper_1501_03545_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _alone(d):
+    import torch
+    p = P.rhg_plan(d["n"], d["avg_degree"], d["gamma"], d["seed"])
+    b = P.GraphBuffers(p)
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.rhg_generate_async(p, b.r, b.theta, b.ws, b.row_ptr, b.col, flag)
+    torch.cuda.synchronize()
+    if int(flag.item()):
+        b.col = torch.empty(int(b.row_ptr[-1].item()), dtype=torch.int32, device="cuda")
+        P.rhg_generate_async(p, b.r, b.theta, b.ws, b.row_ptr, b.col, flag)
+        torch.cuda.synchronize()
+    return b
+
+
+def _same(a, b):
+    import torch
+    nnz = int(a.row_ptr[-1].item())
+    n = int(a.params.n)
+    return (torch.equal(a.row_ptr, b.row_ptr) and torch.equal(a.col[:nnz], b.col[:nnz])
+            and torch.equal(a.r[:n], b.r[:n]) and torch.equal(a.theta[:n], b.theta[:n]))
+
+
+def test_results_in_the_mix_equal_results_alone():
+    import torch
+    P.load()
+    # a burst of 48 requests, every slot busy, plus two large requests
+    draws = W.batch_params(count=46, seed=21)
+    draws.insert(5, dict(W.SERVE_LARGE, seed=77))
+    draws.insert(30, dict(n=2_000_000, avg_degree=16.0, gamma=2.5, seed=78))
+    stream = [(0.0005 * i, dict(d, seed=d["seed"])) for i, d in enumerate(draws)]
+    ex = S.GpuExecutor(slots=16)
+    srv = S.Server(ex, slots=16, budget_bytes=200e9, hold_s=10.0, keep=range(len(stream)))
+    st = srv.run(stream)
+    torch.cuda.synchronize()
+    _say("mix", st)
+    assert st["requests"] == len(stream) and st["rejected"] == 0
+    assert st["max_inflight"] >= 8, "requests did not overlap"
+    for rid, (_, d) in enumerate(stream):
+        assert _same(srv.kept[rid], _alone(d)), (rid, d)
+    srv.kept.clear()
+
+
+def test_poisson_stream_and_memory_budget():
+    import torch
+    stream = W.serve_stream(duration_s=2.0, rate_hz=200.0, seed=5)
+    ex = S.GpuExecutor(slots=16)
+    # a budget of 3 GB: the large request (about 1.7 GB) must wait for room
+    srv = S.Server(ex, slots=16, budget_bytes=3e9, hold_s=0.2, keep=[0, 1, 2])
+    st = srv.run(stream)
+    torch.cuda.synchronize()
+    _say("poisson", st)
+    assert st["requests"] + st["rejected"] == len(stream) and st["rejected"] == 0
+    assert st["max_reserved_bytes"] <= 3e9
+    assert 0 < st["p50_ms"] <= st["p99_ms"] < 2000
+    assert st["edges"] > 0
+    for rid in (0, 1, 2):
+        assert _same(srv.kept[rid], _alone(stream[rid][1]))

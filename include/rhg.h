@@ -75,7 +75,11 @@ typedef struct {
     double inner_radius;   /* radius below which all points share one band    */
     int32_t cell_target;   /* mean points per angular cell                    */
     int32_t heavy_points;  /* expected points searched one per workgroup      */
-    int32_t reserved[4];
+    int32_t no_stage;      /* 0: the count pass also stores each light query's
+                            * tested neighbours in the workspace and the emit
+                            * pass copies them (one search); nonzero: the emit
+                            * pass repeats the search (smaller workspace)     */
+    int32_t reserved[3];
 } rhg_tuning;
 
 /* Device-side diagnostics of the last count/emit pass over an index. */
@@ -83,6 +87,9 @@ typedef struct {
     int64_t fp32_undecided;  /* pairs the FP32 screen passed to FP64          */
     int64_t dd_fallbacks;    /* pairs FP64 passed to double-double            */
     int64_t ties;            /* pairs double-double could not separate        */
+    int64_t stage_fallbacks; /* wavefronts of 64 light queries whose stored
+                              * neighbours overflowed their slots; the emit
+                              * pass searched them again                      */
 } rhg_stats;
 
 typedef struct rhg_index rhg_index;  /* opaque, host-side handle */
@@ -145,23 +152,29 @@ rhg_status rhg_build_index(const rhg_params *p /* host */, const double *r,
 /* Count pass and scan (Algorithm 1, query loop, counting).            */
 /* ------------------------------------------------------------------ */
 
-/* Runs the neighbour search without writing edges and writes the CSR row
- * offsets: row_ptr[0] = 0, row_ptr[i + 1] - row_ptr[i] = deg(i) (device,
- * n + 1 int64).  row_ptr[n] = 2m.  Asynchronous. */
+/* Runs the neighbour search and writes the CSR row offsets: row_ptr[0] = 0,
+ * row_ptr[i + 1] - row_ptr[i] = deg(i) (device, n + 1 int64); row_ptr[n] =
+ * 2m.  Unless the tuning sets no_stage, the neighbours found by per-point
+ * tests are also stored in the index workspace, in slots sized by the
+ * expected degree at the point's radius, for rhg_emit_edges.  Asynchronous. */
 rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Emit pass (Algorithm 1, edge insertion for each query).             */
 /* ------------------------------------------------------------------ */
 
-/* Repeats the search and writes the neighbours of vertex i to
- * col_idx[row_ptr[i] .. row_ptr[i+1]) (device, int32).  row_ptr must be
- * the output of rhg_count_edges on the same index.  Each undirected edge
- * appears in both rows; there are no self-loops.  Rows are in search order
- * (deterministic for a given tuning) or, with canonical_rows != 0,
- * ascending.  col_capacity is the number of int32 slots in col_idx; the
- * call reads row_ptr[n] back (one synchronisation) and returns
- * RHG_ECAPACITY if it exceeds col_capacity. */
+/* Writes the neighbours of vertex i to col_idx[row_ptr[i] .. row_ptr[i+1])
+ * (device, int32): stored neighbours are copied, and the search is repeated
+ * for the heavy queries and for stored slots that overflowed (or for every
+ * query with no_stage).  row_ptr must be the output of rhg_count_edges on the
+ * same index, and the call must follow that count pass (it reads what the
+ * count pass stored).  Each undirected edge appears in both rows; there are
+ * no self-loops.  Rows are in search order, deterministic for a given
+ * tuning and the same with and without staging; canonical_rows must be 0
+ * (ascending rows are not provided by this library: RHG_EINVAL).
+ * col_capacity is the number of int32 slots in col_idx; the call reads
+ * row_ptr[n] back (one synchronisation) and returns RHG_ECAPACITY if it
+ * exceeds col_capacity. */
 rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx,
                           int64_t col_capacity, int canonical_rows, void *stream);
 
@@ -192,6 +205,7 @@ typedef struct {
 /* Plans, samples, indexes, counts, scans and emits one graph.  All device
  * memory (points, index workspace, CSR) comes from `alloc`; the only host
  * synchronisation is the 8-byte read of 2m before col_idx is allocated.
+ * canonical_rows must be 0, as for rhg_emit_edges.
  * Errors: those of rhg_plan, and RHG_ENOMEM if `alloc` returns NULL. */
 rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t seed,
                         const rhg_tuning *t /* host, may be NULL */,

@@ -36,11 +36,13 @@ class rhg_params(C.Structure):
 
 class rhg_tuning(C.Structure):
     _fields_ = [("band_width", C.c_double), ("inner_radius", C.c_double),
-                ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("no_stage", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class rhg_stats(C.Structure):
-    _fields_ = [("fp32_undecided", C.c_int64), ("dd_fallbacks", C.c_int64), ("ties", C.c_int64)]
+    _fields_ = [("fp32_undecided", C.c_int64), ("dd_fallbacks", C.c_int64), ("ties", C.c_int64),
+                ("stage_fallbacks", C.c_int64)]
 
 
 class rhg_csr(C.Structure):
@@ -122,6 +124,7 @@ def _tuning(t: Optional[dict]):
     tu.inner_radius = float(t.get("inner_radius", 0.0))
     tu.cell_target = int(t.get("cell_target", 0))
     tu.heavy_points = int(t.get("heavy_points", 0))
+    tu.no_stage = 1 if t.get("no_stage") else 0
     return C.byref(tu)
 
 
@@ -200,7 +203,8 @@ def rhg_emit_edges(idx: Index, row_ptr, col_idx, canonical_rows: bool = False, s
 def rhg_index_stats(idx: Index, stream=None) -> dict:
     st = rhg_stats()
     _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
-    return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties}
+    return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties,
+            "stage_fallbacks": st.stage_fallbacks}
 
 
 PHASES = ["sample", "keys+sort", "index", "gather", "count", "scan", "emit"]

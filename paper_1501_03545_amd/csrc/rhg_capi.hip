@@ -65,7 +65,8 @@ void phase_end(void *rec, hipStream_t s)
 }
 
 struct WsPlan {
-    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcnt, hitem, hscal, stats, tmp, total, tmp_bytes;
+    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcnt, hitem, hscal, lkap, woff, wflag, stage,
+        stats, tmp, total, tmp_bytes;
     int64_t max_chunks;
 };
 
@@ -97,10 +98,20 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.hcnt = take((size_t)w.max_chunks * 8);
     w.hitem = take((size_t)w.max_chunks * 4);
     w.hscal = take(64);
+    const int64_t nw = (int64_t)((N + 63) / 64);  // wavefronts of 64 sorted positions
+    w.lkap = w.woff = w.wflag = w.stage = 0;
+    size_t t5 = 0;
+    if (L.stage) {
+        w.lkap = take((size_t)(RHG_KAP_SUB * L.B + 1) * 4);
+        w.woff = take((size_t)(nw + 1) * 8);
+        w.wflag = take((size_t)nw * 4);
+        w.stage = take((size_t)L.stage_cap * 4);
+        t5 = scan_tmp_bytes(nw);
+    }
     w.stats = take(ST_COUNT * 8);
     size_t t1 = radix_sort_tmp_bytes(n), t2 = scan_tmp_bytes(n + 1);
     size_t t3 = scan_tmp_bytes(w.max_chunks), t4 = scan_tmp_bytes(items > 0 ? items : 1);
-    w.tmp_bytes = std::max(std::max(t1, t2), std::max(t3, t4));
+    w.tmp_bytes = std::max(std::max(std::max(t1, t2), std::max(t3, t4)), t5);
     w.tmp = take(w.tmp_bytes);
     w.total = off + 256;  // slack for aligning the base pointer
     return w;
@@ -233,6 +244,10 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->hscal = (int64_t *)(base + w.hscal);
     idx->heavy_cap = idx->L.heavy_cap;
     idx->max_chunks = w.max_chunks;
+    idx->lkap = idx->L.stage ? (float *)(base + w.lkap) : nullptr;
+    idx->woff = idx->L.stage ? (int64_t *)(base + w.woff) : nullptr;
+    idx->wflag = idx->L.stage ? (int32_t *)(base + w.wflag) : nullptr;
+    idx->stage = idx->L.stage ? (int32_t *)(base + w.stage) : nullptr;
     idx->stats = (unsigned long long *)(base + w.stats);
     idx->tmp = base + w.tmp;
     idx->tmp_bytes = w.tmp_bytes;
@@ -315,6 +330,7 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
     out->fp32_undecided = (int64_t)h[ST_FP32_UNDECIDED];
     out->dd_fallbacks = (int64_t)h[ST_DD];
     out->ties = (int64_t)h[ST_TIES];
+    out->stage_fallbacks = (int64_t)h[ST_STAGE_FALLBACK];
     if (h[ST_EMIT_MISMATCH]) return fail(RHG_EINTERNAL, "emit pass disagreed with the count pass");
     return RHG_OK;
 }

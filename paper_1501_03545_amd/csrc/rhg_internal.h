@@ -13,6 +13,7 @@
 #define RHG_HEAVY_CHUNK 8192      // candidates per heavy chunk (at least)
 #define RHG_HEAVY_BLOCKS 2048     // workgroups striding over the heavy chunks
 #define RHG_HEAVY_EXTRA_CHUNKS (1 << 20)
+#define RHG_KAP_SUB 4             // expected-degree table points per band
 
 namespace rhg {
 
@@ -41,7 +42,47 @@ struct Layout {
     int64_t dir_total;                // entries of the directory (all bands)
     int heavy_band;                   // bands [0, heavy_band) hold the heavy queries
     int64_t heavy_cap;                // at most this many heavy queries
+    int stage;                        // count pass stores tested neighbours
+    int64_t stage_cap;                // int32 slots of the neighbour store
 };
+
+// Expected degree of a point at radius r (threshold model): the other n - 1
+// points are within R when r' <= R - r, and otherwise with probability
+// theta_max(r, r') / pi, cos theta_max = (cosh r cosh r' - cosh R) /
+// (sinh r sinh r'), r' drawn from the radial density of Eq. (1).  Composite
+// 8-point Gauss-Legendre quadrature over 16 panels of [max(0, R - r), R].
+// Used only to size the neighbour store.
+RHG_HD double expected_degree(double n, double alpha, double R, double r)
+{
+    const double xg[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+    const double wg[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    const double den = cosh(alpha * R) - 1.0;
+    const double lo = fmax(0.0, R - r);
+    double tot = (cosh(alpha * lo) - 1.0) / den;
+    if (r > 0.0 && lo < R) {
+        const double cR = cosh(R), chr = cosh(r), shr = sinh(r);
+        const int P = 16;
+        const double h = (R - lo) / P;
+        for (int k = 0; k < P; ++k) {
+            const double mid = lo + (k + 0.5) * h;
+            for (int g = 0; g < 8; ++g) {
+                const double x = mid + ((g & 1) ? 0.5 : -0.5) * h * xg[g >> 1];
+                const double c = (chr * cosh(x) - cR) / (shr * sinh(x));
+                const double th = acos(fmin(1.0, fmax(-1.0, c)));
+                tot += 0.5 * h * wg[g >> 1] * (alpha * sinh(alpha * x) / den) * (th / 3.141592653589793);
+            }
+        }
+    }
+    return (n - 1.0) * fmin(1.0, tot);
+}
+
+// Neighbour-store slots of a light query whose expected degree is k: the
+// mean with a small relative and Poisson-scale margin (an overflowing slot
+// only sends its wavefront back to the search in the emit pass).
+RHG_HD int64_t stage_slots(double k)
+{
+    return (int64_t)ceil(1.03 * k + 3.0 * sqrt(k) + 6.0);
+}
 
 void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L);
 
@@ -60,7 +101,8 @@ struct PhaseScope {
 };
 
 // Device-side counters (one 64-bit word each).
-enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4, ST_COUNT = 8 };
+enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4,
+       ST_STAGE_FALLBACK = 5, ST_COUNT = 8 };
 
 }  // namespace rhg
 
@@ -82,6 +124,10 @@ struct rhg_index {
     int64_t *hscal;        // heavy plan scalars
     int64_t heavy_cap;
     int64_t max_chunks;
+    float *lkap;           // log expected degree at RHG_KAP_SUB points per band, and at R
+    int64_t *woff;         // per wavefront of 64 positions: prefix of its store slots
+    int32_t *wflag;        // per wavefront: 1 when a slot overflowed in the count pass
+    int32_t *stage;        // the neighbour store (stage_cap slots)
     unsigned long long *stats;  // ST_COUNT counters
     void *tmp;             // scratch for sort and scan
     size_t tmp_bytes;

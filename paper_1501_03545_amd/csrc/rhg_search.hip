@@ -65,7 +65,18 @@ struct SearchArgs {
     unsigned long long *stats;
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
     int32_t *overflow;                // emit pass: set to 1 when 2m > col_cap
+    // neighbour store (count pass writes, emit pass copies)
+    double alpha, nd;                 // alpha and n, for the expected-degree table
+    float *lkap;                      // log expected degree, RHG_KAP_SUB points per band and R
+    int64_t *woff;                    // per wavefront: first slot (prefix), then [nw] = total
+    int32_t *wflag;                   // per wavefront: 1 = slots overflowed, search again
+    int32_t *store;                   // the slots
+    int64_t store_cap;
 };
+
+// Passes of the search kernel: count, emit by searching again, count while
+// storing the tested neighbours, emit by copying the stored neighbours.
+enum { M_COUNT = 0, M_EMIT = 1, M_STAGE = 2, M_COPY = 3 };
 
 constexpr float P32_ACC = 1.0f - 0x1p-18f;
 constexpr float P32_REJ = 1.0f + 0x1p-18f;
@@ -392,36 +403,6 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
 
 // ------------------------------------------------------------ light path
 
-// The lane's own window over band j's cells: candidates loaded by each lane
-// from memory (used when the wave's staged list would overflow).
-template <bool EMIT>
-__device__ __forceinline__ void lane_runs(const SearchArgs &A, int j, int64_t s, int64_t e, int64_t p, double rq,
-                                          double tq, float4 fq, int64_t &cnt, int32_t *out, int64_t lim)
-{
-    const double w = window_w(A, fq.x, fq.y, fq.z, j);
-    int64_t ra[2], rb[2];
-    int nr;
-    if (w >= 3.0) { ra[0] = s; rb[0] = e; nr = 1; }
-    else nr = window_runs(A, j, tq - w, tq + w, s, e, ra, rb);
-    // candidates of the boundary cells lie up to one cell width outside
-    const bool full_poly = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-    for (int k = 0; k < nr; ++k) {
-        for (int64_t c = ra[k]; c < rb[k]; ++c) {
-            if (c == p) continue;
-            // boundary cells reach past the window; w bounds the band's
-            // angular reach with a relative pad far above the 2^-52 error of
-            // the angle, so points beyond it are not neighbours
-            const double tc = A.st[c];
-            if (short_angle(tq, tc) > w) continue;
-            const float4 fc = A.rec[c];
-            if (decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, full_poly)) {
-                if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
-                ++cnt;
-            }
-        }
-    }
-}
-
 __device__ __forceinline__ double wave_min(double v)
 {
 #pragma unroll
@@ -500,6 +481,32 @@ __device__ __forceinline__ float lane_float(float v, int l)
 
 constexpr int STAGE = 384;  // staged candidates per wavefront
 
+// Slots of the neighbour store for the light query at sorted position p:
+// its expected degree, interpolated (log-linear) in the table at
+// RHG_KAP_SUB points per band, with the margin of stage_slots.
+__device__ __forceinline__ int64_t slot_of(const SearchArgs &A, int64_t p)
+{
+    const int j = A.band_bits ? (int)(A.keys[p] >> (32 - A.band_bits)) : 0;
+    const double u = (A.sr[p] - A.E[j]) / (A.E[j + 1] - A.E[j]) * RHG_KAP_SUB;
+    const int sub = min(RHG_KAP_SUB - 1, max(0, (int)u));
+    const double t = fmin(1.0, fmax(0.0, u - sub));
+    const int i = j * RHG_KAP_SUB + sub;
+    const double lk = (double)A.lkap[i] + t * ((double)A.lkap[i + 1] - (double)A.lkap[i]);
+    return stage_slots(exp(lk));
+}
+
+__device__ __forceinline__ int64_t wave_excl_sum64(int64_t v, int lane, int64_t *total)
+{
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
 struct WaveStage {
     uint32_t key[STAGE];   // staged band key bits (the sort order inside a band)
     double th[STAGE];      // staged angles
@@ -513,9 +520,18 @@ struct WaveStage {
 // every candidate, their runs concatenated and read 64 at a time from LDS.
 // For the other bands the runs' keys and angles are staged in LDS and each
 // lane binary searches its own window, then tests what lies inside.
-template <bool EMIT>
+//
+// MODE M_COUNT counts; M_STAGE counts and writes the neighbours found by
+// tests into the lane's store slots (bands wholly inside the circle are only
+// counted: the emit pass copies them from the index); M_EMIT writes the
+// whole row into col_idx.  The row order is the same in all modes: the
+// inside bands in band order, then the tested neighbours in search order.
+template <int MODE>
 __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, int32_t *col)
 {
+    constexpr bool EMIT = MODE == M_EMIT;
+    constexpr bool STORE = MODE == M_STAGE;
+    constexpr bool WRITE = EMIT || STORE;
     __shared__ WaveStage stg[4];
     __shared__ int32_t stage_pre[4][2][RHG_MAX_BANDS + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -523,7 +539,10 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     const int64_t p = base + lane;
     const int64_t hend = uni64(*A.heavy_end);
     const bool active = p < A.n && p >= hend;
-    if (__ballot(active) == 0) return;
+    if (__ballot(active) == 0) {
+        if (STORE && lane == 0 && base < A.n) A.wflag[base >> 6] = 0;
+        return;
+    }
     double rq = 0.0, tq = 0.0;
     float4 fq = make_float4(0.f, 0.f, 0.f, 1.f);
     if (active) {
@@ -532,8 +551,8 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         fq = A.rec[p];
     }
     const int32_t id = __float_as_int(fq.w);
-    int32_t *out = nullptr;
-    int64_t lim = 0;
+    int32_t *out = nullptr;  // entry k of the row goes to out[ob + k] while k < lim
+    int64_t ob = 0, lim = 0;
     if (EMIT && active) {
         out = col + row_ptr[id];
         lim = row_ptr[id + 1] - row_ptr[id];
@@ -567,6 +586,18 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 cnt += (e - s) - ((p >= s && p < e) ? 1 : 0);
             }
         }
+    }
+    bool store_ok = true;
+    if (STORE) {
+        // this lane's slots follow the wave's earlier lanes' slots
+        const int64_t slot = active ? slot_of(A, p) : 0;
+        int64_t wtot;
+        const int64_t excl = wave_excl_sum64(slot, lane, &wtot);
+        const int64_t w0 = uni64(A.woff[base >> 6]);
+        store_ok = w0 + wtot <= A.store_cap;
+        out = A.store;
+        ob = w0 + excl - cnt;  // tested neighbour k (k >= cnt) -> slot k - cnt
+        lim = store_ok ? cnt + slot : cnt;
     }
 
     // band table: lane j describes band j
@@ -648,7 +679,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             const int bt = (int)(meta & 255u);
             if (active && ct != p && !((full >> bt) & 1ull)) {
                 if (decide(A, rq, tq, fq.x, fq.y, fq.z, ct, tc, fc.x, fc.y, fc.z, (meta >> 8) != 0)) {
-                    if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
+                    if (WRITE && cnt < lim) out[ob + cnt] = __float_as_int(fc.w);
                     ++cnt;
                 }
             }
@@ -725,7 +756,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     if (c == p) continue;
                     const float4 fc = A.rec[c];
                     if (decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp)) {
-                        if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
+                        if (WRITE && cnt < lim) out[ob + cnt] = __float_as_int(fc.w);
                         ++cnt;
                     }
                 }
@@ -749,7 +780,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         }
         const int64_t len0 = rb[0] - ra[0], len = len0 + (rb[1] - ra[1]);
         const bool fpl = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-        int32_t *outc = out + cnt;  // this lane's next output slot
+        int32_t *outc = out + (ob + cnt);  // this lane's next output slot
         for (uint64_t lm = __ballot(mine && len > 0); lm; lm &= lm - 1) {
             const int l = __ffsll((unsigned long long)lm) - 1;
             const int64_t la0 = uni_lane64(ra[0], l), lb0 = uni_lane64(rb[0], l), la1 = uni_lane64(ra[1], l);
@@ -758,8 +789,8 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             const double lr = lane_double(rq, l), lt = lane_double(tq, l), lw = lane_double(w, l);
             const float le = lane_float(fq.x, l), lmq = lane_float(fq.y, l), ls = lane_float(fq.z, l);
             const bool lfp = __builtin_amdgcn_readlane((int)fpl, l) != 0;
-            int32_t *lout = EMIT ? (int32_t *)uni_lane64((int64_t)outc, l) : nullptr;
-            const int64_t llim = EMIT ? uni_lane64(lim - cnt, l) : 0;
+            int32_t *lout = WRITE ? (int32_t *)uni_lane64((int64_t)outc, l) : nullptr;
+            const int64_t llim = WRITE ? uni_lane64(lim - cnt, l) : 0;
             int64_t got = 0;
             for (int64_t vb = 0; vb < llen; vb += 64) {
                 const int64_t v = vb + lane;
@@ -774,7 +805,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     }
                 }
                 const uint64_t bal = __ballot(acc);
-                if (EMIT && acc) {
+                if (WRITE && acc) {
                     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
                     const int64_t o = got + __popcll(bal & lt_mask);
                     if (o < llim) lout[o] = cid;
@@ -782,6 +813,13 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 got += __popcll(bal);
             }
             if (lane == l) cnt += got;
+        }
+    }
+    if (STORE) {
+        const uint64_t over = __ballot(active && cnt > lim);
+        if (lane == 0) {
+            A.wflag[base >> 6] = over ? 1 : 0;
+            if (over) atomicAdd(&A.stats[ST_STAGE_FALLBACK], 1ull);
         }
     }
     if (!active) return;
@@ -792,12 +830,91 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     }
 }
 
+// Emit pass for a wavefront whose stored neighbours fit their slots: each
+// row is the inside bands (copied from the index, the query itself left
+// out) followed by the stored neighbours.
+__device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_ptr, int32_t *col)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t p = base + lane;
+    const int64_t hend = uni64(*A.heavy_end);
+    const bool active = p < A.n && p >= hend;
+    if (__ballot(active) == 0) return;
+    int64_t dst = 0, deg = 0, fullc = 0, slot = 0;
+    uint64_t full = 0;
+    if (active) {
+        const double rq = A.sr[p];
+        const int32_t id = __float_as_int(A.rec[p].w);
+        dst = row_ptr[id];
+        deg = row_ptr[id + 1] - dst;
+        for (int j = 0; j < A.B; ++j) {
+            const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+            if (s == e || !band_inside(A, rq, j)) continue;
+            full |= 1ull << j;
+            fullc += (e - s) - ((p >= s && p < e) ? 1 : 0);
+        }
+        slot = slot_of(A, p);
+    }
+    int64_t wtot;
+    const int64_t src = uni64(A.woff[base >> 6]) + wave_excl_sum64(slot, lane, &wtot);
+    // inside bands: the whole wave copies one row's bands at a time
+    for (uint64_t lm = __ballot(active && full != 0); lm; lm &= lm - 1) {
+        const int l = __ffsll((unsigned long long)lm) - 1;
+        const uint64_t lf = (uint64_t)uni_lane64((int64_t)full, l);
+        const int64_t lp = uni_lane64(p, l);
+        int64_t o = uni_lane64(dst, l);
+        for (uint64_t bm = lf; bm; bm &= bm - 1) {
+            const int j = __ffsll((unsigned long long)bm) - 1;
+            const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+            const bool self = lp >= s && lp < e;
+            for (int64_t c0 = s; c0 < e; c0 += 64) {
+                const int64_t c = c0 + lane;
+                if (c < e && c != lp) col[o + (c - s) - ((self && c > lp) ? 1 : 0)] = __float_as_int(A.rec[c].w);
+            }
+            o += (e - s) - (self ? 1 : 0);
+        }
+    }
+    // stored neighbours: entry t of the wave's concatenated stored parts
+    // belongs to the last lane whose prefix is <= t
+    const int64_t sc = active ? deg - fullc : 0;
+    int64_t T;
+    const int64_t pre = wave_excl_sum64(sc, lane, &T);
+    const int64_t at = dst + fullc;
+    constexpr int U = 4;  // entries per lane in flight
+    for (int64_t t0 = 0; t0 < T; t0 += 64 * U) {
+        int64_t from[U], to[U];
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t t = t0 + 64 * u + lane;
+            int l = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int64_t pv = __shfl(pre, l + step, 64);
+                if (t >= pv) l += step;
+            }
+            // every lane takes part in the shuffles (a lane reading from an
+            // inactive lane would get garbage); the range test comes after
+            const int64_t k = t - __shfl(pre, l, 64);
+            const int64_t so = __shfl(src, l, 64), dd = __shfl(at, l, 64);
+            from[u] = t < T ? so + k : -1;
+            to[u] = dd + k;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = from[u] >= 0 ? A.store[from[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (from[u] >= 0) col[to[u]] = v[u];
+    }
+}
+
 // ------------------------------------------------------------ kernels
 
-template <bool EMIT>
+template <int MODE>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
                                                      int32_t *__restrict__ col_idx)
 {
+    constexpr bool EMIT = MODE == M_EMIT || MODE == M_COPY;
     // emit pass into a buffer too small for the graph: write nothing (the
     // prologue has raised the overflow flag)
     if (EMIT && A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
@@ -809,7 +926,54 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs A, int64_t *__re
         return;
     }
     const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
-    light_wave<EMIT>(A, base, row_ptr, col_idx);
+    if (MODE == M_COPY) {
+        // copy_kernel handles the wavefronts whose stored neighbours fit
+        if (base < A.n && __builtin_amdgcn_readfirstlane(A.wflag[base >> 6]))
+            light_wave<M_EMIT>(A, base, row_ptr, col_idx);
+    } else {
+        light_wave<MODE == M_COPY ? M_EMIT : MODE>(A, base, row_ptr, col_idx);
+    }
+}
+
+// Emit pass with the neighbour store: copy the rows of every wavefront of
+// 64 light queries whose stored neighbours fit their slots.  Kept apart from
+// search_kernel so that its small register footprint gives full occupancy.
+__global__ void __launch_bounds__(256) copy_kernel(SearchArgs A, const int64_t *__restrict__ row_ptr,
+                                                   int32_t *__restrict__ col_idx)
+{
+    if (A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
+    const int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+    if (base >= A.n || __builtin_amdgcn_readfirstlane(A.wflag[base >> 6])) return;
+    copy_wave(A, base, row_ptr, col_idx);
+}
+
+// Expected-degree table of the neighbour store: log of the expected degree
+// at RHG_KAP_SUB equally spaced radii per band, and at R.
+__global__ void __launch_bounds__(64) store_table(SearchArgs A)
+{
+    const int i = (int)(blockIdx.x * 64 + threadIdx.x);
+    const int last = RHG_KAP_SUB * A.B;
+    if (i > last) return;
+    double r = A.R;
+    if (i < last) {
+        const int j = i / RHG_KAP_SUB, sub = i % RHG_KAP_SUB;
+        r = A.E[j] + (A.E[j + 1] - A.E[j]) * sub / RHG_KAP_SUB;
+    }
+    A.lkap[i] = (float)log(fmax(expected_degree(A.nd, A.alpha, A.R, r), 1e-3));
+}
+
+// Slots per wavefront of 64 sorted positions (light queries only); the
+// host scans woff[1..nw] into the wavefronts' first slots.
+__global__ void __launch_bounds__(256) store_plan(SearchArgs A, int64_t nw)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t hend = *A.heavy_end;
+    int64_t slot = (p < A.n && p >= hend) ? slot_of(A, p) : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) slot += __shfl_xor(slot, o, 64);
+    const int64_t w = p >> 6;
+    if ((threadIdx.x & 63) == 0 && w < nw) A.woff[w + 1] = slot;
+    if (p == 0) A.woff[0] = 0;
 }
 
 // Before the count pass: heavy_end = the first light position (the end of
@@ -901,6 +1065,15 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.stats = idx->stats;
     A.col_cap = col_cap;
     A.overflow = overflow;
+    A.alpha = p.alpha;
+    A.nd = (double)idx->n;
+    A.lkap = idx->lkap;
+    A.woff = idx->woff;
+    A.wflag = idx->wflag;
+    A.store = idx->stage;
+    A.store_cap = L.stage_cap;
+    const bool store = L.stage != 0;
+    const int64_t nw = (idx->n + 63) / 64;
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
     hipError_t e;
@@ -919,6 +1092,12 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
                                idx->max_chunks);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
+        if (store) {
+            hipLaunchKernelGGL(store_table, dim3((unsigned)((RHG_KAP_SUB * L.B + 1 + 63) / 64)), dim3(64), 0, s, A);
+            hipLaunchKernelGGL(store_plan, dim3((unsigned)((nw * 64 + 255) / 256)), dim3(256), 0, s, A, nw);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = inclusive_scan_i64(idx->woff + 1, nw, idx->tmp, s)) != hipSuccess) return e;
+        }
     } else {
         if (overflow) {
             hipLaunchKernelGGL(emit_prologue, dim3(1), dim3(64), 0, s, row_ptr, n, col_cap, overflow);
@@ -927,10 +1106,18 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         if (n <= 0) return hipSuccess;
     }
     const int64_t blocks = A.heavy_blocks + (n + 255) / 256;
-    if (emit)
-        hipLaunchKernelGGL(search_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, A, row_ptr, col_idx);
+    const dim3 g((unsigned)blocks), b(256);
+    if (emit && store) {
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), b, 0, s, A, row_ptr, col_idx);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(search_kernel<M_COPY>, g, b, 0, s, A, row_ptr, col_idx);
+    }
+    else if (emit)
+        hipLaunchKernelGGL(search_kernel<M_EMIT>, g, b, 0, s, A, row_ptr, col_idx);
+    else if (store)
+        hipLaunchKernelGGL(search_kernel<M_STAGE>, g, b, 0, s, A, row_ptr, col_idx);
     else
-        hipLaunchKernelGGL(search_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, A, row_ptr, col_idx);
+        hipLaunchKernelGGL(search_kernel<M_COUNT>, g, b, 0, s, A, row_ptr, col_idx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!emit && items > 0) {
         if ((e = inclusive_scan_i64(idx->hcnt, idx->max_chunks, idx->tmp, s)) != hipSuccess) return e;

@@ -87,6 +87,43 @@ def test_search_parity_independent_of_tuning():
         assert np.array_equal(canonical(rp, col), ocol)
 
 
+def test_stored_neighbours_give_the_rows_of_a_second_search():
+    """With the neighbour store the emit pass copies what the count pass
+    found; without it the emit pass searches again.  Both must give the same
+    rows, entry for entry, across tunings."""
+    n, k, g = 20_000, 12.0, 2.3
+    params, a, R = _params_for(n, k, g, 31)
+    r, t, _ = O.sample(31, a, R, n)
+    orp, ocol, _, _ = O.csr(r, t, R)
+    for tun in [{}, {"band_width": 1.0, "heavy_points": 2048}, {"band_width": 3.0, "cell_target": 4}]:
+        rp_s, col_s, st_s = run_search(P, params, r, t, tuning=dict(tun) or None)
+        rp_d, col_d, st_d = run_search(P, params, r, t, tuning=dict(tun, no_stage=1))
+        _say("store", tun, st_s)
+        assert st_s["stage_fallbacks"] == 0 and st_d["stage_fallbacks"] == 0
+        assert np.array_equal(rp_s, orp) and np.array_equal(rp_d, orp)
+        assert np.array_equal(col_s, col_d)
+        assert np.array_equal(canonical(rp_s, col_s), ocol)
+
+
+def test_store_overflow_falls_back_to_search():
+    """Points crowded into a narrow sector have far more neighbours than the
+    expected degree at their radius sizes the store for: the overflowing
+    wavefronts are searched again in the emit pass, with the same rows."""
+    n, k, g = 8_000, 8.0, 2.6
+    params, a, R = _params_for(n, k, g, 41)
+    r, t, _ = O.sample(41, a, R, n)
+    t = t.copy()
+    t[: n // 2] = t[: n // 2] * 1e-3  # half the points within 0.0063 rad
+    orp, ocol, _, nt = O.csr(r, t, R)
+    rp_s, col_s, st_s = run_search(P, params, r, t)
+    rp_d, col_d, _ = run_search(P, params, r, t, tuning={"no_stage": 1})
+    _say("crowded", st_s)
+    assert st_s["stage_fallbacks"] > 0
+    assert np.array_equal(rp_s, orp)
+    assert np.array_equal(col_s, col_d)
+    assert np.array_equal(canonical(rp_s, col_s), ocol)
+
+
 def test_search_degenerate_inputs():
     """Points at the origin, on the rim, sharing an angle, duplicated, and
     straddling the 0 / 2 pi seam."""

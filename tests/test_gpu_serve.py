@@ -63,13 +63,14 @@ def test_poisson_stream_and_memory_budget():
     import torch
     stream = W.serve_stream(duration_s=2.0, rate_hz=200.0, seed=5)
     ex = S.GpuExecutor(slots=16)
-    # a budget of 3 GB: the large request (about 1.7 GB) must wait for room
-    srv = S.Server(ex, slots=16, budget_bytes=3e9, hold_s=0.2, keep=[0, 1, 2])
+    # a budget of 8 GB: about three large requests (2.9 GB each with the
+    # neighbour store) fit beside the small ones
+    srv = S.Server(ex, slots=16, budget_bytes=8e9, hold_s=0.2, keep=[0, 1, 2])
     st = srv.run(stream)
     torch.cuda.synchronize()
     _say("poisson", st)
     assert st["requests"] + st["rejected"] == len(stream) and st["rejected"] == 0
-    assert st["max_reserved_bytes"] <= 3e9
+    assert st["max_reserved_bytes"] <= 8e9
     assert 0 < st["p50_ms"] <= st["p99_ms"] < 2000
     assert st["edges"] > 0
     for rid in (0, 1, 2):

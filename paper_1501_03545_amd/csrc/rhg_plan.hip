@@ -202,7 +202,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // Heavy queries: the innermost bands, holding about `heavy_points` points
     // in expectation (those with the largest degrees, about 5e3 and more at
     // n = 1e8).  The cap leaves room for the statistical excess.
-    const double hp = (t && t->heavy_points > 0) ? (double)t->heavy_points : 65536.0;
+    const double hp = (t && t->heavy_points > 0) ? (double)t->heavy_points : 16384.0;
     int jh = 0;
     while (jh < B && n * ((cosh(a * L->E[jh + 1]) - 1.0) / denom) <= hp) ++jh;
     if (jh >= B) jh = B - 1;

@@ -7,7 +7,10 @@
 // F(r) = (cosh(alpha r) - 1) / (cosh(alpha R) - 1) (Appendix C with the full
 // angular range): r = acosh(1 + u (cosh(alpha R) - 1)) / alpha, evaluated as
 // log1p(x + sqrt(x (x + 2))) / alpha with x = u (cosh(alpha R) - 1), which
-// keeps full relative accuracy for small u.
+// keeps full relative accuracy for small u.  The radius is evaluated in
+// double-double (about 104 bits) and rounded once, so it is the correctly
+// rounded binary64 value unless the exact radius lies within about 2^-100
+// (relative) of a rounding boundary.
 #include "rhg_internal.h"
 
 namespace rhg {
@@ -27,7 +30,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
 }
 
 __global__ void __launch_bounds__(256) sample_kernel(int64_t n, uint32_t k0, uint32_t k1, double alpha,
-                                                     double R, double c, double *__restrict__ r,
+                                                     double R, double c, double c_lo, double *__restrict__ r,
                                                      double *__restrict__ theta)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -39,9 +42,10 @@ __global__ void __launch_bounds__(256) sample_kernel(int64_t n, uint32_t k0, uin
         const double ut = (double)(a >> 11) * 0x1p-53;
         const double ur = (double)(b >> 11) * 0x1p-53;
         theta[i] = RHG_TWO_PI_D * ut;
-        const double x = ur * c;
-        const double ri = log1p(x + sqrt(x * (x + 2.0))) / alpha;
-        r[i] = fmin(ri, R);  // the exact value is <= R; keep rounding inside
+        const dd x = dd_mul_d(dd_make(c, c_lo), ur);
+        const dd y = dd_add(x, dd_sqrt(dd_mul(x, dd_add_d(x, 2.0))));
+        const dd ri = dd_div_d(dd_log1p(y), alpha);
+        r[i] = fmin(ri.hi, R);  // the exact value is <= R
     }
 }
 
@@ -51,7 +55,7 @@ hipError_t launch_sample(const rhg_params &p, double *r, double *theta, hipStrea
     int64_t blocks = (p.n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p.n, (uint32_t)p.seed,
-                       (uint32_t)(p.seed >> 32), p.alpha, p.R, p.cosh_aR_m1, r, theta);
+                       (uint32_t)(p.seed >> 32), p.alpha, p.R, p.cosh_aR_m1, p.cosh_aR_m1_lo, r, theta);
     return hipGetLastError();
 }
 

@@ -911,7 +911,7 @@ __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_
 // ------------------------------------------------------------ kernels
 
 template <int MODE>
-__global__ void __launch_bounds__(256) search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
                                                      int32_t *__restrict__ col_idx)
 {
     constexpr bool EMIT = MODE == M_EMIT || MODE == M_COPY;

@@ -2,7 +2,6 @@
 compare CSR graphs with the oracle's."""
 import numpy as np
 
-import mpmath as mp
 
 
 def run_search(P, params, r_np, t_np, tuning=None, validate=True):
@@ -44,15 +43,6 @@ def check_simple_symmetric(row_ptr, col):
     assert np.array_equal(fwd, bwd), "not symmetric"
 
 
-def near_threshold(r1, t1, r2, t2, R, rel=1e-12):
-    """True when cosh(d) of the two points is within `rel` of cosh(R), i.e.
-    an ulp-level change of a coordinate may legitimately flip the pair."""
-    mp.mp.dps = 60
-    r1, t1, r2, t2, R = (mp.mpf(float(x)) for x in (r1, t1, r2, t2, R))
-    L = mp.cosh(r1) * mp.cosh(r2) - mp.sinh(r1) * mp.sinh(r2) * mp.cos(t1 - t2)
-    return abs(L / mp.cosh(R) - 1) < rel
-
-
 def ulp_diff(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -62,20 +52,17 @@ def ulp_diff(a, b):
 
 
 def pipeline_compare(g, r_o, t_o, R, orp, ocol):
-    """GPU pipeline vs oracle pipeline: angles bit-exact, radii within ulps,
-    edges identical except pairs an ulp of radius can flip (none expected)."""
+    """GPU pipeline vs oracle pipeline: angles and radii bit for bit, then
+    the edge sets; returns the number of edges in one set only (pairs within
+    an ulp-scale change of the threshold are reported, not excused)."""
     tg = g.theta.cpu().numpy()
     rg = g.r.cpu().numpy()
     assert np.array_equal(tg, t_o)
-    assert ulp_diff(rg, r_o).max() <= 4
+    assert np.array_equal(rg, r_o), "radii differ: max %d ulp" % ulp_diff(rg, r_o).max()
     rp = g.row_ptr.cpu().numpy()
     col = g.col_idx.cpu().numpy()
     check_simple_symmetric(rp, col)
     n = rp.shape[0] - 1
     a = set((np.repeat(np.arange(n), np.diff(rp)) * n + col).tolist())
     b = set((np.repeat(np.arange(n), np.diff(orp)) * n + ocol).tolist())
-    diff = a ^ b
-    for key in list(diff)[:100]:
-        i, j = divmod(key, n)
-        assert near_threshold(r_o[i], t_o[i], r_o[j], t_o[j], R), (i, j)
-    return len(diff)
+    return len(a ^ b)

@@ -41,21 +41,21 @@ def _source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(phase: str, n: int, m: int) -> int:
-    """Minimum bytes a phase must move per launch (stated in the design doc)."""
-    if phase == "sample":
-        return 16 * n                      # write r, theta
-    if phase == "keys+sort":
-        return 16 * n + 8 * n              # read r, theta; write sorted key + id
-    if phase == "gather":
-        return 4 * n + 16 * n + 16 * n     # read ids, gather r, theta; write sorted r, theta
-    if phase == "count":
-        return 16 * n + 8 * n              # read r, theta once; write row_ptr
-    if phase == "scan":
-        return 16 * n                      # read + write row_ptr
-    if phase == "emit":
-        return 16 * n + 8 * n + 8 * m      # read r, theta and row_ptr; write 2m int32
-    return 0
+def algorithmic_bytes(phase: str, n: int, m: int, stored: int) -> int:
+    """Least bytes a phase has to move per launch (its inputs read once, its
+    outputs written once); `stored` is the number of neighbours the count
+    pass kept for the copy kernel."""
+    table = {
+        "sample": 16 * n,                     # write r, theta
+        "keys+sort": 16 * n + 8 * n,          # read r, theta; write sorted (key, id)
+        "index": 4 * n,                       # read sorted keys (band starts, cell directory)
+        "gather": 4 * n + 16 * n + 32 * n,    # read ids, gather r, theta; write sorted r, theta, record
+        "count": 16 * n + 8 * n + 4 * stored,  # read sorted r, theta; write row offsets, stored neighbours
+        "scan": 16 * n,                       # read + write row offsets
+        "copy": 8 * stored + 8 * n,           # read + write stored neighbours; read row offsets
+        "emit": 8 * (m * 2 - stored) // 2,    # write the rest of the rows (heavy, inside bands, fallbacks)
+    }
+    return int(table.get(phase, 0))
 
 
 def run_gpu(cfg, steps, warmup, tuning=None):
@@ -204,6 +204,25 @@ def run_serve(duration_s, rate_hz=200.0, slots=16, budget=200e9, hold_s=1.0):
     return st
 
 
+def copy_calibration(nbytes=4 << 30, reps=5):
+    """A plain device-to-device copy of known size: its event-timed rate is
+    the practical HBM ceiling, and under rocprofv3 --pmc its FETCH_SIZE and
+    WRITE_SIZE per dispatch calibrate those counters (nbytes each way)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"bytes_each_way": nbytes, "ms": ms, "GB_s": 2 * nbytes / (ms / 1000.0) / 1e9}
+
+
 def cpu_baseline(cfg, params, m_edges, sample_pts):
     """Oracle pair-test rate on all pairs among the first `sample_pts`
     points of the same graph, scaled to the oracle's full job
@@ -238,6 +257,7 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="graphs in the batch workload (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the serving run (0: skip)")
+    ap.add_argument("--calibrate", action="store_true", help="also time a 4 GiB device copy (HBM reference)")
     ap.add_argument("--band-width", type=float, default=0.0)
     ap.add_argument("--cell-target", type=int, default=0)
     args = ap.parse_args()
@@ -258,9 +278,10 @@ def main():
     m = res["nnz"] // 2
     sec = res["ms_per_step"] / 1000.0
     phases = res["phases"]
+    stored = int(res["stats"].get("stored", 0))
     dom = max(phases, key=lambda k: phases[k][0])
     dom_ms = phases[dom][0]
-    achieved = algorithmic_bytes(dom, n, m) / (dom_ms / 1000.0) / 1e9
+    achieved = algorithmic_bytes(dom, n, m, stored) / (dom_ms / 1000.0) / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (dom, args.config))
     if os.path.exists(tfile):
@@ -286,11 +307,13 @@ def main():
             "undirected_edges": m, "parallelism": "1 gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": algorithmic_bytes(dom, n, m), "avg_launch_ms": dom_ms},
-        "phases_ms": {k: round(v[0], 4) for k, v in phases.items()},
+                     "algorithmic_bytes": algorithmic_bytes(dom, n, m, stored), "avg_launch_ms": dom_ms},
+        "phases_ms": {k: round(v[0] * v[1] / args.steps, 4) for k, v in phases.items()},
         "pipeline_floor_frac": (56 * n + 8 * m) / sec / 1e9 / HBM_PEAK_GBS,
         "search_stats": res["stats"],
     }
+    if args.calibrate:
+        out["copy_calibration"] = copy_calibration()
     if args.batch > 0:
         import torch
         del res

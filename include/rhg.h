@@ -90,6 +90,8 @@ typedef struct {
     int64_t stage_fallbacks; /* wavefronts of 64 light queries whose stored
                               * neighbours overflowed their slots; the emit
                               * pass searched them again                      */
+    int64_t stored;          /* neighbours the count pass stored (copied by
+                              * the emit pass)                                */
 } rhg_stats;
 
 typedef struct rhg_index rhg_index;  /* opaque, host-side handle */
@@ -224,8 +226,12 @@ rhg_status rhg_set_profiling(int on);
 /* Average duration in ms and number of recorded launches of each phase
  * since profiling was last turned on (synchronises on the events).  Phases:
  * 0 sample, 1 keys+sort, 2 index (band starts + directory), 3 gather,
- * 4 count pass, 5 scan, 6 emit pass.  avg_ms, count: host arrays of at
- * least 7 entries (cap). */
+ * 4 plan (the small kernels around the searches: heavy-work plan, store
+ * slots, their scans, heavy degrees, capacity check), 5 count (the search
+ * kernel of the count pass), 6 scan (row offsets), 7 copy (the kernel
+ * copying stored neighbours), 8 emit (the search kernel of the emit pass).
+ * Each of 5, 7 and 8 brackets exactly one kernel launch.  avg_ms, count:
+ * host arrays of at least 9 entries (cap). */
 rhg_status rhg_phase_times(double *avg_ms /* host */, int64_t *count /* host */, int cap);
 
 /* Name of a phase index ("" if out of range). */

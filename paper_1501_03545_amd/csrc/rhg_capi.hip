@@ -38,8 +38,8 @@ __global__ void zero_u64_kernel(unsigned long long *p, int count)
 
 // ---- optional phase timing: HIP events recorded on the caller's stream
 // around each kernel group, kept in a ring and averaged on request.
-static const char *kPhaseNames[RHG_PHASE_COUNT] = {"sample", "keys+sort", "index", "gather", "count",
-                                                   "scan", "emit"};
+static const char *kPhaseNames[RHG_PHASE_COUNT] = {"sample", "keys+sort", "index", "gather", "plan",
+                                                   "count", "scan", "copy", "emit"};
 struct ProfRec {
     int phase;
     hipEvent_t a, b;
@@ -55,18 +55,18 @@ void *phase_begin(int phase, hipStream_t s)
     g_prof_next = (g_prof_next + 1) % kProfRing;
     if (g_prof_used < kProfRing) ++g_prof_used;
     rec->phase = phase;
-    hipEventRecord(rec->a, s);
+    (void)hipEventRecord(rec->a, s);
     return rec;
 }
 
 void phase_end(void *rec, hipStream_t s)
 {
-    if (rec) hipEventRecord(((ProfRec *)rec)->b, s);
+    if (rec) (void)hipEventRecord(((ProfRec *)rec)->b, s);
 }
 
 struct WsPlan {
     size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcnt, hitem, hscal, lkap, woff, wflag, stage,
-        stats, tmp, total, tmp_bytes;
+        stag, stats, tmp, total, tmp_bytes;
     int64_t max_chunks;
 };
 
@@ -99,13 +99,14 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.hitem = take((size_t)w.max_chunks * 4);
     w.hscal = take(64);
     const int64_t nw = (int64_t)((N + 63) / 64);  // wavefronts of 64 sorted positions
-    w.lkap = w.woff = w.wflag = w.stage = 0;
+    w.lkap = w.woff = w.wflag = w.stage = w.stag = 0;
     size_t t5 = 0;
     if (L.stage) {
         w.lkap = take((size_t)(RHG_KAP_SUB * L.B + 1) * 4);
         w.woff = take((size_t)(nw + 1) * 8);
         w.wflag = take((size_t)nw * 4);
         w.stage = take((size_t)L.stage_cap * 4);
+        w.stag = take((size_t)L.stage_cap);
         t5 = scan_tmp_bytes(nw);
     }
     w.stats = take(ST_COUNT * 8);
@@ -248,6 +249,7 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->woff = idx->L.stage ? (int64_t *)(base + w.woff) : nullptr;
     idx->wflag = idx->L.stage ? (int32_t *)(base + w.wflag) : nullptr;
     idx->stage = idx->L.stage ? (int32_t *)(base + w.stage) : nullptr;
+    idx->stag = idx->L.stage ? (uint8_t *)(base + w.stag) : nullptr;
     idx->stats = (unsigned long long *)(base + w.stats);
     idx->tmp = base + w.tmp;
     idx->tmp_bytes = w.tmp_bytes;
@@ -286,10 +288,7 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream)
     g_last_error.clear();
     if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_count_edges: NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    {
-        PhaseScope ps(RHG_PHASE_COUNT_PASS, s);
-        RHG_HIP(launch_search(idx, row_ptr, nullptr, 0, s));
-    }
+    RHG_HIP(launch_search(idx, row_ptr, nullptr, 0, s));
     if (idx->n > 0) {
         PhaseScope ps(RHG_PHASE_SCAN, s);
         RHG_HIP(inclusive_scan_i64(row_ptr + 1, idx->n, idx->tmp, s));
@@ -312,10 +311,7 @@ rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_i
         return fail(RHG_ECAPACITY, "rhg_emit_edges: col_idx holds " + std::to_string(col_capacity) +
                                        " entries, the graph needs " + std::to_string(nnz));
     if (nnz > 0 && !col_idx) return fail(RHG_EINVAL, "rhg_emit_edges: col_idx is NULL");
-    if (nnz > 0) {
-        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
-        RHG_HIP(launch_search(idx, (int64_t *)row_ptr, col_idx, 1, s));
-    }
+    if (nnz > 0) RHG_HIP(launch_search(idx, (int64_t *)row_ptr, col_idx, 1, s));
     return RHG_OK;
 }
 
@@ -331,6 +327,7 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
     out->dd_fallbacks = (int64_t)h[ST_DD];
     out->ties = (int64_t)h[ST_TIES];
     out->stage_fallbacks = (int64_t)h[ST_STAGE_FALLBACK];
+    out->stored = (int64_t)h[ST_STORED];
     if (h[ST_EMIT_MISMATCH]) return fail(RHG_EINTERNAL, "emit pass disagreed with the count pass");
     return RHG_OK;
 }
@@ -352,7 +349,6 @@ rhg_status rhg_generate_async(const rhg_params *p, const rhg_tuning *t, double *
     if ((st = rhg_build_index(p, r, theta, t, workspace, workspace_bytes, 0, &idx, stream)) != RHG_OK) return st;
     if ((st = rhg_count_edges(idx, row_ptr, stream)) != RHG_OK) { rhg_index_free(idx); return st; }
     {
-        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
         const hipError_t e = launch_search(idx, row_ptr, col_idx, 1, s, col_capacity, overflow);
         if (e != hipSuccess) { rhg_index_free(idx); return check_hip(e, "rhg_generate_async (emit)"); }
     }
@@ -410,16 +406,16 @@ rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *t
     g_prof_on = 0;  // no event records inside the captured graph
     hipError_t e = hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-        hipEventRecord(ev[n_streams], origin);
-        for (int k = 0; k < n_streams; ++k) hipStreamWaitEvent(st[k], ev[n_streams], 0);
+        (void)hipEventRecord(ev[n_streams], origin);
+        for (int k = 0; k < n_streams; ++k) (void)hipStreamWaitEvent(st[k], ev[n_streams], 0);
         for (int g : order) {
             if (status != RHG_OK) break;
             status = rhg_generate_async(&ps[g], ts ? &ts[g] : nullptr, r[g], theta[g], ws[g], ws_bytes[g], row_ptr[g],
                                         col[g], col_cap[g], overflow + g, st[owner[g]]);
         }
         for (int k = 0; k < n_streams; ++k) {
-            hipEventRecord(ev[k], st[k]);
-            hipStreamWaitEvent(origin, ev[k], 0);
+            (void)hipEventRecord(ev[k], st[k]);
+            (void)hipStreamWaitEvent(origin, ev[k], 0);
         }
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(origin, &graph);
@@ -433,11 +429,11 @@ rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *t
         status = check_hip(e, "rhg_batch_create (begin capture)");
     }
     g_prof_on = prof;
-    for (int k = 0; k <= n_streams; ++k) hipEventDestroy(ev[k]);
-    for (int k = 0; k < n_streams; ++k) hipStreamDestroy(st[k]);
-    hipStreamDestroy(origin);
+    for (int k = 0; k <= n_streams; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k < n_streams; ++k) (void)hipStreamDestroy(st[k]);
+    (void)hipStreamDestroy(origin);
     if (status != RHG_OK) {
-        if (b->graph) hipGraphDestroy(b->graph);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
         delete b;
         return status;
     }
@@ -456,8 +452,8 @@ rhg_status rhg_batch_launch(rhg_batch *b, void *stream)
 void rhg_batch_destroy(rhg_batch *b)
 {
     if (!b) return;
-    hipGraphExecDestroy(b->exec);
-    hipGraphDestroy(b->graph);
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
     delete b;
 }
 

@@ -176,27 +176,49 @@ RHG_HD dd dd_sin(dd x)
     return dd_mul(p, x);
 }
 
-// log(1 + y) for y >= 0: log z = 2 atanh(s), s = (z - 1)/(z + 1), with z
-// scaled by a power of two into [1/sqrt2, sqrt2) first when y is large.
+// 2 atanh(s) / s - 2 = 2 (s^2/3 + s^4/5 + ...), the first `terms` terms, in
+// double-double; the reciprocals 1/(2k+1) are correctly rounded hi/lo pairs.
+template <int TERMS>
+RHG_HD dd atanh_series(dd s)
+{
+    constexpr double inv_hi[24] = {
+        0x1.0000000000000p+0, 0x1.5555555555555p-2, 0x1.999999999999ap-3, 0x1.2492492492492p-3,
+        0x1.c71c71c71c71cp-4, 0x1.745d1745d1746p-4, 0x1.3b13b13b13b14p-4, 0x1.1111111111111p-4,
+        0x1.e1e1e1e1e1e1ep-5, 0x1.af286bca1af28p-5, 0x1.8618618618618p-5, 0x1.642c8590b2164p-5,
+        0x1.47ae147ae147bp-5, 0x1.2f684bda12f68p-5, 0x1.1a7b9611a7b96p-5, 0x1.0842108421084p-5,
+        0x1.f07c1f07c1f08p-6, 0x1.d41d41d41d41dp-6, 0x1.bacf914c1bad0p-6, 0x1.a41a41a41a41ap-6,
+        0x1.8f9c18f9c18fap-6, 0x1.7d05f417d05f4p-6, 0x1.6c16c16c16c17p-6, 0x1.5c9882b931057p-6};
+    constexpr double inv_lo[24] = {
+        0x0.0p+0, 0x1.5555555555555p-56, -0x1.999999999999ap-57, 0x1.2492492492492p-57,
+        0x1.c71c71c71c71cp-58, -0x1.745d1745d1746p-59, -0x1.3b13b13b13b14p-58, 0x1.1111111111111p-60,
+        0x1.e1e1e1e1e1e1ep-61, 0x1.af286bca1af28p-59, 0x1.8618618618618p-59, 0x1.642c8590b2164p-60,
+        -0x1.eb851eb851eb8p-61, 0x1.2f684bda12f68p-59, 0x1.1a7b9611a7b96p-61, 0x1.0842108421084p-60,
+        -0x1.f07c1f07c1f08p-61, 0x1.0750750750750p-60, -0x1.bacf914c1bad0p-60, 0x1.0690690690690p-60,
+        -0x1.f3831f3831f38p-61, 0x1.7d05f417d05f4p-62, -0x1.f49f49f49f49fp-61, 0x1.310572620ae4cp-61};
+    static_assert(TERMS >= 1 && TERMS <= 24, "series length");
+    const dd s2 = dd_mul(s, s);
+    dd p = dd_make(inv_hi[TERMS - 1], inv_lo[TERMS - 1]);
+#pragma unroll
+    for (int i = TERMS - 2; i >= 0; --i) p = dd_add(dd_mul(p, s2), dd_make(inv_hi[i], inv_lo[i]));
+    return dd_mul_pow2(dd_mul(p, s), 2.0);  // 2 atanh(s)
+}
+
+// log(1 + y) for y >= 0 as 2 atanh((z - 1)/(z + 1)), z = 1 + y.  For small y
+// the quotient y / (y + 2) keeps full relative accuracy (|s| <= 0.172, 24
+// terms).  Otherwise z is scaled by a power of two into [1/sqrt2, sqrt2)
+// and its eighth root is taken (three double-double square roots), so that
+// |s| <= 0.0217 and 11 terms reach the double-double precision.
 RHG_HD dd dd_log1p(dd y)
 {
-    dd s;
-    double k = 0.0;
-    if (y.hi <= 0.41421356237309503) {
-        s = dd_div(y, dd_add_d(y, 2.0));
-    } else {
-        dd z = dd_add_d(y, 1.0);
-        int e;
-        frexp(z.hi, &e);              // z.hi = f * 2^e, f in [1/2, 1)
-        dd m = dd_mul_pow2(z, ldexp(1.0, -e));
-        if (m.hi < 0.70710678118654757) { m = dd_mul_pow2(m, 2.0); e -= 1; }
-        k = (double)e;
-        s = dd_div(dd_add_d(m, -1.0), dd_add_d(m, 1.0));
-    }
-    dd s2 = dd_mul(s, s);
-    dd p = dd_make(1.0 / 47.0);
-    for (int j = 45; j >= 1; j -= 2) p = dd_add(dd_mul(p, s2), dd_div(dd_make(1.0), dd_make((double)j)));
-    dd r = dd_mul_pow2(dd_mul(p, s), 2.0);
+    if (y.hi <= 0.41421356237309503) return atanh_series<24>(dd_div(y, dd_add_d(y, 2.0)));
+    dd z = dd_add_d(y, 1.0);
+    int e;
+    frexp(z.hi, &e);  // z.hi = f * 2^e, f in [1/2, 1)
+    dd m = dd_mul_pow2(z, ldexp(1.0, -e));
+    if (m.hi < 0.70710678118654757) { m = dd_mul_pow2(m, 2.0); e -= 1; }
+    m = dd_sqrt(dd_sqrt(dd_sqrt(m)));
+    dd r = dd_mul_pow2(atanh_series<11>(dd_div(dd_add_d(m, -1.0), dd_add_d(m, 1.0))), 8.0);
+    const double k = (double)e;
     if (k != 0.0) {
         dd kl = two_prod(k, RHG_LN2_0);
         kl = dd_add(kl, two_prod(k, RHG_LN2_1));

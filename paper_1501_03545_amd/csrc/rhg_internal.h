@@ -76,19 +76,25 @@ RHG_HD double expected_degree(double n, double alpha, double R, double r)
     return (n - 1.0) * fmin(1.0, tot);
 }
 
-// Neighbour-store slots of a light query whose expected degree is k: the
-// mean with a small relative and Poisson-scale margin (an overflowing slot
-// only sends its wavefront back to the search in the emit pass).
+// Neighbour-store slots a light query adds to its wavefront's region when
+// its expected degree is k: the mean with a relative and a Poisson-scale
+// margin.  The 64 queries of a wavefront are neighbours in the index and
+// share most of their neighbourhoods, so their degrees rise and fall
+// together and pooling their slots does not shrink the relative spread: the
+// margin is sized per query (over 3 standard deviations).  A region that
+// still overflows only sends its wavefront back to the search in the emit
+// pass.
 RHG_HD int64_t stage_slots(double k)
 {
-    return (int64_t)ceil(1.03 * k + 3.0 * sqrt(k) + 6.0);
+    return (int64_t)ceil(1.03 * k + 3.0 * sqrt(k) + 4.0);
 }
 
 void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L);
 
 // Timed phases (rhg_phase_times).
 enum { RHG_PHASE_SAMPLE = 0, RHG_PHASE_SORT = 1, RHG_PHASE_INDEX = 2, RHG_PHASE_GATHER = 3,
-       RHG_PHASE_COUNT_PASS = 4, RHG_PHASE_SCAN = 5, RHG_PHASE_EMIT_PASS = 6, RHG_PHASE_COUNT = 7 };
+       RHG_PHASE_PLAN = 4, RHG_PHASE_COUNT_PASS = 5, RHG_PHASE_SCAN = 6, RHG_PHASE_COPY = 7,
+       RHG_PHASE_EMIT_PASS = 8, RHG_PHASE_COUNT = 9 };
 
 // Brackets a phase with HIP events on stream s when profiling is on.
 void *phase_begin(int phase, hipStream_t s);
@@ -97,12 +103,17 @@ struct PhaseScope {
     void *rec;
     hipStream_t s;
     PhaseScope(int phase, hipStream_t st) : rec(phase_begin(phase, st)), s(st) {}
-    ~PhaseScope() { phase_end(rec, s); }
+    void end()
+    {
+        phase_end(rec, s);
+        rec = nullptr;
+    }
+    ~PhaseScope() { end(); }
 };
 
 // Device-side counters (one 64-bit word each).
 enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4,
-       ST_STAGE_FALLBACK = 5, ST_COUNT = 8 };
+       ST_STAGE_FALLBACK = 5, ST_STORED = 6, ST_COUNT = 8 };
 
 }  // namespace rhg
 
@@ -128,6 +139,7 @@ struct rhg_index {
     int64_t *woff;         // per wavefront of 64 positions: prefix of its store slots
     int32_t *wflag;        // per wavefront: 1 when a slot overflowed in the count pass
     int32_t *stage;        // the neighbour store (stage_cap slots)
+    uint8_t *stag;         // the lane of each stored neighbour (stage_cap)
     unsigned long long *stats;  // ST_COUNT counters
     void *tmp;             // scratch for sort and scan
     size_t tmp_bytes;

@@ -70,7 +70,8 @@ struct SearchArgs {
     float *lkap;                      // log expected degree, RHG_KAP_SUB points per band and R
     int64_t *woff;                    // per wavefront: first slot (prefix), then [nw] = total
     int32_t *wflag;                   // per wavefront: 1 = slots overflowed, search again
-    int32_t *store;                   // the slots
+    int32_t *store;                   // the store: accepted neighbour ids
+    uint8_t *stag;                    // and the lane (query) of each
     int64_t store_cap;
 };
 
@@ -531,7 +532,6 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
 {
     constexpr bool EMIT = MODE == M_EMIT;
     constexpr bool STORE = MODE == M_STAGE;
-    constexpr bool WRITE = EMIT || STORE;
     __shared__ WaveStage stg[4];
     __shared__ int32_t stage_pre[4][2][RHG_MAX_BANDS + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -551,8 +551,8 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         fq = A.rec[p];
     }
     const int32_t id = __float_as_int(fq.w);
-    int32_t *out = nullptr;  // entry k of the row goes to out[ob + k] while k < lim
-    int64_t ob = 0, lim = 0;
+    int32_t *out = nullptr;  // EMIT: entry k of the row goes to out[k] while k < lim
+    int64_t lim = 0;
     if (EMIT && active) {
         out = col + row_ptr[id];
         lim = row_ptr[id + 1] - row_ptr[id];
@@ -587,18 +587,31 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             }
         }
     }
-    bool store_ok = true;
+    // STORE: the wave appends the neighbours its tests accept to its region
+    // [w0, w0 + wlim) of the store, in acceptance order, each with the lane
+    // of its query; one coalesced write per step.
+    int64_t w0 = 0, wlim = 0, fill = 0;
     if (STORE) {
-        // this lane's slots follow the wave's earlier lanes' slots
-        const int64_t slot = active ? slot_of(A, p) : 0;
-        int64_t wtot;
-        const int64_t excl = wave_excl_sum64(slot, lane, &wtot);
-        const int64_t w0 = uni64(A.woff[base >> 6]);
-        store_ok = w0 + wtot <= A.store_cap;
-        out = A.store;
-        ob = w0 + excl - cnt;  // tested neighbour k (k >= cnt) -> slot k - cnt
-        lim = store_ok ? cnt + slot : cnt;
+        long long slot = active ? (long long)slot_of(A, p) : 0ll;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) slot += __shfl_xor(slot, o, 64);
+        w0 = uni64(A.woff[base >> 6]);
+        wlim = (w0 + slot <= A.store_cap) ? uni64(slot) : 0;
     }
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    auto put = [&](int acc, int32_t cid, int tag) {
+        const uint64_t bal = __ballot(acc);
+        if (bal) {
+            if (acc) {
+                const int64_t pos = fill + __popcll(bal & lt_mask);
+                if (pos < wlim) {
+                    A.store[w0 + pos] = cid;
+                    A.stag[w0 + pos] = (uint8_t)tag;
+                }
+            }
+            fill += __popcll(bal);
+        }
+    };
 
     // band table: lane j describes band j
     int mode = 0;  // 0 nothing, 1 shared, 2 staged, 3 cooperative per query
@@ -677,12 +690,12 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             const int64_t ct = spos[t];
             const uint32_t meta = spos[64 + t];
             const int bt = (int)(meta & 255u);
-            if (active && ct != p && !((full >> bt) & 1ull)) {
-                if (decide(A, rq, tq, fq.x, fq.y, fq.z, ct, tc, fc.x, fc.y, fc.z, (meta >> 8) != 0)) {
-                    if (WRITE && cnt < lim) out[ob + cnt] = __float_as_int(fc.w);
-                    ++cnt;
-                }
-            }
+            int acc = 0;
+            if (active && ct != p && !((full >> bt) & 1ull))
+                acc = decide(A, rq, tq, fq.x, fq.y, fq.z, ct, tc, fc.x, fc.y, fc.z, (meta >> 8) != 0);
+            if (EMIT && acc && cnt < lim) out[cnt] = __float_as_int(fc.w);
+            if (STORE) put(acc, __float_as_int(fc.w), lane);
+            cnt += acc;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -720,45 +733,57 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         const int seg0 = stage_pre[wv][1][j];
         const int seg1 = seg0 + (jb0 - ja0);
         const int seg2 = seg1 + (jb1 - ja1);
-        if (!active || ((full >> j) & 1ull)) continue;
-        const double w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
-        const bool fp = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-        const double lo = tq - w, hi = tq + w;
-        uint32_t k0[2], k1[2];
-        int nk;
-        if (hi - lo >= RHG_TWO_PI_D) {  // the whole band (disjoint ranges below need w < pi)
-            k0[0] = 0u; k1[0] = kmask;
-            nk = 1;
-        } else if (lo < 0.0) {
-            k0[0] = 0u; k1[0] = angle_key_s(hi) >> kshift;
-            k0[1] = angle_key_s(lo + RHG_TWO_PI_D) >> kshift; k1[1] = kmask;
-            nk = 2;
-        } else if (hi >= RHG_TWO_PI_D) {
-            k0[0] = 0u; k1[0] = angle_key_s(hi - RHG_TWO_PI_D) >> kshift;
-            k0[1] = angle_key_s(lo) >> kshift; k1[1] = kmask;
-            nk = 2;
-        } else {
-            k0[0] = angle_key_s(lo) >> kshift; k1[0] = angle_key_s(hi) >> kshift;
-            nk = 1;
+        const bool me = active && !((full >> j) & 1ull);
+        double w = 0.0;
+        bool fp = true;
+        uint32_t k00 = 1u, k10 = 0u, k01 = 1u, k11 = 0u;  // key ranges [k0r, k1r]; empty by default
+        if (me) {
+            w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
+            fp = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+            const double lo = tq - w, hi = tq + w;
+            if (hi - lo >= RHG_TWO_PI_D) {  // the whole band (disjoint ranges below need w < pi)
+                k00 = 0u; k10 = kmask;
+            } else if (lo < 0.0) {
+                k00 = 0u; k10 = angle_key_s(hi) >> kshift;
+                k01 = angle_key_s(lo + RHG_TWO_PI_D) >> kshift; k11 = kmask;
+            } else if (hi >= RHG_TWO_PI_D) {
+                k00 = 0u; k10 = angle_key_s(hi - RHG_TWO_PI_D) >> kshift;
+                k01 = angle_key_s(lo) >> kshift; k11 = kmask;
+            } else {
+                k00 = angle_key_s(lo) >> kshift; k10 = angle_key_s(hi) >> kshift;
+            }
         }
-        for (int r = 0; r < nk; ++r) {
+        // every lane walks its key ranges inside both runs of the band; the
+        // loops run while any lane still has candidates, so the acceptances
+        // of a step can be appended together
+        for (int r = 0; r < 2; ++r) {
+            const uint32_t kb = r ? k01 : k00, ke = r ? k11 : k10;
             for (int sg = 0; sg < 2; ++sg) {
                 const int sa = sg ? seg1 : seg0, sb = sg ? seg2 : seg1;
                 if (sa == sb) continue;
                 const int64_t run0 = sg ? ja1 : ja0;
-                for (int i = lds_lower_bound(S.key, sa, sb, k0[r]); i < sb && S.key[i] <= k1[r]; ++i) {
-                    const double tc = S.th[i];
-                    // keys bucket angles: skip what lies past the window (w
-                    // carries a relative pad far above the angle's rounding,
-                    // so these are not neighbours)
-                    if (short_angle(tq, tc) > w) continue;
-                    const int64_t c = run0 + (i - sa);
-                    if (c == p) continue;
-                    const float4 fc = A.rec[c];
-                    if (decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp)) {
-                        if (WRITE && cnt < lim) out[ob + cnt] = __float_as_int(fc.w);
-                        ++cnt;
+                int i = (kb <= ke) ? lds_lower_bound(S.key, sa, sb, kb) : sb;
+                for (;;) {
+                    const bool live = i < sb && S.key[i] <= ke;
+                    if (__ballot(live) == 0) break;
+                    int acc = 0;
+                    int32_t cid = 0;
+                    if (live) {
+                        const double tc = S.th[i];
+                        const int64_t c = run0 + (i - sa);
+                        // keys bucket angles: skip what lies past the window
+                        // (w carries a relative pad far above the angle's
+                        // rounding, so these are not neighbours)
+                        if (c != p && !(short_angle(tq, tc) > w)) {
+                            const float4 fc = A.rec[c];
+                            cid = __float_as_int(fc.w);
+                            acc = decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp);
+                        }
+                        ++i;
                     }
+                    if (EMIT && acc && cnt < lim) out[cnt] = cid;
+                    if (STORE) put(acc, cid, lane);
+                    cnt += acc;
                 }
             }
         }
@@ -780,7 +805,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         }
         const int64_t len0 = rb[0] - ra[0], len = len0 + (rb[1] - ra[1]);
         const bool fpl = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-        int32_t *outc = out + (ob + cnt);  // this lane's next output slot
+        int32_t *outc = out + cnt;  // EMIT: this lane's next output slot
         for (uint64_t lm = __ballot(mine && len > 0); lm; lm &= lm - 1) {
             const int l = __ffsll((unsigned long long)lm) - 1;
             const int64_t la0 = uni_lane64(ra[0], l), lb0 = uni_lane64(rb[0], l), la1 = uni_lane64(ra[1], l);
@@ -789,8 +814,8 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             const double lr = lane_double(rq, l), lt = lane_double(tq, l), lw = lane_double(w, l);
             const float le = lane_float(fq.x, l), lmq = lane_float(fq.y, l), ls = lane_float(fq.z, l);
             const bool lfp = __builtin_amdgcn_readlane((int)fpl, l) != 0;
-            int32_t *lout = WRITE ? (int32_t *)uni_lane64((int64_t)outc, l) : nullptr;
-            const int64_t llim = WRITE ? uni_lane64(lim - cnt, l) : 0;
+            int32_t *lout = EMIT ? (int32_t *)uni_lane64((int64_t)outc, l) : nullptr;
+            const int64_t llim = EMIT ? uni_lane64(lim - cnt, l) : 0;
             int64_t got = 0;
             for (int64_t vb = 0; vb < llen; vb += 64) {
                 const int64_t v = vb + lane;
@@ -805,22 +830,21 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     }
                 }
                 const uint64_t bal = __ballot(acc);
-                if (WRITE && acc) {
-                    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+                if (EMIT && acc) {
                     const int64_t o = got + __popcll(bal & lt_mask);
                     if (o < llim) lout[o] = cid;
                 }
+                if (STORE) put(acc, cid, l);
                 got += __popcll(bal);
             }
             if (lane == l) cnt += got;
         }
     }
-    if (STORE) {
-        const uint64_t over = __ballot(active && cnt > lim);
-        if (lane == 0) {
-            A.wflag[base >> 6] = over ? 1 : 0;
-            if (over) atomicAdd(&A.stats[ST_STAGE_FALLBACK], 1ull);
-        }
+    if (STORE && lane == 0) {
+        const bool over = fill > wlim;
+        A.wflag[base >> 6] = over ? 1 : 0;
+        if (over) atomicAdd(&A.stats[ST_STAGE_FALLBACK], 1ull);
+        else if (fill) atomicAdd(&A.stats[ST_STORED], (unsigned long long)fill);
     }
     if (!active) return;
     if (EMIT) {
@@ -830,17 +854,38 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     }
 }
 
-// Emit pass for a wavefront whose stored neighbours fit their slots: each
+// Emit pass for a wavefront whose stored neighbours fit its region: each
 // row is the inside bands (copied from the index, the query itself left
-// out) followed by the stored neighbours.
+// out) followed by its lane's stored neighbours in acceptance order.  The
+// store holds the wave's acceptances interleaved across lanes; chunks of
+// COPY_CHUNK entries are sorted by lane in LDS (stably, so each lane keeps
+// its order) and each lane's part of a chunk is written as one run.
+constexpr int COPY_K = 8;                  // entries per lane per chunk
+constexpr int COPY_CHUNK = 64 * COPY_K;
+
+struct CopyStage {
+    int32_t id[COPY_CHUNK];
+    uint8_t tag[COPY_CHUNK];
+    int32_t cnt[64];
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_ptr, int32_t *col)
 {
+    __shared__ CopyStage stage[4];
     const int lane = threadIdx.x & 63;
+    CopyStage &C = stage[threadIdx.x >> 6];
     const int64_t p = base + lane;
     const int64_t hend = uni64(*A.heavy_end);
     const bool active = p < A.n && p >= hend;
     if (__ballot(active) == 0) return;
-    int64_t dst = 0, deg = 0, fullc = 0, slot = 0;
+    int64_t dst = 0, deg = 0, fullc = 0;
     uint64_t full = 0;
     if (active) {
         const double rq = A.sr[p];
@@ -853,10 +898,7 @@ __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_
             full |= 1ull << j;
             fullc += (e - s) - ((p >= s && p < e) ? 1 : 0);
         }
-        slot = slot_of(A, p);
     }
-    int64_t wtot;
-    const int64_t src = uni64(A.woff[base >> 6]) + wave_excl_sum64(slot, lane, &wtot);
     // inside bands: the whole wave copies one row's bands at a time
     for (uint64_t lm = __ballot(active && full != 0); lm; lm &= lm - 1) {
         const int l = __ffsll((unsigned long long)lm) - 1;
@@ -874,37 +916,60 @@ __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_
             o += (e - s) - (self ? 1 : 0);
         }
     }
-    // stored neighbours: entry t of the wave's concatenated stored parts
-    // belongs to the last lane whose prefix is <= t
-    const int64_t sc = active ? deg - fullc : 0;
-    int64_t T;
-    const int64_t pre = wave_excl_sum64(sc, lane, &T);
-    const int64_t at = dst + fullc;
-    constexpr int U = 4;  // entries per lane in flight
-    for (int64_t t0 = 0; t0 < T; t0 += 64 * U) {
-        int64_t from[U], to[U];
-        int32_t v[U];
+    // stored neighbours
+    long long T = active ? (long long)(deg - fullc) : 0ll;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t t = t0 + 64 * u + lane;
-            int l = 0;
+    for (int o = 32; o > 0; o >>= 1) T += __shfl_xor(T, o, 64);
+    const int64_t total = uni64(T);
+    const int64_t w0 = uni64(A.woff[base >> 6]);
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int64_t at = dst + fullc;  // this lane's next output position
+    for (int64_t c0 = 0; c0 < total; c0 += COPY_CHUNK) {
+        C.cnt[lane] = 0;
+        wave_sync();
+        int32_t idk[COPY_K];
+        int tagk[COPY_K], posk[COPY_K];
 #pragma unroll
-            for (int step = 32; step > 0; step >>= 1) {
-                const int64_t pv = __shfl(pre, l + step, 64);
-                if (t >= pv) l += step;
+        for (int k = 0; k < COPY_K; ++k) {
+            const int64_t e = c0 + k * 64 + lane;
+            const bool valid = e < total;
+            idk[k] = valid ? A.store[w0 + e] : 0;
+            const int tg = valid ? (int)A.stag[w0 + e] : 0;
+            tagk[k] = tg;
+            // lanes holding entries of the same query lane in this step
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 6; ++b) {
+                const uint64_t bb = __ballot((tg >> b) & 1);
+                peers &= ((tg >> b) & 1) ? bb : ~bb;
             }
-            // every lane takes part in the shuffles (a lane reading from an
-            // inactive lane would get garbage); the range test comes after
-            const int64_t k = t - __shfl(pre, l, 64);
-            const int64_t so = __shfl(src, l, 64), dd = __shfl(at, l, 64);
-            from[u] = t < T ? so + k : -1;
-            to[u] = dd + k;
+            const int before = valid ? C.cnt[tg] : 0;
+            posk[k] = valid ? before + __popcll(peers & lt_mask) : -1;
+            wave_sync();  // every read of cnt before its update
+            if (valid && lane == 63 - __clzll(peers)) C.cnt[tg] = before + __popcll(peers);
+            wave_sync();
         }
+        const int mine = C.cnt[lane];
+        int chunk_total;
+        const int bin = wave_excl_sum(mine, lane, &chunk_total);
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = from[u] >= 0 ? A.store[from[u]] : 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (from[u] >= 0) col[to[u]] = v[u];
+        for (int k = 0; k < COPY_K; ++k) {
+            const int start = __shfl(bin, tagk[k], 64);
+            if (posk[k] >= 0) {
+                C.id[start + posk[k]] = idk[k];
+                C.tag[start + posk[k]] = (uint8_t)tagk[k];
+            }
+        }
+        wave_sync();
+        for (int i0 = 0; i0 < chunk_total; i0 += 64) {
+            const int i = i0 + lane;
+            const int t = i < chunk_total ? (int)C.tag[i] : 0;
+            // all lanes take part in the shuffles; the range test comes after
+            const int64_t d = __shfl(at, t, 64) + (i - __shfl(bin, t, 64));
+            if (i < chunk_total) col[d] = C.id[i];
+        }
+        at += mine;
+        wave_sync();  // the stage is rewritten by the next chunk
     }
 }
 
@@ -1071,12 +1136,14 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.woff = idx->woff;
     A.wflag = idx->wflag;
     A.store = idx->stage;
+    A.stag = idx->stag;
     A.store_cap = L.stage_cap;
     const bool store = L.stage != 0;
     const int64_t nw = (idx->n + 63) / 64;
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
     hipError_t e;
+    PhaseScope plan_ps(RHG_PHASE_PLAN, s);  // ended before the search kernel
     if (!emit) {
         hipLaunchKernelGGL(search_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1105,21 +1172,30 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         }
         if (n <= 0) return hipSuccess;
     }
+    plan_ps.end();
     const int64_t blocks = A.heavy_blocks + (n + 255) / 256;
     const dim3 g((unsigned)blocks), b(256);
     if (emit && store) {
-        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), b, 0, s, A, row_ptr, col_idx);
+        {
+            PhaseScope ps(RHG_PHASE_COPY, s);
+            hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), b, 0, s, A, row_ptr, col_idx);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
         hipLaunchKernelGGL(search_kernel<M_COPY>, g, b, 0, s, A, row_ptr, col_idx);
-    }
-    else if (emit)
+    } else if (emit) {
+        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
         hipLaunchKernelGGL(search_kernel<M_EMIT>, g, b, 0, s, A, row_ptr, col_idx);
-    else if (store)
-        hipLaunchKernelGGL(search_kernel<M_STAGE>, g, b, 0, s, A, row_ptr, col_idx);
-    else
-        hipLaunchKernelGGL(search_kernel<M_COUNT>, g, b, 0, s, A, row_ptr, col_idx);
+    } else {
+        PhaseScope ps(RHG_PHASE_COUNT_PASS, s);
+        if (store)
+            hipLaunchKernelGGL(search_kernel<M_STAGE>, g, b, 0, s, A, row_ptr, col_idx);
+        else
+            hipLaunchKernelGGL(search_kernel<M_COUNT>, g, b, 0, s, A, row_ptr, col_idx);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!emit && items > 0) {
+        PhaseScope ps(RHG_PHASE_PLAN, s);
         if ((e = inclusive_scan_i64(idx->hcnt, idx->max_chunks, idx->tmp, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(heavy_degrees, dim3((unsigned)((idx->heavy_cap + 255) / 256)), dim3(256), 0, s, A,
                            row_ptr);

@@ -99,7 +99,8 @@ def test_stored_neighbours_give_the_rows_of_a_second_search():
         rp_s, col_s, st_s = run_search(P, params, r, t, tuning=dict(tun) or None)
         rp_d, col_d, st_d = run_search(P, params, r, t, tuning=dict(tun, no_stage=1))
         _say("store", tun, st_s)
-        assert st_s["stage_fallbacks"] == 0 and st_d["stage_fallbacks"] == 0
+        assert st_d["stage_fallbacks"] == 0 and st_d["stored"] == 0
+        assert st_s["stored"] > 0
         assert np.array_equal(rp_s, orp) and np.array_equal(rp_d, orp)
         assert np.array_equal(col_s, col_d)
         assert np.array_equal(canonical(rp_s, col_s), ocol)

@@ -428,27 +428,6 @@ __device__ __forceinline__ int wave_excl_sum(int v, int lane, int *total)
     return x - v;
 }
 
-// Largest j in [0, nb) with pre[j] <= g (pre ascending, pre[0] = 0).
-__device__ __forceinline__ int find_band(const int32_t *pre, int nb, int g)
-{
-    int lo = 0, hi = nb - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// First index in [a, b) of the staged keys with key >= k.
-__device__ __forceinline__ int lds_lower_bound(const uint32_t *key, int a, int b, uint32_t k)
-{
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (key[mid] < k) a = mid + 1; else b = mid;
-    }
-    return a;
-}
-
 // Upper bound of band j's window for a query with normalised record
 // (e', m', s'): dropping the non-negative cosh(r_q - E[j]) / cosh R term
 // gives X <= 1 / (s'_q s'(E[j])), so sqrt X <= rs_q * rs_j with the reciprocal
@@ -480,7 +459,6 @@ __device__ __forceinline__ float lane_float(float v, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-constexpr int STAGE = 384;  // staged candidates per wavefront
 
 // Slots of the neighbour store for the light query at sorted position p:
 // its expected degree, interpolated (log-linear) in the table at
@@ -508,19 +486,15 @@ __device__ __forceinline__ int64_t wave_excl_sum64(int64_t v, int lane, int64_t 
     return x - v;
 }
 
-struct WaveStage {
-    uint32_t key[STAGE];   // staged band key bits (the sort order inside a band)
-    double th[STAGE];      // staged angles
-};
 
 // Light queries: a wavefront of 64 consecutive sorted positions.  Lane j
 // first builds band j's entry of the wave's band table: the union of the
 // lanes' windows (the window of the innermost lane, stretched over the
-// lanes' angle range) as at most two position runs.  Bands whose lane
-// windows overlap ("shared") are tested exhaustively, every lane against
-// every candidate, their runs concatenated and read 64 at a time from LDS.
-// For the other bands the runs' keys and angles are staged in LDS and each
-// lane binary searches its own window, then tests what lies inside.
+// lanes' angle range) as at most two position runs.  Where the lanes'
+// windows overlap (the window is at least as wide as the lanes' angle
+// spread) the band is "shared": every lane tests every candidate of the
+// union.  Otherwise each lane finds its own window's runs and the wave
+// works through all lanes' runs as one stream, 64 candidates per step.
 //
 // MODE M_COUNT counts; M_STAGE counts and writes the neighbours found by
 // tests into the lane's store slots (bands wholly inside the circle are only
@@ -532,10 +506,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
 {
     constexpr bool EMIT = MODE == M_EMIT;
     constexpr bool STORE = MODE == M_STAGE;
-    __shared__ WaveStage stg[4];
-    __shared__ int32_t stage_pre[4][2][RHG_MAX_BANDS + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    WaveStage &S = stg[wv];
+    const int lane = threadIdx.x & 63;
     const int64_t p = base + lane;
     const int64_t hend = uni64(*A.heavy_end);
     const bool active = p < A.n && p >= hend;
@@ -614,16 +585,14 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     };
 
     // band table: lane j describes band j
-    int mode = 0;  // 0 nothing, 1 shared, 2 staged, 3 cooperative per query
+    int mode = 0;  // 0 nothing, 1 shared window, 2 per-query windows
     int32_t a0 = 0, b0 = 0, a1 = 0, b1 = 0;
     bool fpoly = true;
-    double W_band = 4.0;
     if (lane < B) {
         const int j = lane;
         const int64_t s = A.band_start[j], e = A.band_start[j + 1];
         if (s < e) {
             const double W = window_w(A, eqm, mqm, sqm, j);
-            W_band = W;
             if (W >= 3.0) {
                 a0 = (int32_t)s; b0 = (int32_t)e;
                 mode = 1;
@@ -644,143 +613,32 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         for (int o = 32; o > 0; o >>= 1) f &= (uint64_t)__shfl_xor((long long)f, o, 64);
         if (lane < B && ((f >> lane) & 1ull)) mode = 0;
     }
-    const int U = (b0 - a0) + (b1 - a1);
-    if (U == 0) mode = 0;
-    // per-lane windows: a lane's window holds about U 2W / (span + 2W)
-    // candidates; large windows go to the cooperative mode (the whole wave
-    // on one query at a time), small ones to the staged binary searches
-    if (mode == 2 && (double)U * (2.0 * W_band) >= 16.0 * (span + 2.0 * W_band)) mode = 3;
-    int tot2;
-    int off2 = wave_excl_sum(mode == 2 ? U : 0, lane, &tot2);
-    if (mode == 2 && off2 + U > STAGE) mode = 3;  // would overflow the stage
-    off2 = wave_excl_sum(mode == 2 ? U : 0, lane, &tot2);
-    int tot1;
-    const int off1 = wave_excl_sum(mode == 1 ? U : 0, lane, &tot1);
-    if (lane <= B) {
-        stage_pre[wv][0][lane] = lane < B ? off1 : tot1;
-        stage_pre[wv][1][lane] = lane < B ? off2 : tot2;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if ((b0 - a0) + (b1 - a1) == 0) mode = 0;
 
-    // shared bands: every lane tests every candidate, 64 staged at a time
-    uint32_t *spos = S.key;                         // position | band << 26 (n < 2^31, B <= 64)
-    float4 *srec = (float4 *)&S.th[64];             // records of the chunk
-    for (int g0 = 0; g0 < tot1; g0 += 64) {
-        const int g = g0 + lane;
-        const int bj = find_band(stage_pre[wv][0], B, g < tot1 ? g : tot1 - 1);
-        const int pa0 = __shfl(a0, bj, 64), pb0 = __shfl(b0, bj, 64), pa1 = __shfl(a1, bj, 64);
-        const int fpb = __shfl((int)fpoly, bj, 64);
-        if (g < tot1) {
-            const int o = g - stage_pre[wv][0][bj];
-            const int64_t pos = (o < pb0 - pa0) ? (int64_t)pa0 + o : (int64_t)pa1 + (o - (pb0 - pa0));
-            S.th[lane] = A.st[pos];
-            srec[lane] = A.rec[pos];
-            spos[lane] = (uint32_t)pos;
-            spos[64 + lane] = (uint32_t)bj | ((uint32_t)fpb << 8);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int m = min(64, tot1 - g0);
-        for (int t = 0; t < m; ++t) {
-            const double tc = S.th[t];
-            const float4 fc = srec[t];
-            const int64_t ct = spos[t];
-            const uint32_t meta = spos[64 + t];
-            const int bt = (int)(meta & 255u);
-            int acc = 0;
-            if (active && ct != p && !((full >> bt) & 1ull))
-                acc = decide(A, rq, tq, fq.x, fq.y, fq.z, ct, tc, fc.x, fc.y, fc.z, (meta >> 8) != 0);
-            if (EMIT && acc && cnt < lim) out[cnt] = __float_as_int(fc.w);
-            if (STORE) put(acc, __float_as_int(fc.w), lane);
-            cnt += acc;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-
-    // staged bands: band keys and angles of the runs in LDS; the index is
-    // sorted by the top 32 - band_bits bits of the angle key inside a band,
-    // so those bits (not the full key) are searched
-    const int kshift = A.band_bits;
-    const uint32_t kmask = kshift ? ((1u << (32 - kshift)) - 1u) : 0xffffffffu;
-    // (the trip count is uniform: cross-lane reads from lanes that have left
-    // a loop would return garbage)
-    for (int g0 = 0; g0 < tot2; g0 += 64) {
-        const int g = g0 + lane;
-        const int bj = find_band(stage_pre[wv][1], B, g < tot2 ? g : tot2 - 1);
-        const int pa0 = __shfl(a0, bj, 64), pb0 = __shfl(b0, bj, 64), pa1 = __shfl(a1, bj, 64);
-        if (g < tot2) {
-            const int o = g - stage_pre[wv][1][bj];
-            const int64_t pos = (o < pb0 - pa0) ? (int64_t)pa0 + o : (int64_t)pa1 + (o - (pb0 - pa0));
-            S.key[g] = A.keys[pos] & kmask;
-            S.th[g] = A.st[pos];
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint64_t staged = __ballot(lane < B && mode == 2);
-    const uint64_t percell = __ballot(lane < B && mode == 3);
-    const float rsq = active && fq.z > 0.0f ? rsqrtf(fq.z) : 0.0f;
-    for (uint64_t mk = staged; mk; mk &= mk - 1) {
-        const int j = __ffsll((unsigned long long)mk) - 1;
-        const int ja0 = __builtin_amdgcn_readlane(a0, j), jb0 = __builtin_amdgcn_readlane(b0, j);
-        const int ja1 = __builtin_amdgcn_readlane(a1, j), jb1 = __builtin_amdgcn_readlane(b1, j);
-        const int seg0 = stage_pre[wv][1][j];
-        const int seg1 = seg0 + (jb0 - ja0);
-        const int seg2 = seg1 + (jb1 - ja1);
-        const bool me = active && !((full >> j) & 1ull);
-        double w = 0.0;
-        bool fp = true;
-        uint32_t k00 = 1u, k10 = 0u, k01 = 1u, k11 = 0u;  // key ranges [k0r, k1r]; empty by default
-        if (me) {
-            w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
-            fp = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-            const double lo = tq - w, hi = tq + w;
-            if (hi - lo >= RHG_TWO_PI_D) {  // the whole band (disjoint ranges below need w < pi)
-                k00 = 0u; k10 = kmask;
-            } else if (lo < 0.0) {
-                k00 = 0u; k10 = angle_key_s(hi) >> kshift;
-                k01 = angle_key_s(lo + RHG_TWO_PI_D) >> kshift; k11 = kmask;
-            } else if (hi >= RHG_TWO_PI_D) {
-                k00 = 0u; k10 = angle_key_s(hi - RHG_TWO_PI_D) >> kshift;
-                k01 = angle_key_s(lo) >> kshift; k11 = kmask;
-            } else {
-                k00 = angle_key_s(lo) >> kshift; k10 = angle_key_s(hi) >> kshift;
-            }
-        }
-        // every lane walks its key ranges inside both runs of the band; the
-        // loops run while any lane still has candidates, so the acceptances
-        // of a step can be appended together
-        for (int r = 0; r < 2; ++r) {
-            const uint32_t kb = r ? k01 : k00, ke = r ? k11 : k10;
-            for (int sg = 0; sg < 2; ++sg) {
-                const int sa = sg ? seg1 : seg0, sb = sg ? seg2 : seg1;
-                if (sa == sb) continue;
-                const int64_t run0 = sg ? ja1 : ja0;
-                int i = (kb <= ke) ? lds_lower_bound(S.key, sa, sb, kb) : sb;
-                for (;;) {
-                    const bool live = i < sb && S.key[i] <= ke;
-                    if (__ballot(live) == 0) break;
+    // shared bands: every lane tests every candidate of the band's union
+    // window.  The candidate is the same for the whole wave, so its angle and
+    // record are read through the scalar cache (the index is read-only while
+    // the search runs) and enter the test as scalar operands.
+    {
+        const double __attribute__((address_space(4))) *cst =
+            (const double __attribute__((address_space(4))) *)A.st;
+        const float __attribute__((address_space(4))) *crec =
+            (const float __attribute__((address_space(4))) *)A.rec;
+        for (uint64_t mk = __ballot(lane < B && mode == 1); mk; mk &= mk - 1) {
+            const int j = __ffsll((unsigned long long)mk) - 1;
+            const int ja0 = __builtin_amdgcn_readlane(a0, j), jb0 = __builtin_amdgcn_readlane(b0, j);
+            const int ja1 = __builtin_amdgcn_readlane(a1, j), jb1 = __builtin_amdgcn_readlane(b1, j);
+            const bool fpj = __builtin_amdgcn_readlane((int)fpoly, j) != 0;
+            const bool me = active && !((full >> j) & 1ull);
+            for (int run = 0; run < 2; ++run) {
+                const int cs = run ? ja1 : ja0, ce = run ? jb1 : jb0;
+                for (int c = cs; c < ce; ++c) {
+                    const double tc = cst[c];
+                    const int64_t c4 = 4 * (int64_t)c;
+                    const float cx = crec[c4], cy = crec[c4 + 1], cz = crec[c4 + 2];
+                    const int32_t cid = __float_as_int(crec[c4 + 3]);
                     int acc = 0;
-                    int32_t cid = 0;
-                    if (live) {
-                        const double tc = S.th[i];
-                        const int64_t c = run0 + (i - sa);
-                        // keys bucket angles: skip what lies past the window
-                        // (w carries a relative pad far above the angle's
-                        // rounding, so these are not neighbours)
-                        if (c != p && !(short_angle(tq, tc) > w)) {
-                            const float4 fc = A.rec[c];
-                            cid = __float_as_int(fc.w);
-                            acc = decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp);
-                        }
-                        ++i;
-                    }
+                    if (me && c != p) acc = decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, cx, cy, cz, fpj);
                     if (EMIT && acc && cnt < lim) out[cnt] = cid;
                     if (STORE) put(acc, cid, lane);
                     cnt += acc;
@@ -788,56 +646,88 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             }
         }
     }
-    // large per-lane windows: each lane finds its own runs in band j, then
-    // the whole wave works through one lane's runs at a time, 64 consecutive
-    // candidates per step (coalesced loads; in the emit pass contiguous,
-    // ordered writes from a ballot prefix)
+
+    const uint64_t percell = __ballot(lane < B && mode == 2);
+    const float rsq = active && fq.z > 0.0f ? rsqrtf(fq.z) : 0.0f;
+    // per-query windows (the lanes' angles spread wider than the window):
+    // each lane finds its own runs in band j; the
+    // runs of all lanes are then concatenated (lane order) and worked
+    // through 64 candidates per step, each candidate tested against the
+    // query of the lane that owns it.  The loads of the next step are issued
+    // before the current step is tested.
     for (uint64_t mk = percell; mk; mk &= mk - 1) {
         const int j = __ffsll((unsigned long long)mk) - 1;
         const int64_t s = A.band_start[j], e = A.band_start[j + 1];
-        int64_t ra[2] = {0, 0}, rb[2] = {0, 0};
+        int64_t ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0;
         double w = 0.0;
         const bool mine = active && !((full >> j) & 1ull);
         if (mine) {
             w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
+            int64_t ra[2] = {0, 0}, rb[2] = {0, 0};
             if (w >= 3.0) { ra[0] = s; rb[0] = e; }
             else window_runs(A, j, tq - w, tq + w, s, e, ra, rb);
+            ra0 = ra[0]; rb0 = rb[0]; ra1 = ra[1]; rb1 = rb[1];
         }
-        const int64_t len0 = rb[0] - ra[0], len = len0 + (rb[1] - ra[1]);
-        const bool fpl = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
-        int32_t *outc = out + cnt;  // EMIT: this lane's next output slot
-        for (uint64_t lm = __ballot(mine && len > 0); lm; lm &= lm - 1) {
-            const int l = __ffsll((unsigned long long)lm) - 1;
-            const int64_t la0 = uni_lane64(ra[0], l), lb0 = uni_lane64(rb[0], l), la1 = uni_lane64(ra[1], l);
-            const int64_t llen0 = lb0 - la0, llen = uni_lane64(len, l);
-            const int64_t lp = uni_lane64(p, l);
-            const double lr = lane_double(rq, l), lt = lane_double(tq, l), lw = lane_double(w, l);
-            const float le = lane_float(fq.x, l), lmq = lane_float(fq.y, l), ls = lane_float(fq.z, l);
-            const bool lfp = __builtin_amdgcn_readlane((int)fpl, l) != 0;
-            int32_t *lout = EMIT ? (int32_t *)uni_lane64((int64_t)outc, l) : nullptr;
-            const int64_t llim = EMIT ? uni_lane64(lim - cnt, l) : 0;
-            int64_t got = 0;
-            for (int64_t vb = 0; vb < llen; vb += 64) {
-                const int64_t v = vb + lane;
-                int acc = 0, cid = 0;
-                if (v < llen) {
-                    const int64_t c = (v < llen0) ? la0 + v : la1 + (v - llen0);
-                    const double tc = A.st[c];
-                    if (c != lp && !(short_angle(lt, tc) > lw)) {
-                        const float4 fc = A.rec[c];
-                        cid = __float_as_int(fc.w);
-                        acc = decide(A, lr, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp);
-                    }
-                }
-                const uint64_t bal = __ballot(acc);
-                if (EMIT && acc) {
-                    const int64_t o = got + __popcll(bal & lt_mask);
-                    if (o < llim) lout[o] = cid;
-                }
-                if (STORE) put(acc, cid, l);
-                got += __popcll(bal);
+        const int64_t len0 = rb0 - ra0, len = len0 + (rb1 - ra1);
+        const int fpl = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+        int64_t total;
+        const int64_t pre = wave_excl_sum64(len, lane, &total);  // this lane's runs: [pre, pre + len)
+        if (total == 0) continue;
+        // owner lane and position of stream entry t (every lane takes part)
+        auto locate = [&](int64_t t, int &l, int64_t &c) {
+            l = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int64_t pv = __shfl(pre, l + step, 64);
+                if (t >= pv) l += step;
             }
-            if (lane == l) cnt += got;
+            const int64_t k = t - __shfl(pre, l, 64);
+            const int64_t l0 = __shfl(len0, l, 64), la0 = __shfl(ra0, l, 64), la1 = __shfl(ra1, l, 64);
+            c = (k < l0) ? la0 + k : la1 + (k - l0);
+        };
+        int ln;
+        int64_t cn;
+        locate(lane, ln, cn);
+        double tn = 0.0;
+        float4 fn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < total) { tn = A.st[cn]; fn = A.rec[cn]; }
+        for (int64_t t0 = 0; t0 < total; t0 += 64) {
+            const int l = ln;
+            const int64_t c = cn;
+            const double tc = tn;
+            const float4 fc = fn;
+            const bool valid = t0 + lane < total;
+            if (t0 + 64 < total) {
+                locate(t0 + 64 + lane, ln, cn);
+                if (t0 + 64 + lane < total) { tn = A.st[cn]; fn = A.rec[cn]; }
+            }
+            // the owner's query
+            const double lr = __shfl(rq, l, 64), lt = __shfl(tq, l, 64), lw = __shfl(w, l, 64);
+            const float le = __shfl(fq.x, l, 64), lmq = __shfl(fq.y, l, 64), ls = __shfl(fq.z, l, 64);
+            const int64_t lp = __shfl(p, l, 64);
+            const bool lfp = __shfl(fpl, l, 64) != 0;
+            int acc = 0;
+            const int cid = __float_as_int(fc.w);
+            if (valid && c != lp && !(short_angle(lt, tc) > lw))
+                acc = decide(A, lr, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp);
+            const uint64_t bal = __ballot(acc);
+            // this lane's part of the step, as the owner of [pre, pre + len)
+            const int64_t lo = pre - t0, hi = pre + len - t0;
+            const uint64_t lom = lo <= 0 ? ~0ull : (lo >= 64 ? 0ull : ~0ull << lo);
+            const uint64_t him = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ~(~0ull << hi));
+            const int got = __popcll(bal & lom & him);
+            if (EMIT) {
+                // position inside the owner's row: its count before the step plus
+                // the acceptances of its earlier entries in this step
+                const int64_t lo_l = __shfl(pre, l, 64) - t0;
+                const uint64_t seg = lo_l <= 0 ? ~0ull : ~0ull << lo_l;
+                const int64_t at = __shfl(cnt, l, 64) + __popcll(bal & seg & lt_mask);
+                int32_t *const lout = (int32_t *)__shfl((int64_t)out, l, 64);
+                const int64_t llim = __shfl(lim, l, 64);
+                if (acc && at < llim) lout[at] = cid;
+            }
+            if (STORE) put(acc, cid, l);
+            cnt += got;
         }
     }
     if (STORE && lane == 0) {

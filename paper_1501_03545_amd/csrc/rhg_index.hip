@@ -89,29 +89,42 @@ struct DirArgs {
 };
 
 // dir[dir_base[j] + c] = first sorted position of band j whose cell is >= c,
-// for c = 0 .. 2^cbits[j] (the last entry is the band's end).
-__global__ void __launch_bounds__(256) dir_kernel(DirArgs A, const uint32_t *__restrict__ keys,
-                                                  const int32_t *__restrict__ band_start,
-                                                  int32_t *__restrict__ dir)
+// for c = 0 .. 2^cbits[j] (the last entry is the band's end).  One pass over
+// the sorted keys: position p writes the entries of the cells after its
+// predecessor's cell up to its own (and the last position of a band those
+// up to the band's end), so every entry is written once.
+__global__ void __launch_bounds__(256) dir_fill_kernel(DirArgs A, int64_t n, const uint32_t *__restrict__ keys,
+                                                       const int32_t *__restrict__ band_start,
+                                                       int32_t *__restrict__ dir)
 {
+    const int ab = 32 - A.band_bits;  // angle bits of a key
+    const uint32_t amask = ab >= 32 ? 0xffffffffu : ((1u << ab) - 1u);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.total; e += stride) {
-        int j = 0;
-        while (j + 1 < A.B && A.dir_base[j + 1] <= e) ++j;
-        const int64_t c = e - A.dir_base[j];
-        const int64_t s = band_start[j], t = band_start[j + 1];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const uint32_t k = keys[p];
+        const int j = A.band_bits ? (int)(k >> ab) : 0;
         const int cb = A.cbits[j];
-        int64_t p;
-        if (c == 0) p = s;
-        else if (c >= ((int64_t)1 << cb)) p = t;
-        else {
-            // key of the first angle in cell c of band j
-            const int shift = 32 - A.band_bits - cb;  // >= 0 by construction
-            const uint64_t k = ((uint64_t)j << (32 - A.band_bits)) + ((uint64_t)c << shift);
-            p = lower_bound_key(keys, s, t, A.band_bits ? k : ((uint64_t)c << (32 - cb)));
-        }
-        dir[e] = (int32_t)p;
+        const int64_t s = band_start[j], t = band_start[j + 1];
+        const int64_t c = cb ? (int64_t)((k & amask) >> (ab - cb)) : 0;
+        const int64_t cp = (p > s) ? (cb ? (int64_t)((keys[p - 1] & amask) >> (ab - cb)) : 0) : -1;
+        int32_t *d = dir + A.dir_base[j];
+        for (int64_t cc = cp + 1; cc <= c; ++cc) d[cc] = (int32_t)p;
+        if (p == t - 1)
+            for (int64_t cc = c + 1; cc <= ((int64_t)1 << cb); ++cc) d[cc] = (int32_t)t;
     }
+}
+
+// Empty bands have no position to write their directory: all of it is the
+// band's (empty) start.  One block per band.
+__global__ void __launch_bounds__(256) dir_empty_kernel(DirArgs A, const int32_t *__restrict__ band_start,
+                                                        int32_t *__restrict__ dir)
+{
+    const int j = blockIdx.x;
+    if (j >= A.B) return;
+    const int32_t s = band_start[j];
+    if (s != band_start[j + 1]) return;
+    const int64_t m = ((int64_t)1 << A.cbits[j]) + 1;
+    for (int64_t c = threadIdx.x; c < m; c += 256) dir[A.dir_base[j] + c] = s;
 }
 
 // Sorted per-point records: r, theta (binary64) and the FP32 screen record
@@ -171,8 +184,10 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
     da.B = L.B;
     da.band_bits = L.band_bits;
     da.total = L.dir_total;
-    hipLaunchKernelGGL(dir_kernel, dim3(grid_for(L.dir_total)), dim3(256), 0, s, da, idx->keys, idx->band_start,
-                       idx->dir);
+    if (n > 0)
+        hipLaunchKernelGGL(dir_fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, da, n, idx->keys, idx->band_start,
+                           idx->dir);
+    hipLaunchKernelGGL(dir_empty_kernel, dim3((unsigned)L.B), dim3(256), 0, s, da, idx->band_start, idx->dir);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     phase_end(ps_index.rec, s);
     ps_index.rec = nullptr;

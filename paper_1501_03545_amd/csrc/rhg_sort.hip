@@ -179,25 +179,32 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid)
     return m;
 }
 
+// One LSD pass over a tile of RS_TILE elements: the tile is first sorted by
+// the digit in LDS (stably: by wave, chunk and lane, as in the input), then
+// written out in LDS order, so that consecutive threads write consecutive
+// addresses of the same digit's run.
 __global__ void __launch_bounds__(RS_BLOCK) radix_scatter_kernel(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets, int64_t nblocks)
 {
     __shared__ uint32_t wh[RS_WAVES][256];
+    __shared__ uint32_t lstart[256], gbase[256], tot[256];
+    __shared__ uint32_t lk[RS_TILE], lv[RS_TILE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int d = threadIdx.x; d < RS_WAVES * 256; d += RS_BLOCK) (&wh[0][0])[d] = 0;
     __syncthreads();
-    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)wave * RS_WAVE_TILE;
+    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t wbase = tbase + (int64_t)wave * RS_WAVE_TILE;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t key[RS_ITEMS], val[RS_ITEMS];
-#pragma unroll
+#pragma unroll 4
     for (int c = 0; c < RS_ITEMS; ++c) {
         const int64_t i = wbase + c * 64 + lane;
         key[c] = (i < n) ? kin[i] : 0u;
         val[c] = (i < n) ? vin[i] : 0u;
     }
     // per-wave digit histogram
-#pragma unroll
+#pragma unroll 4
     for (int c = 0; c < RS_ITEMS; ++c) {
         const int64_t i = wbase + c * 64 + lane;
         const uint64_t valid = __ballot(i < n);
@@ -206,18 +213,33 @@ __global__ void __launch_bounds__(RS_BLOCK) radix_scatter_kernel(
         if (i < n && (m & lt) == 0) wh[wave][d] += (uint32_t)__popcll(m);
     }
     __syncthreads();
+    // digit totals of the tile, their exclusive prefix (the digit runs in
+    // LDS), and each wave's start inside its digits' runs
+    const int dt = threadIdx.x;  // RS_BLOCK == 256 digits
+    uint32_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) sum += wh[w][dt];
+    tot[dt] = sum;
+    gbase[dt] = offsets[(int64_t)dt * nblocks + blockIdx.x];
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t add = dt >= o ? tot[dt - o] : 0u;
+        __syncthreads();
+        tot[dt] += add;
+        __syncthreads();
+    }
     {
-        const int d = threadIdx.x;  // RS_BLOCK == 256 digits
-        uint32_t run = offsets[(int64_t)d * nblocks + blockIdx.x];
+        uint32_t run = tot[dt] - sum;  // exclusive prefix
+        lstart[dt] = run;
 #pragma unroll
         for (int w = 0; w < RS_WAVES; ++w) {
-            const uint32_t t = wh[w][d];
-            wh[w][d] = run;
+            const uint32_t t = wh[w][dt];
+            wh[w][dt] = run;
             run += t;
         }
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 4
     for (int c = 0; c < RS_ITEMS; ++c) {
         const int64_t i = wbase + c * 64 + lane;
         const uint64_t valid = __ballot(i < n);
@@ -226,12 +248,23 @@ __global__ void __launch_bounds__(RS_BLOCK) radix_scatter_kernel(
         const uint32_t rank = (uint32_t)__popcll(m & lt);
         const uint32_t pos = wh[wave][d] + rank;
         __builtin_amdgcn_wave_barrier();
-        if (i < n && pos < (uint64_t)n) {
-            kout[pos] = key[c];
-            vout[pos] = val[c];
+        if (i < n && pos < (uint32_t)RS_TILE) {
+            lk[pos] = key[c];
+            lv[pos] = val[c];
             if (rank == 0) wh[wave][d] = pos + (uint32_t)__popcll(m);
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    const int64_t count = n - tbase < (int64_t)RS_TILE ? n - tbase : (int64_t)RS_TILE;
+    for (int t = threadIdx.x; t < count; t += RS_BLOCK) {
+        const uint32_t k = lk[t];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint64_t pos = (uint64_t)gbase[d] + (uint32_t)t - lstart[d];
+        if (pos < (uint64_t)n) {
+            kout[pos] = k;
+            vout[pos] = lv[t];
+        }
     }
 }
 

@@ -109,7 +109,7 @@ def run_gpu(cfg, steps, warmup, tuning=None):
                 params=p)
 
 
-def run_batch(count, reps, tuned=True, n_streams=16):
+def run_batch(count, reps, tuned=True, n_streams=64):
     """The batch workload: `count` uneven graphs as one captured launch
     (autotuned per class when a tuning cache exists), against the plain
     per-graph loop over the same graphs (one stream, default tuning,

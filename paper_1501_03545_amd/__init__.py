@@ -305,7 +305,7 @@ class Batch:
     """Many graphs captured into one HIP graph (rhg_batch_create); launch()
     runs the whole batch as one submission."""
 
-    def __init__(self, bufs, n_streams: int = 16):
+    def __init__(self, bufs, n_streams: int = 64):
         import torch
         self.bufs = bufs
         k = len(bufs)

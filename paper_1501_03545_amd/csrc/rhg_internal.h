@@ -52,27 +52,36 @@ struct Layout {
 // (sinh r sinh r'), r' drawn from the radial density of Eq. (1).  Composite
 // 8-point Gauss-Legendre quadrature over 16 panels of [max(0, R - r), R].
 // Used only to size the neighbour store.
-RHG_HD double expected_degree(double n, double alpha, double R, double r)
+#define RHG_KAP_NODES 128  // 16 panels x 8 Gauss-Legendre nodes
+
+// Contribution of quadrature node `node` (0 .. RHG_KAP_NODES-1) to the
+// probability part of the expected degree at radius r (r > 0, R - r < R).
+RHG_HD double degree_node(double alpha, double R, double r, int node)
 {
     const double xg[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
     const double wg[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
     const double den = cosh(alpha * R) - 1.0;
     const double lo = fmax(0.0, R - r);
-    double tot = (cosh(alpha * lo) - 1.0) / den;
-    if (r > 0.0 && lo < R) {
-        const double cR = cosh(R), chr = cosh(r), shr = sinh(r);
-        const int P = 16;
-        const double h = (R - lo) / P;
-        for (int k = 0; k < P; ++k) {
-            const double mid = lo + (k + 0.5) * h;
-            for (int g = 0; g < 8; ++g) {
-                const double x = mid + ((g & 1) ? 0.5 : -0.5) * h * xg[g >> 1];
-                const double c = (chr * cosh(x) - cR) / (shr * sinh(x));
-                const double th = acos(fmin(1.0, fmax(-1.0, c)));
-                tot += 0.5 * h * wg[g >> 1] * (alpha * sinh(alpha * x) / den) * (th / 3.141592653589793);
-            }
-        }
-    }
+    const double h = (R - lo) / 16.0;
+    const int k = node >> 3, g = node & 7;
+    const double mid = lo + (k + 0.5) * h;
+    const double x = mid + ((g & 1) ? 0.5 : -0.5) * h * xg[g >> 1];
+    const double c = (cosh(r) * cosh(x) - cosh(R)) / (sinh(r) * sinh(x));
+    const double th = acos(fmin(1.0, fmax(-1.0, c)));
+    return 0.5 * h * wg[g >> 1] * (alpha * sinh(alpha * x) / den) * (th / 3.141592653589793);
+}
+
+// The part of partners within R - r of the centre (always neighbours).
+RHG_HD double degree_inner(double alpha, double R, double r)
+{
+    return (cosh(alpha * fmax(0.0, R - r)) - 1.0) / (cosh(alpha * R) - 1.0);
+}
+
+RHG_HD double expected_degree(double n, double alpha, double R, double r)
+{
+    double tot = degree_inner(alpha, R, r);
+    if (r > 0.0)
+        for (int q = 0; q < RHG_KAP_NODES; ++q) tot += degree_node(alpha, R, r, q);
     return (n - 1.0) * fmin(1.0, tot);
 }
 

@@ -903,18 +903,26 @@ __global__ void __launch_bounds__(256) copy_kernel(SearchArgs A, const int64_t *
 }
 
 // Expected-degree table of the neighbour store: log of the expected degree
-// at RHG_KAP_SUB equally spaced radii per band, and at R.
-__global__ void __launch_bounds__(64) store_table(SearchArgs A)
+// at RHG_KAP_SUB equally spaced radii per band, and at R.  One wavefront per
+// radius, two quadrature nodes per lane.
+__global__ void __launch_bounds__(256) store_table(SearchArgs A)
 {
-    const int i = (int)(blockIdx.x * 64 + threadIdx.x);
+    const int i = (int)(blockIdx.x * 4 + (threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int last = RHG_KAP_SUB * A.B;
-    if (i > last) return;
+    if (i > last) return;  // whole wavefronts leave together
     double r = A.R;
     if (i < last) {
         const int j = i / RHG_KAP_SUB, sub = i % RHG_KAP_SUB;
         r = A.E[j] + (A.E[j + 1] - A.E[j]) * sub / RHG_KAP_SUB;
     }
-    A.lkap[i] = (float)log(fmax(expected_degree(A.nd, A.alpha, A.R, r), 1e-3));
+    double part = 0.0;
+    if (r > 0.0) part = degree_node(A.alpha, A.R, r, lane) + degree_node(A.alpha, A.R, r, lane + 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (lane == 0) {
+        const double k = (A.nd - 1.0) * fmin(1.0, degree_inner(A.alpha, A.R, r) + part);
+        A.lkap[i] = (float)log(fmax(k, 1e-3));
+    }
 }
 
 // Slots per wavefront of 64 sorted positions (light queries only); the
@@ -1050,7 +1058,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         if (store) {
-            hipLaunchKernelGGL(store_table, dim3((unsigned)((RHG_KAP_SUB * L.B + 1 + 63) / 64)), dim3(64), 0, s, A);
+            hipLaunchKernelGGL(store_table, dim3((unsigned)((RHG_KAP_SUB * L.B + 1 + 3) / 4)), dim3(256), 0, s, A);
             hipLaunchKernelGGL(store_plan, dim3((unsigned)((nw * 64 + 255) / 256)), dim3(256), 0, s, A, nw);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = inclusive_scan_i64(idx->woff + 1, nw, idx->tmp, s)) != hipSuccess) return e;

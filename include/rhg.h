@@ -171,14 +171,36 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
  * query with no_stage).  row_ptr must be the output of rhg_count_edges on the
  * same index, and the call must follow that count pass (it reads what the
  * count pass stored).  Each undirected edge appears in both rows; there are
- * no self-loops.  Rows are in search order, deterministic for a given
- * tuning and the same with and without staging; canonical_rows must be 0
- * (ascending rows are not provided by this library: RHG_EINVAL).
+ * no self-loops.  canonical_rows = 0: rows are in search order,
+ * deterministic for a given tuning and the same with and without staging.
+ * canonical_rows = 1: every row is then sorted ascending (rhg_sort_rows on
+ * the index's own scratch), so col_idx is the same bytes for every tuning.
  * col_capacity is the number of int32 slots in col_idx; the call reads
  * row_ptr[n] back (one synchronisation) and returns RHG_ECAPACITY if it
- * exceeds col_capacity. */
+ * exceeds col_capacity, or if canonical rows are asked for a graph whose mean
+ * degree passes 4096 (sort such a graph with rhg_sort_rows instead). */
 rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx,
                           int64_t col_capacity, int canonical_rows, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Canonical rows.                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Sorts every row of a CSR ascending, in place: the canonical layout of the
+ * edge set of Prop. 2 (the pairs within distance R), identical for every
+ * tuning.  row_ptr: device, n + 1 non-decreasing int64 offsets into col_idx;
+ * col_idx: device int32 entries, compared as signed integers (equal entries
+ * are allowed).  nnz must be at least row_ptr[n] - row_ptr[0]: it sizes the
+ * list of rows longer than 8192 entries and the merge levels; with a smaller
+ * value some long rows stay unsorted (no access leaves the rows).
+ * workspace: device, rhg_sort_rows_workspace_bytes(n, nnz) bytes, scratch
+ * only.  Asynchronous on `stream`, no allocation and no host synchronisation.
+ * Errors: RHG_EINVAL for n < 0, n > 2^31 - 1, nnz < 0 or a NULL pointer
+ * (nothing is needed when n or nnz is 0); RHG_ECAPACITY for a smaller
+ * workspace. */
+size_t rhg_sort_rows_workspace_bytes(int64_t n, int64_t nnz);
+rhg_status rhg_sort_rows(int64_t n, const int64_t *row_ptr, int32_t *col_idx, int64_t nnz,
+                         void *workspace, size_t workspace_bytes, void *stream);
 
 /* Diagnostics accumulated by the count and emit passes (synchronises). */
 rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out /* host */, void *stream);
@@ -207,7 +229,7 @@ typedef struct {
 /* Plans, samples, indexes, counts, scans and emits one graph.  All device
  * memory (points, index workspace, CSR) comes from `alloc`; the only host
  * synchronisation is the 8-byte read of 2m before col_idx is allocated.
- * canonical_rows must be 0, as for rhg_emit_edges.
+ * canonical_rows as for rhg_emit_edges.
  * Errors: those of rhg_plan, and RHG_ENOMEM if `alloc` returns NULL. */
 rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t seed,
                         const rhg_tuning *t /* host, may be NULL */,
@@ -229,9 +251,10 @@ rhg_status rhg_set_profiling(int on);
  * 4 plan (the small kernels around the searches: heavy-work plan, store
  * slots, their scans, heavy degrees, capacity check), 5 count (the search
  * kernel of the count pass), 6 scan (row offsets), 7 copy (the kernel
- * copying stored neighbours), 8 emit (the search kernel of the emit pass).
- * Each of 5, 7 and 8 brackets exactly one kernel launch.  avg_ms, count:
- * host arrays of at least 9 entries (cap). */
+ * copying stored neighbours), 8 emit (the search kernel of the emit pass),
+ * 9 rows (the row sort of canonical rows).  Each of 5, 7 and 8 brackets
+ * exactly one kernel launch.  avg_ms, count: host arrays of at least 10
+ * entries (cap). */
 rhg_status rhg_phase_times(double *avg_ms /* host */, int64_t *count /* host */, int cap);
 
 /* Name of a phase index ("" if out of range). */

@@ -78,6 +78,8 @@ def load():
         "rhg_build_index": (i32, [P(rhg_params), vp, vp, P(rhg_tuning), vp, C.c_size_t, i32, P(vp), vp]),
         "rhg_count_edges": (i32, [vp, vp, vp]),
         "rhg_emit_edges": (i32, [vp, vp, vp, i64, i32, vp]),
+        "rhg_sort_rows_workspace_bytes": (C.c_size_t, [i64, i64]),
+        "rhg_sort_rows": (i32, [i64, vp, vp, i64, vp, C.c_size_t, vp]),
         "rhg_index_stats": (i32, [vp, P(rhg_stats), vp]),
         "rhg_index_free": (None, [vp]),
         "rhg_generate": (i32, [i64, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
@@ -200,6 +202,27 @@ def rhg_emit_edges(idx: Index, row_ptr, col_idx, canonical_rows: bool = False, s
                                  1 if canonical_rows else 0, _stream(stream)))
 
 
+def rhg_sort_rows_workspace_bytes(n: int, nnz: int) -> int:
+    return int(load().rhg_sort_rows_workspace_bytes(int(n), int(nnz)))
+
+
+def rhg_sort_rows(row_ptr, col_idx, nnz: Optional[int] = None, workspace=None, stream=None):
+    """Sorts every row of the CSR (row_ptr: device int64, n + 1; col_idx:
+    device int32) ascending, in place.  nnz defaults to row_ptr[n] (read
+    back); the workspace defaults to a new device tensor."""
+    import torch
+    assert row_ptr.dtype == torch.int64 and col_idx.dtype == torch.int32
+    assert row_ptr.is_contiguous() and col_idx.is_contiguous()
+    n = row_ptr.numel() - 1
+    if nnz is None:
+        nnz = int(row_ptr[n].item()) - int(row_ptr[0].item()) if n >= 0 else 0
+    nbytes = rhg_sort_rows_workspace_bytes(n, nnz)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=col_idx.device)
+    _check(load().rhg_sort_rows(n, _ptr(row_ptr), _ptr(col_idx), int(nnz), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def rhg_index_stats(idx: Index, stream=None) -> dict:
     st = rhg_stats()
     _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
@@ -207,7 +230,7 @@ def rhg_index_stats(idx: Index, stream=None) -> dict:
             "stage_fallbacks": st.stage_fallbacks, "stored": st.stored}
 
 
-PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count", "scan", "copy", "emit"]
+PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count", "scan", "copy", "emit", "rows"]
 
 
 def rhg_set_profiling(on: bool):
@@ -360,7 +383,8 @@ class Batch:
 
 
 __all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_workspace_bytes",
-           "rhg_build_index", "rhg_count_edges", "rhg_emit_edges", "rhg_index_stats", "rhg_generate",
+           "rhg_build_index", "rhg_count_edges", "rhg_emit_edges", "rhg_sort_rows",
+           "rhg_sort_rows_workspace_bytes", "rhg_index_stats", "rhg_generate",
            "rhg_set_profiling", "rhg_phase_times", "rhg_generate_async", "GraphBuffers", "Batch",
            "expected_col_capacity", "RhgError", "Graph", "Index", "load", "version",
            "LIB_PATH", "PHASES"]

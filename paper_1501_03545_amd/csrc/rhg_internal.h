@@ -14,6 +14,7 @@
 #define RHG_HEAVY_BLOCKS 2048     // workgroups striding over the heavy chunks
 #define RHG_HEAVY_EXTRA_CHUNKS (1 << 20)
 #define RHG_KAP_SUB 4             // expected-degree table points per band
+#define RHG_ROWS_TILE 8192        // LDS tile (entries) of the row sort
 
 namespace rhg {
 
@@ -103,7 +104,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L);
 // Timed phases (rhg_phase_times).
 enum { RHG_PHASE_SAMPLE = 0, RHG_PHASE_SORT = 1, RHG_PHASE_INDEX = 2, RHG_PHASE_GATHER = 3,
        RHG_PHASE_PLAN = 4, RHG_PHASE_COUNT_PASS = 5, RHG_PHASE_SCAN = 6, RHG_PHASE_COPY = 7,
-       RHG_PHASE_EMIT_PASS = 8, RHG_PHASE_COUNT = 9 };
+       RHG_PHASE_EMIT_PASS = 8, RHG_PHASE_ROWS = 9, RHG_PHASE_COUNT = 10 };
 
 // Brackets a phase with HIP events on stream s when profiling is on.
 void *phase_begin(int phase, hipStream_t s);
@@ -150,6 +151,9 @@ struct rhg_index {
     int32_t *stage;        // the neighbour store (stage_cap slots)
     uint8_t *stag;         // the lane of each stored neighbour (stage_cap)
     unsigned long long *stats;  // ST_COUNT counters
+    int32_t *rows_ids;     // row lists of the row sort (n slots; the sort values' buffer, free after the build)
+    void *rows_aux;        // row sort counters and long-row list
+    int64_t rows_lcap;     // long rows the list holds
     void *tmp;             // scratch for sort and scan
     size_t tmp_bytes;
 };
@@ -173,5 +177,14 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
                               uint32_t *v0, uint32_t *v1, int validate, hipStream_t s);
 hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
                          int64_t col_cap = -1, int32_t *overflow = nullptr);
+
+// Row sort (ascending rows, in place).  ids: n int32 slots; aux:
+// rows_aux_bytes(lcap) bytes holding up to lcap rows longer than
+// RHG_ROWS_TILE; rows_long_bound(nnz) is the most such rows nnz entries
+// can form.  maxlen_bound: no row is longer.
+size_t rows_aux_bytes(int64_t lcap);
+int64_t rows_long_bound(int64_t nnz);
+hipError_t launch_sort_rows(const int64_t *row_ptr, int32_t *col, int64_t n, int64_t maxlen_bound, int32_t *ids,
+                            void *aux, int64_t lcap, hipStream_t s);
 
 }  // namespace rhg

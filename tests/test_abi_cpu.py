@@ -97,3 +97,21 @@ def test_workspace_size_is_host_only_and_grows_with_n():
     big = P.rhg_index_workspace_bytes(P.rhg_plan(1_000_000, 10.0, 2.7, 1))
     assert 0 < small < big
     assert big >= 40 * 1_000_000
+
+
+def test_row_sort_workspace_and_argument_checks_are_host_only():
+    import ctypes as C
+    lib = P.load()
+    # ids for n rows + counters + the long-row list (at most nnz / 8193 + 1 rows)
+    assert P.rhg_sort_rows_workspace_bytes(0, 0) > 0
+    a = P.rhg_sort_rows_workspace_bytes(1_000_000, 10_000_000)
+    b = P.rhg_sort_rows_workspace_bytes(1_000_000, 1_000_000_000)
+    assert 4_000_000 <= a < b <= 4_000_000 + 8 * (1_000_000_000 // 8193 + 1) + 1024
+    assert P.rhg_sort_rows_workspace_bytes(-1, 5) == 0
+    fake = C.c_void_p(0x1000)
+    assert lib.rhg_sort_rows(-1, fake, fake, 5, fake, 1 << 20, None) == P.RHG_EINVAL
+    assert lib.rhg_sort_rows(10, fake, fake, -1, fake, 1 << 20, None) == P.RHG_EINVAL
+    assert lib.rhg_sort_rows(10, None, fake, 5, fake, 1 << 20, None) == P.RHG_EINVAL
+    assert lib.rhg_sort_rows(10, fake, fake, 5, fake, 16, None) == P.RHG_ECAPACITY
+    assert lib.rhg_sort_rows(0, None, None, 0, None, 0, None) == P.RHG_OK
+    assert lib.rhg_sort_rows(10, None, None, 0, None, 0, None) == P.RHG_OK

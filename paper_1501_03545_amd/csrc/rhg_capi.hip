@@ -67,7 +67,7 @@ void phase_end(void *rec, hipStream_t s)
 struct WsPlan {
     size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcnt, hitem, hscal, lkap, woff, wflag, stage,
         stag, stats, raux, tmp, total, tmp_bytes;
-    int64_t max_chunks, rows_lcap;
+    int64_t max_chunks, rows_lcap, rows_mapcap, rows_nnz_cap;
 };
 
 static WsPlan ws_plan(int64_t n, const Layout &L)
@@ -110,11 +110,12 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
         t5 = scan_tmp_bytes(nw);
     }
     w.stats = take(ST_COUNT * 8);
-    // canonical rows: the row lists reuse the sort values (free after the
-    // build); the long-row list holds n / 2 rows, enough unless the mean
-    // degree passes 4096
-    w.rows_lcap = (int64_t)(N / 2 + 1);
-    w.raux = take(rows_aux_bytes(w.rows_lcap));
+    // canonical rows: room for the long rows and tiles of a graph of up to
+    // twice the estimated entries (plus 2^23)
+    w.rows_nnz_cap = (int64_t)std::min(9.0e18, 2.0 * L.entries_est + 8388608.0);
+    w.rows_lcap = std::min<int64_t>((int64_t)N, rows_long_bound(w.rows_nnz_cap));
+    w.rows_mapcap = rows_tile_bound(w.rows_nnz_cap, w.rows_lcap);
+    w.raux = take(rows_aux_bytes(w.rows_lcap, w.rows_mapcap));
     size_t t1 = radix_sort_tmp_bytes(n), t2 = scan_tmp_bytes(n + 1);
     size_t t3 = scan_tmp_bytes(w.max_chunks), t4 = scan_tmp_bytes(items > 0 ? items : 1);
     w.tmp_bytes = std::max(std::max(std::max(t1, t2), std::max(t3, t4)), t5);
@@ -256,9 +257,10 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->stage = idx->L.stage ? (int32_t *)(base + w.stage) : nullptr;
     idx->stag = idx->L.stage ? (uint8_t *)(base + w.stag) : nullptr;
     idx->stats = (unsigned long long *)(base + w.stats);
-    idx->rows_ids = (int32_t *)v0;
     idx->rows_aux = base + w.raux;
     idx->rows_lcap = w.rows_lcap;
+    idx->rows_mapcap = w.rows_mapcap;
+    idx->rows_nnz_cap = w.rows_nnz_cap;
     idx->tmp = base + w.tmp;
     idx->tmp_bytes = w.tmp_bytes;
     // the sort's second key/value buffers live in the FP32 record array,
@@ -318,23 +320,25 @@ rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_i
         return fail(RHG_ECAPACITY, "rhg_emit_edges: col_idx holds " + std::to_string(col_capacity) +
                                        " entries, the graph needs " + std::to_string(nnz));
     if (nnz > 0 && !col_idx) return fail(RHG_EINVAL, "rhg_emit_edges: col_idx is NULL");
-    if (canonical_rows && rows_long_bound(nnz) > idx->rows_lcap)
+    if (canonical_rows && nnz > idx->rows_nnz_cap)
         return fail(RHG_ECAPACITY, "rhg_emit_edges: canonical rows of " + std::to_string(nnz) +
-                                       " entries need rhg_sort_rows with its own workspace");
+                                       " entries (over twice the expected count) need rhg_sort_rows");
     if (nnz > 0) RHG_HIP(launch_search(idx, (int64_t *)row_ptr, col_idx, 1, s));
     if (nnz > 0 && canonical_rows) {
         PhaseScope ps(RHG_PHASE_ROWS, s);
-        RHG_HIP(launch_sort_rows(row_ptr, col_idx, idx->n, std::min<int64_t>(nnz, idx->n - 1), idx->rows_ids,
-                                 idx->rows_aux, idx->rows_lcap, s));
+        RHG_HIP(launch_sort_rows(row_ptr, col_idx, idx->n, std::min<int64_t>(nnz, idx->n - 1), idx->rows_aux,
+                                 idx->rows_lcap, idx->rows_mapcap, s));
     }
     return RHG_OK;
 }
 
+static int64_t sort_lcap(int64_t n, int64_t nnz) { return std::min<int64_t>(std::max<int64_t>(n, 1), rows_long_bound(nnz)); }
+
 size_t rhg_sort_rows_workspace_bytes(int64_t n, int64_t nnz)
 {
     if (n < 0 || nnz < 0) return 0;
-    const int64_t lcap = std::min<int64_t>(std::max<int64_t>(n, 1), rows_long_bound(nnz));
-    return align_up((size_t)std::max<int64_t>(n, 1) * 4, 256) + rows_aux_bytes(lcap) + 256;
+    const int64_t lcap = sort_lcap(n, nnz);
+    return rows_aux_bytes(lcap, rows_tile_bound(nnz, lcap)) + 256;
 }
 
 rhg_status rhg_sort_rows(int64_t n, const int64_t *row_ptr, int32_t *col_idx, int64_t nnz, void *workspace,
@@ -346,13 +350,11 @@ rhg_status rhg_sort_rows(int64_t n, const int64_t *row_ptr, int32_t *col_idx, in
     if (!row_ptr || !col_idx || !workspace) return fail(RHG_EINVAL, "rhg_sort_rows: NULL argument");
     if (workspace_bytes < rhg_sort_rows_workspace_bytes(n, nnz))
         return fail(RHG_ECAPACITY, "rhg_sort_rows: workspace smaller than rhg_sort_rows_workspace_bytes");
-    char *base = (char *)align_up((size_t)workspace, 256);
-    int32_t *ids = (int32_t *)base;
-    void *aux = base + align_up((size_t)n * 4, 256);
-    const int64_t lcap = std::min<int64_t>(n, rows_long_bound(nnz));
+    void *aux = (void *)align_up((size_t)workspace, 256);
+    const int64_t lcap = sort_lcap(n, nnz);
     hipStream_t s = (hipStream_t)stream;
     PhaseScope ps(RHG_PHASE_ROWS, s);
-    RHG_HIP(launch_sort_rows(row_ptr, col_idx, n, nnz, ids, aux, lcap, s));
+    RHG_HIP(launch_sort_rows(row_ptr, col_idx, n, nnz, aux, lcap, rows_tile_bound(nnz, lcap), s));
     return RHG_OK;
 }
 

@@ -45,6 +45,7 @@ struct Layout {
     int64_t heavy_cap;                // at most this many heavy queries
     int stage;                        // count pass stores tested neighbours
     int64_t stage_cap;                // int32 slots of the neighbour store
+    double entries_est;               // upper estimate of the graph's entries (2m)
 };
 
 // Expected degree of a point at radius r (threshold model): the other n - 1
@@ -151,9 +152,10 @@ struct rhg_index {
     int32_t *stage;        // the neighbour store (stage_cap slots)
     uint8_t *stag;         // the lane of each stored neighbour (stage_cap)
     unsigned long long *stats;  // ST_COUNT counters
-    int32_t *rows_ids;     // row lists of the row sort (n slots; the sort values' buffer, free after the build)
-    void *rows_aux;        // row sort counters and long-row list
+    void *rows_aux;        // row sort: counters, long-row list, tile map
     int64_t rows_lcap;     // long rows the list holds
+    int64_t rows_mapcap;   // tiles the map holds
+    int64_t rows_nnz_cap;  // canonical rows are sorted here for graphs of up to this many entries
     void *tmp;             // scratch for sort and scan
     size_t tmp_bytes;
 };
@@ -178,13 +180,15 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
 hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
                          int64_t col_cap = -1, int32_t *overflow = nullptr);
 
-// Row sort (ascending rows, in place).  ids: n int32 slots; aux:
-// rows_aux_bytes(lcap) bytes holding up to lcap rows longer than
-// RHG_ROWS_TILE; rows_long_bound(nnz) is the most such rows nnz entries
-// can form.  maxlen_bound: no row is longer.
-size_t rows_aux_bytes(int64_t lcap);
+// Row sort (ascending rows, in place).  aux: rows_aux_bytes(lcap, mapcap)
+// bytes holding counters, up to lcap rows longer than RHG_ROWS_TILE and the
+// map of up to mapcap of their tiles.  For a CSR of nnz entries,
+// rows_long_bound(nnz) long rows and rows_tile_bound(nnz, lcap) tiles are
+// enough.  maxlen_bound: no row is longer.
 int64_t rows_long_bound(int64_t nnz);
-hipError_t launch_sort_rows(const int64_t *row_ptr, int32_t *col, int64_t n, int64_t maxlen_bound, int32_t *ids,
-                            void *aux, int64_t lcap, hipStream_t s);
+int64_t rows_tile_bound(int64_t nnz, int64_t lcap);
+size_t rows_aux_bytes(int64_t lcap, int64_t mapcap);
+hipError_t launch_sort_rows(const int64_t *row_ptr, int32_t *col, int64_t n, int64_t maxlen_bound, void *aux,
+                            int64_t lcap, int64_t mapcap, hipStream_t s);
 
 }  // namespace rhg

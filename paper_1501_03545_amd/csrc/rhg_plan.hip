@@ -212,22 +212,25 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // Neighbour store: per light band sub-interval, the expected points (with
     // a binomial margin) times the slots at its inner edge, where the
     // expected degree is largest.
+    // An upper estimate of the entries of the graph (2m): per band
+    // sub-interval, its expected points times the expected degree at its
+    // inner edge, where the degree is largest.
     L->stage = !(t && t->no_stage) && p.n >= 2;
     L->stage_cap = 0;
-    if (L->stage) {
-        double slots = 0.0;
-        for (int j = jh; j < B; ++j) {
-            for (int sub = 0; sub < RHG_KAP_SUB; ++sub) {
-                const double ra = L->E[j] + (L->E[j + 1] - L->E[j]) * sub / RHG_KAP_SUB;
-                const double rb = L->E[j] + (L->E[j + 1] - L->E[j]) * (sub + 1) / RHG_KAP_SUB;
-                const double pts = n * std::max(0.0, (cosh(a * rb) - cosh(a * ra)) / denom);
-                if (pts <= 0.0) continue;
-                const double k = expected_degree(n, a, R, ra);
-                slots += (pts + 4.0 * sqrt(pts) + 64.0) * (double)stage_slots(k);
-            }
+    double slots = 0.0, entries = 0.0;
+    for (int j = 0; j < B; ++j) {
+        for (int sub = 0; sub < RHG_KAP_SUB; ++sub) {
+            const double ra = L->E[j] + (L->E[j + 1] - L->E[j]) * sub / RHG_KAP_SUB;
+            const double rb = L->E[j] + (L->E[j + 1] - L->E[j]) * (sub + 1) / RHG_KAP_SUB;
+            const double pts = n * std::max(0.0, (cosh(a * rb) - cosh(a * ra)) / denom);
+            if (pts <= 0.0) continue;
+            const double k = expected_degree(n, a, R, ra);
+            entries += pts * k;
+            if (L->stage && j >= jh) slots += (pts + 4.0 * sqrt(pts) + 64.0) * (double)stage_slots(k);
         }
-        L->stage_cap = (int64_t)std::min(1.02 * slots + 4096.0, 9.0e18);
     }
+    L->entries_est = p.n >= 2 ? entries : 0.0;
+    if (L->stage) L->stage_cap = (int64_t)std::min(1.02 * slots + 4096.0, 9.0e18);
 }
 
 }  // namespace rhg

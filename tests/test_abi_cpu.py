@@ -102,11 +102,17 @@ def test_workspace_size_is_host_only_and_grows_with_n():
 def test_row_sort_workspace_and_argument_checks_are_host_only():
     import ctypes as C
     lib = P.load()
-    # ids for n rows + counters + the long-row list (at most nnz / 8193 + 1 rows)
+    # counters + the list of rows over 8192 entries (at most nnz / 8193 + 1,
+    # and at most n) + the map of their 8192-entry tiles
+    def bound(n, nnz):
+        lcap = min(max(n, 1), nnz // 8193 + 1)
+        return 256 + 8 * lcap + 8 * (nnz // 8192 + lcap + 1) + 512
     assert P.rhg_sort_rows_workspace_bytes(0, 0) > 0
     a = P.rhg_sort_rows_workspace_bytes(1_000_000, 10_000_000)
     b = P.rhg_sort_rows_workspace_bytes(1_000_000, 1_000_000_000)
-    assert 4_000_000 <= a < b <= 4_000_000 + 8 * (1_000_000_000 // 8193 + 1) + 1024
+    c = P.rhg_sort_rows_workspace_bytes(10, 10_000_000)  # ten rows of 10^6
+    assert 8 * (10_000_000 // 8192) < a < b <= bound(1_000_000, 1_000_000_000)
+    assert a <= bound(1_000_000, 10_000_000) and 8 * (10_000_000 // 8192) < c <= bound(10, 10_000_000)
     assert P.rhg_sort_rows_workspace_bytes(-1, 5) == 0
     fake = C.c_void_p(0x1000)
     assert lib.rhg_sort_rows(-1, fake, fake, 5, fake, 1 << 20, None) == P.RHG_EINVAL

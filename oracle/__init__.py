@@ -68,6 +68,8 @@ def _load():
         lib.orc_is_edge.argtypes = [d, d, d, d, d, pi64]
         lib.orc_is_edge_quad.restype = i32
         lib.orc_is_edge_quad.argtypes = [d, d, d, d, d]
+        lib.orc_is_edge_literal.restype = i32
+        lib.orc_is_edge_literal.argtypes = [d, d, d, d, d]
         lib.orc_degrees.argtypes = [i64, pd, pd, d, pi32, i32, pi64]
         lib.orc_csr_fill.argtypes = [i64, pd, pd, d, pi64, pi32, i32]
         lib.orc_rows.restype = i64
@@ -148,6 +150,12 @@ def is_edge(ri, ti, rj, tj, R):
     st = np.zeros(2, dtype=np.int64)
     e = _load().orc_is_edge(ri, ti, rj, tj, R, _p(st, C.c_int64))
     return bool(e), int(st[0]), int(st[1])
+
+
+def is_edge_literal(ri, ti, rj, tj, R):
+    """The printed cosh-distance law evaluated literally in binary64
+    (diagnostic: it loses the decision near the rim at large R)."""
+    return bool(_load().orc_is_edge_literal(ri, ti, rj, tj, R))
 
 
 def is_edge_quad(ri, ti, rj, tj, R):

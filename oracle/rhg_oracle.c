@@ -266,6 +266,18 @@ int orc_is_edge(double ri, double ti, double rj, double tj, double R, int64_t st
     return e;
 }
 
+/* The distance law as printed, evaluated literally in binary64:
+ *   cosh r_i cosh r_j - sinh r_i sinh r_j cos(theta_i - theta_j) <= cosh R.
+ * Diagnostic only, never used for a decision: near the rim both products
+ * are about e^{r_i + r_j} / 4 while their difference is about cosh R, so the
+ * cancellation leaves an error of the order of cosh R itself at large R.
+ * A test shows how often it disagrees with the exact relation. */
+int orc_is_edge_literal(double ri, double ti, double rj, double tj, double R)
+{
+    const double lhs = cosh(ri) * cosh(rj) - sinh(ri) * sinh(rj) * cos(ti - tj);
+    return lhs <= orc_cosh(R);
+}
+
 /* Binary128-only decision, for tests of the binary64 screen. */
 int orc_is_edge_quad(double ri, double ti, double rj, double tj, double R)
 {

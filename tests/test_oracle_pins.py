@@ -258,6 +258,29 @@ def test_edge_decision_equals_poincare_metric_near_threshold(cfg, rim):
         assert O.is_edge(r2, t2, r1, t1, R)[0] == e
 
 
+def test_literal_distance_law_loses_rim_decisions_that_the_oracle_keeps():
+    """Why the oracle decides on the rewritten (non-negative sum) form: the
+    printed law evaluated literally in binary64 cancels two products of
+    about e^{2r}/4 down to cosh R, so its error grows like e^R ulp.  On rim
+    pairs placed 1e-3 .. 1e-14 (relative) from the threshold it gets a
+    growing share wrong as R grows, while the oracle's decision matches
+    100-digit arithmetic on every pair at every radius."""
+    mp.mp.dps = 100
+    wrong = {}
+    for name, cfg in (("C1", C1), ("C3", C3)):
+        a, R = O.solve_R(*cfg)
+        rng = np.random.default_rng(29)
+        wrong_lit = wrong_orc = total = 0
+        for (r1, t1, r2, t2) in _near_threshold_pairs(R, rng, 150, rim=True):
+            ref = _mp_dist_poincare(r1, t1, r2, t2) <= mp.mpf(R)
+            wrong_orc += O.is_edge(r1, t1, r2, t2, R)[0] != ref
+            wrong_lit += O.is_edge_literal(r1, t1, r2, t2, R) != ref
+            total += 1
+        assert wrong_orc == 0, name
+        wrong[name] = wrong_lit
+    assert wrong["C3"] >= 150 // 4 and wrong["C3"] > 1.5 * wrong["C1"], wrong
+
+
 def test_edge_decision_equals_proposition1_circle():
     """Algorithm 1's range query: w is a neighbour of v iff w's Poincare image
     lies in the Euclidean circle of Proposition 1 around v's image."""

@@ -70,6 +70,7 @@ def _load():
         lib.orc_is_edge_quad.argtypes = [d, d, d, d, d]
         lib.orc_is_edge_literal.restype = i32
         lib.orc_is_edge_literal.argtypes = [d, d, d, d, d]
+        lib.orc_lr_candidates.argtypes = [u64, i64, i64, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         lib.orc_degrees.argtypes = [i64, pd, pd, d, pi32, i32, pi64]
         lib.orc_csr_fill.argtypes = [i64, pd, pd, d, pi64, pi32, i32]
         lib.orc_rows.restype = i64
@@ -217,3 +218,68 @@ def generate(n: int, kbar: float, gamma: float, seed: int, nthreads: int = 0):
     r, t, hard = sample(seed, a, R, n, nthreads=nthreads)
     row_ptr, col, nq, nt = csr(r, t, R, nthreads)
     return a, R, r, t, row_ptr, col, {"near_midpoint": hard, "quad": nq, "ties": nt}
+
+
+# --------------------------------------------------------------------------
+# Long-range augmentation (RHG-LR): the paper adds a small share (0.5 % in
+# its experiment) of edges between vertex pairs drawn uniformly at random
+# to correct the diameter (Sec. 4.2, comparison with real-world networks;
+# RHG-LR in the generator table of Sec. 4.3; Appendix I).  Definition used
+# here, in plain sequential form:
+#   candidate j = 0, 1, 2, ... is the pair orc_lr_candidates(seed, j);
+#   it is rejected if it is a self-loop, an edge of the graph, or a pair an
+#   earlier candidate already added; the first k accepted are added, and at
+#   most the candidates j < 2k + 4096 are drawn (fewer than k are added only
+#   when more than half of the drawn pairs are rejected, i.e. in very dense
+#   or tiny graphs).
+# --------------------------------------------------------------------------
+
+def lr_candidates(seed: int, j0: int, count: int, n: int):
+    lib = _load()
+    a = np.empty(max(count, 0), dtype=np.int64)
+    b = np.empty(max(count, 0), dtype=np.int64)
+    if count > 0:
+        lib.orc_lr_candidates(seed, j0, count, n, _p(a, C.c_int64), _p(b, C.c_int64))
+    return a, b
+
+
+def lr_draw_limit(k: int) -> int:
+    return 2 * k + 4096
+
+
+def lr_added_pairs(n: int, row_ptr, col, k: int, seed: int):
+    """The accepted candidates, in order, as a list of (a, b), a < b."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    edges = set((src * n + col).tolist())
+    seen, added = set(), []
+    ca, cb = lr_candidates(seed, 0, lr_draw_limit(k), n)
+    for a, b in zip(ca.tolist(), cb.tolist()):
+        if len(added) == k:
+            break
+        key = a * n + b
+        if a == b or key in edges or key in seen:
+            continue
+        seen.add(key)
+        added.append((a, b))
+    return added
+
+
+def lr_augment(n: int, row_ptr, col, k: int, seed: int):
+    """The augmented CSR: each row is the given row followed by its added
+    neighbours in the order their pairs were accepted."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col)
+    extra = [[] for _ in range(n)]
+    added = lr_added_pairs(n, row_ptr, col, k, seed)
+    for a, b in added:
+        extra[a].append(b)
+        extra[b].append(a)
+    out_ptr = np.zeros(n + 1, dtype=np.int64)
+    out = []
+    for v in range(n):
+        out.extend(col[row_ptr[v]:row_ptr[v + 1]].tolist())
+        out.extend(extra[v])
+        out_ptr[v + 1] = len(out)
+    return out_ptr, np.asarray(out, dtype=np.int32), len(added)

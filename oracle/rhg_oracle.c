@@ -355,3 +355,31 @@ int64_t orc_rows(int64_t n, const double *r, const double *theta, double R,
 }
 
 int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------ */
+/* Long-range augmentation (RHG-LR: Sec. 4.2, the generator table of   */
+/* Sec. 4.3, Appendix I): a small share of extra edges between          */
+/* uniformly chosen vertex pairs.                                       */
+/* ------------------------------------------------------------------ */
+
+/* Candidate pair j of the augmentation: Philox4x32-10 with the vertex
+ * key (seed_lo, seed_hi) and counter (j_lo, j_hi, 1, 0) -- the third word 1
+ * keeps these draws apart from the points' (third word 0).  Each 64-bit
+ * word w = (x1:x0), (x3:x2) picks a vertex floor(w * n / 2^64); the pair is
+ * returned as (min, max).  The paper fixes no generator or pair law beyond
+ * "uniformly at random". */
+void orc_lr_candidates(uint64_t seed, int64_t j0, int64_t count, int64_t n, int64_t *a, int64_t *b)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t c = 0; c < count; ++c) {
+        const uint64_t j = (uint64_t)(j0 + c);
+        const uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), 1u, 0u};
+        uint32_t x[4];
+        orc_philox4x32_10(ctr, key, x);
+        const uint64_t w0 = ((uint64_t)x[1] << 32) | x[0], w1 = ((uint64_t)x[3] << 32) | x[2];
+        const uint64_t u = (uint64_t)(((unsigned __int128)w0 * (uint64_t)n) >> 64);
+        const uint64_t v = (uint64_t)(((unsigned __int128)w1 * (uint64_t)n) >> 64);
+        a[c] = (int64_t)(u < v ? u : v);
+        b[c] = (int64_t)(u < v ? v : u);
+    }
+}

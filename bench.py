@@ -120,8 +120,24 @@ def run_gpu(cfg, steps, warmup, tuning=None):
         e1.record(stream)
         torch.cuda.synchronize()
         rows_ms.append(e0.elapsed_time(e1))
+    # long-range augmentation (RHG-LR) of the same graph: 0.5 % extra edges
+    k_lr = P.long_range_count(nnz // 2)
+    lr_ws = torch.empty(P.rhg_long_range_workspace_bytes(n, k_lr), dtype=torch.uint8, device=dev)
+    lr_out = (torch.empty(n + 1, dtype=torch.int64, device=dev),
+              torch.empty(nnz + 2 * k_lr, dtype=torch.int32, device=dev))
+    lr_ms = []
+    for rep in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, _, added = P.rhg_long_range(row_ptr, col[:nnz], k_lr, cfg["seed"], nnz=nnz, workspace=lr_ws, out=lr_out,
+                                       stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lr_ms.append(e0.elapsed_time(e1))
+    lr = {"k": k_lr, "added": int(added.item()), "ms": min(lr_ms)}
+    del lr_ws, lr_out
     return dict(ms_per_step=(t1 - t0) * 1000.0 / steps, nnz=nnz, phases=phases, stats=stats,
-                params=p, rows_ms=min(rows_ms))
+                params=p, rows_ms=min(rows_ms), lr=lr)
 
 
 def run_batch(count, reps, tuned=True, n_streams=64):
@@ -326,6 +342,8 @@ def main():
         "phases_ms": {k: round(v[0] * v[1] / args.steps, 4) for k, v in phases.items() if v[1]},
         "canonical_rows": {"ms": res["rows_ms"], "form": "rhg_sort_rows on the emitted CSR (ascending rows), "
                            "timed apart from the step and not in value"},
+        "long_range": dict(res["lr"], form="rhg_long_range: ceil(0.005 m) random extra edges merged into the "
+                           "emitted CSR (RHG-LR), timed apart from the step and not in value"),
         "pipeline_floor_frac": (56 * n + 8 * m) / sec / 1e9 / HBM_PEAK_GBS,
         "search_stats": res["stats"],
     }

@@ -202,6 +202,37 @@ size_t rhg_sort_rows_workspace_bytes(int64_t n, int64_t nnz);
 rhg_status rhg_sort_rows(int64_t n, const int64_t *row_ptr, int32_t *col_idx, int64_t nnz,
                          void *workspace, size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------ */
+/* Long-range augmentation (RHG-LR).                                   */
+/* ------------------------------------------------------------------ */
+
+/* Adds k random edges to a graph, as the paper does to correct the
+ * diameter of random hyperbolic graphs (0.5 % of the edges in its
+ * experiment: Sec. 4.2; the RHG-LR row of the generator table, Sec. 4.3;
+ * Appendix I).  Candidate j = 0, 1, 2, ... is the vertex pair
+ * (floor(w0 n / 2^64), floor(w1 n / 2^64)) for the words w0 = (x1:x0),
+ * w1 = (x3:x2) of the Philox4x32-10 block with counter (j_lo, j_hi, 1, 0)
+ * and key (seed_lo, seed_hi).  A candidate is rejected if it is a self-loop,
+ * an edge of the input, or a pair an earlier candidate gave; the first k
+ * accepted pairs are added, drawing at most the candidates j < 2k + 4096
+ * (so fewer than k are added only when over half of those pairs are
+ * rejected, in very dense or tiny graphs).
+ * Input: row_ptr (device, n + 1 int64, row_ptr[0] = 0), col_idx (device,
+ * nnz = row_ptr[n] int32 entries, a simple symmetric graph in any row
+ * order).  Output: row_ptr_out (device, n + 1), col_out (device,
+ * col_out_capacity >= nnz + 2k int32 slots): every input row, unchanged,
+ * followed by its added neighbours in the order their pairs were accepted;
+ * *added (device int64) = the number of added edges.  workspace: device,
+ * rhg_long_range_workspace_bytes(n, k) bytes (about 40 B per candidate
+ * plus 48 B per added edge).  Asynchronous, no allocation.
+ * Errors: RHG_EINVAL for n < 0, n > 2^31 - 1, nnz < 0, k < 0,
+ * k > (2^31 - 4097) / 2 or a NULL pointer; RHG_ECAPACITY for a small
+ * col_out or workspace. */
+size_t rhg_long_range_workspace_bytes(int64_t n, int64_t k);
+rhg_status rhg_long_range(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int64_t nnz, int64_t k,
+                          uint64_t seed, void *workspace, size_t workspace_bytes, int64_t *row_ptr_out,
+                          int32_t *col_out, int64_t col_out_capacity, int64_t *added, void *stream);
+
 /* Diagnostics accumulated by the count and emit passes (synchronises). */
 rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out /* host */, void *stream);
 

@@ -252,14 +252,15 @@ def lr_added_pairs(n: int, row_ptr, col, k: int, seed: int):
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
-    edges = set((src * n + col).tolist())
-    seen, added = set(), []
     ca, cb = lr_candidates(seed, 0, lr_draw_limit(k), n)
-    for a, b in zip(ca.tolist(), cb.tolist()):
+    # membership of every candidate in the graph (ordered pairs a < b)
+    in_graph = np.isin(ca * n + cb, src * n + col)
+    seen, added = set(), []
+    for a, b, e in zip(ca.tolist(), cb.tolist(), in_graph.tolist()):
         if len(added) == k:
             break
         key = a * n + b
-        if a == b or key in edges or key in seen:
+        if a == b or e or key in seen:
             continue
         seen.add(key)
         added.append((a, b))
@@ -270,16 +271,23 @@ def lr_augment(n: int, row_ptr, col, k: int, seed: int):
     """The augmented CSR: each row is the given row followed by its added
     neighbours in the order their pairs were accepted."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
-    col = np.asarray(col)
-    extra = [[] for _ in range(n)]
+    col = np.asarray(col, dtype=np.int32)
     added = lr_added_pairs(n, row_ptr, col, k, seed)
+    extra = {}
     for a, b in added:
-        extra[a].append(b)
-        extra[b].append(a)
+        extra.setdefault(a, []).append(b)
+        extra.setdefault(b, []).append(a)
+    cnt = np.zeros(n, dtype=np.int64)
+    for v, lst in extra.items():
+        cnt[v] = len(lst)
     out_ptr = np.zeros(n + 1, dtype=np.int64)
-    out = []
-    for v in range(n):
-        out.extend(col[row_ptr[v]:row_ptr[v + 1]].tolist())
-        out.extend(extra[v])
-        out_ptr[v + 1] = len(out)
-    return out_ptr, np.asarray(out, dtype=np.int32), len(added)
+    np.cumsum(np.diff(row_ptr) + cnt, out=out_ptr[1:])
+    out = np.empty(int(out_ptr[-1]), dtype=np.int32)
+    # every row: its old entries, then its added neighbours
+    shift = out_ptr[:-1] - row_ptr[:-1]
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    out[np.arange(col.size, dtype=np.int64) + shift[src]] = col
+    for v, lst in extra.items():
+        end = out_ptr[v] + (row_ptr[v + 1] - row_ptr[v])
+        out[end:end + len(lst)] = lst
+    return out_ptr, out, len(added)

@@ -80,6 +80,8 @@ def load():
         "rhg_emit_edges": (i32, [vp, vp, vp, i64, i32, vp]),
         "rhg_sort_rows_workspace_bytes": (C.c_size_t, [i64, i64]),
         "rhg_sort_rows": (i32, [i64, vp, vp, i64, vp, C.c_size_t, vp]),
+        "rhg_long_range_workspace_bytes": (C.c_size_t, [i64, i64]),
+        "rhg_long_range": (i32, [i64, vp, vp, i64, i64, u64, vp, C.c_size_t, vp, vp, i64, vp, vp]),
         "rhg_index_stats": (i32, [vp, P(rhg_stats), vp]),
         "rhg_index_free": (None, [vp]),
         "rhg_generate": (i32, [i64, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
@@ -221,6 +223,39 @@ def rhg_sort_rows(row_ptr, col_idx, nnz: Optional[int] = None, workspace=None, s
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=col_idx.device)
     _check(load().rhg_sort_rows(n, _ptr(row_ptr), _ptr(col_idx), int(nnz), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def rhg_long_range_workspace_bytes(n: int, k: int) -> int:
+    return int(load().rhg_long_range_workspace_bytes(int(n), int(k)))
+
+
+def long_range_count(m: int, fraction: float = 0.005) -> int:
+    """k for a share `fraction` of m undirected edges: ceil(fraction * m)."""
+    import math
+    return int(math.ceil(fraction * m))
+
+
+def rhg_long_range(row_ptr, col_idx, k: int, seed: int, nnz: Optional[int] = None, workspace=None,
+                   out=None, stream=None):
+    """Adds k random edges (see rhg.h).  Returns (row_ptr_out, col_out,
+    added) with `added` a device int64 tensor of one entry."""
+    import torch
+    assert row_ptr.dtype == torch.int64 and col_idx.dtype == torch.int32
+    n = row_ptr.numel() - 1
+    if nnz is None:
+        nnz = int(row_ptr[n].item())
+    dev = row_ptr.device
+    if workspace is None:
+        workspace = torch.empty(max(rhg_long_range_workspace_bytes(n, k), 1), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = (torch.empty(n + 1, dtype=torch.int64, device=dev),
+               torch.empty(max(nnz + 2 * k, 1), dtype=torch.int32, device=dev))
+    rp_out, col_out = out
+    added = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(load().rhg_long_range(n, _ptr(row_ptr), _ptr(col_idx), int(nnz), int(k), int(seed), _ptr(workspace),
+                                 workspace.numel(), _ptr(rp_out), _ptr(col_out), col_out.numel(), _ptr(added),
+                                 _stream(stream)))
+    return rp_out, col_out, added
 
 
 def rhg_index_stats(idx: Index, stream=None) -> dict:
@@ -384,7 +419,8 @@ class Batch:
 
 __all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_workspace_bytes",
            "rhg_build_index", "rhg_count_edges", "rhg_emit_edges", "rhg_sort_rows",
-           "rhg_sort_rows_workspace_bytes", "rhg_index_stats", "rhg_generate",
+           "rhg_sort_rows_workspace_bytes", "rhg_long_range", "rhg_long_range_workspace_bytes",
+           "long_range_count", "rhg_index_stats", "rhg_generate",
            "rhg_set_profiling", "rhg_phase_times", "rhg_generate_async", "GraphBuffers", "Batch",
            "expected_col_capacity", "RhgError", "Graph", "Index", "load", "version",
            "LIB_PATH", "PHASES"]

@@ -358,6 +358,32 @@ rhg_status rhg_sort_rows(int64_t n, const int64_t *row_ptr, int32_t *col_idx, in
     return RHG_OK;
 }
 
+size_t rhg_long_range_workspace_bytes(int64_t n, int64_t k)
+{
+    if (n < 0 || k < 0 || k > (INT32_MAX - 4096) / 2) return 0;
+    return lr_workspace_bytes(n, k);
+}
+
+rhg_status rhg_long_range(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int64_t nnz, int64_t k,
+                          uint64_t seed, void *workspace, size_t workspace_bytes, int64_t *row_ptr_out,
+                          int32_t *col_out, int64_t col_out_capacity, int64_t *added, void *stream)
+{
+    g_last_error.clear();
+    if (n < 0 || n > (int64_t)INT32_MAX || nnz < 0) return fail(RHG_EINVAL, "rhg_long_range: bad n or nnz");
+    if (k < 0 || k > (INT32_MAX - 4096) / 2) return fail(RHG_EINVAL, "rhg_long_range: k out of range");
+    if (!row_ptr || !row_ptr_out || !added || !workspace || (nnz > 0 && !col_idx) ||
+        (nnz + 2 * k > 0 && !col_out))
+        return fail(RHG_EINVAL, "rhg_long_range: NULL argument");
+    if (col_out_capacity < nnz + 2 * k)
+        return fail(RHG_ECAPACITY, "rhg_long_range: col_out holds " + std::to_string(col_out_capacity) +
+                                       " entries, nnz + 2k = " + std::to_string(nnz + 2 * k));
+    if (workspace_bytes < lr_workspace_bytes(n, k))
+        return fail(RHG_ECAPACITY, "rhg_long_range: workspace smaller than rhg_long_range_workspace_bytes");
+    RHG_HIP(launch_long_range(n, row_ptr, col_idx, nnz, k, seed, workspace, row_ptr_out, col_out, added,
+                              (hipStream_t)stream));
+    return RHG_OK;
+}
+
 rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
 {
     g_last_error.clear();

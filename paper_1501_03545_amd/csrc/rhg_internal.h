@@ -191,4 +191,10 @@ size_t rows_aux_bytes(int64_t lcap, int64_t mapcap);
 hipError_t launch_sort_rows(const int64_t *row_ptr, int32_t *col, int64_t n, int64_t maxlen_bound, void *aux,
                             int64_t lcap, int64_t mapcap, hipStream_t s);
 
+// Long-range augmentation: k extra edges, workspace of lr_workspace_bytes.
+size_t lr_workspace_bytes(int64_t n, int64_t k);
+hipError_t launch_long_range(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t nnz, int64_t k,
+                             uint64_t seed, void *workspace, int64_t *row_ptr_out, int32_t *col_out, int64_t *added,
+                             hipStream_t s);
+
 }  // namespace rhg

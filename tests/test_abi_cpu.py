@@ -121,3 +121,23 @@ def test_row_sort_workspace_and_argument_checks_are_host_only():
     assert lib.rhg_sort_rows(10, fake, fake, 5, fake, 16, None) == P.RHG_ECAPACITY
     assert lib.rhg_sort_rows(0, None, None, 0, None, 0, None) == P.RHG_OK
     assert lib.rhg_sort_rows(10, None, None, 0, None, 0, None) == P.RHG_OK
+
+
+def test_long_range_workspace_and_argument_checks_are_host_only():
+    import ctypes as C
+    lib = P.load()
+    a = P.rhg_long_range_workspace_bytes(10**6, 25_000)
+    b = P.rhg_long_range_workspace_bytes(10**6, 250_000)
+    assert 0 < a < b
+    # about 40 B per candidate (2k + 4096 of them, hash table at load <= 1/2)
+    # and 48 B per added edge
+    J = 2 * 250_000 + 4096
+    assert b <= 60 * J + 48 * 250_000 + 16384
+    assert P.rhg_long_range_workspace_bytes(-1, 5) == 0 and P.rhg_long_range_workspace_bytes(5, -1) == 0
+    fake = C.c_void_p(0x1000)
+    big = 1 << 30
+    assert lib.rhg_long_range(-1, fake, fake, 0, 1, 1, fake, big, fake, fake, 10, fake, None) == P.RHG_EINVAL
+    assert lib.rhg_long_range(10, fake, fake, 0, -1, 1, fake, big, fake, fake, 10, fake, None) == P.RHG_EINVAL
+    assert lib.rhg_long_range(10, None, fake, 0, 1, 1, fake, big, fake, fake, 10, fake, None) == P.RHG_EINVAL
+    assert lib.rhg_long_range(10, fake, fake, 20, 5, 1, fake, big, fake, fake, 29, fake, None) == P.RHG_ECAPACITY
+    assert lib.rhg_long_range(10, fake, fake, 20, 5, 1, fake, 64, fake, fake, 30, fake, None) == P.RHG_ECAPACITY

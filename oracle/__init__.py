@@ -291,3 +291,63 @@ def lr_augment(n: int, row_ptr, col, k: int, seed: int):
         end = out_ptr[v] + (row_ptr[v + 1] - row_ptr[v])
         out[end:end + len(lst)] = lst
     return out_ptr, out, len(added)
+
+
+# --------------------------------------------------------------------------
+# Graph statistics used to validate generated graphs (Sec. 4.1): the degree
+# distribution and its power-law exponent, degree assortativity, and the
+# clustering coefficient as the fraction of closed triangles to triads
+# (paths of length 2).  Plain numpy / scipy on the host.
+# --------------------------------------------------------------------------
+
+def graph_stats(row_ptr, col, kmin: float = 10.0, triangles: bool = True) -> dict:
+    """row_ptr, col: a simple symmetric CSR.  Returns
+      hist[b]: vertices of degree 0 (b = 0) and of degree in [2^(b-1), 2^b)
+               (b = 1 .. 32);
+      gamma_mle: the discrete power-law maximum-likelihood exponent of the
+               degrees k >= kmin in its usual approximation,
+               1 + N / sum ln(k / (kmin - 1/2)) (Clauset, Shalizi, Newman,
+               "Power-law distributions in empirical data", 2009);
+      assortativity: Pearson correlation of the degrees at the two ends of
+               the edges (Newman 2002), over both directions of every edge;
+      triangles, triads = sum C(d, 2), transitivity = 3 triangles / triads,
+      avg_local_clustering: mean over vertices of degree >= 2 of
+               t(v) / C(d(v), 2), t(v) the triangles through v."""
+    import scipy.sparse as sp
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    n = row_ptr.shape[0] - 1
+    deg = np.diff(row_ptr)
+    out = {"n": n, "nnz": int(row_ptr[-1]), "max_degree": int(deg.max()) if n else 0}
+    hist = np.zeros(33, dtype=np.int64)
+    hist[0] = int(np.sum(deg == 0))
+    pos = deg[deg > 0]
+    b = np.floor(np.log2(pos.astype(np.float64))).astype(np.int64) + 1 if pos.size else pos
+    np.add.at(hist, b, 1)
+    out["hist"] = hist
+    tail = deg[deg >= kmin].astype(np.float64)
+    out["tail_count"] = int(tail.size)
+    out["gamma_mle"] = float(1.0 + tail.size / np.sum(np.log(tail / (kmin - 0.5)))) if tail.size else float("nan")
+    src = np.repeat(np.arange(n, dtype=np.int64), deg)
+    x = deg[src].astype(np.float64)
+    y = deg[col].astype(np.float64)
+    if x.size:
+        mx = x.mean()
+        var = (x * x).mean() - mx * mx
+        out["assortativity"] = float(((x * y).mean() - mx * y.mean()) / var) if var > 0 else float("nan")
+    else:
+        out["assortativity"] = float("nan")
+    d = deg.astype(np.int64)
+    triads = int(np.sum(d * (d - 1) // 2))
+    out["triads"] = triads
+    if triangles:
+        A = sp.csr_matrix((np.ones(col.size, dtype=np.int64), col, row_ptr), shape=(n, n))
+        # t(v) = (1/2) sum_{u,w} A_vu A_uw A_wv
+        t = np.asarray((A @ A).multiply(A).sum(axis=1)).ravel() // 2
+        T = int(t.sum()) // 3
+        out["triangles"] = T
+        out["transitivity"] = 3.0 * T / triads if triads else float("nan")
+        ok = d >= 2
+        out["avg_local_clustering"] = float(np.mean(t[ok] / (d[ok] * (d[ok] - 1) / 2.0))) if ok.any() else float("nan")
+        out["vertex_triangles"] = t
+    return out

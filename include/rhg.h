@@ -233,6 +233,47 @@ rhg_status rhg_long_range(int64_t n, const int64_t *row_ptr, const int32_t *col_
                           uint64_t seed, void *workspace, size_t workspace_bytes, int64_t *row_ptr_out,
                           int32_t *col_out, int64_t col_out_capacity, int64_t *added, void *stream);
 
+/* ------------------------------------------------------------------ */
+/* Validation statistics (Sec. 4.1).                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n, nnz;
+    int64_t max_degree;
+    int64_t hist[33];            /* [0]: degree 0; [b]: degree in [2^(b-1), 2^b)  */
+    double kmin;                 /* the power-law fit uses degrees >= kmin        */
+    int64_t tail_count;          /* vertices of degree >= kmin                    */
+    double gamma_mle;            /* 1 + tail / sum ln(d / (kmin - 1/2)); NaN if no tail */
+    double assortativity;        /* degree correlation over edge ends; NaN if undefined */
+    int64_t triads;              /* sum over vertices of d (d - 1) / 2            */
+    int64_t triangles;           /* -1 when not counted                           */
+    double transitivity;         /* 3 triangles / triads (NaN if not counted)     */
+    double avg_local_clustering; /* mean of t(v) / C(d, 2) over degree >= 2       */
+    int32_t ascending_rows;      /* 1 if every row is strictly ascending          */
+    int32_t reserved;
+} rhg_graph_summary;
+
+/* Statistics of a simple symmetric CSR (row_ptr: device n + 1 int64 with
+ * row_ptr[0] = 0, col_idx: device nnz = row_ptr[n] int32), the properties
+ * the paper reports for generated graphs (Sec. 4.1): the degree histogram;
+ * the power-law exponent of the degrees >= kmin by the usual discrete
+ * maximum-likelihood approximation (Clauset, Shalizi and Newman, 2009);
+ * degree assortativity (Newman, 2002) over both directions of every edge;
+ * and, when `triangles` is set, the triangles, the clustering coefficient
+ * as the fraction of closed triangles to triads, and the average local
+ * clustering.  Triangles need ascending rows (canonical rows): otherwise
+ * the other fields are filled and RHG_EINVAL is returned.  Floating-point
+ * sums are reduced in a fixed order (the same result on every run).
+ * workspace: device, rhg_graph_stats_workspace_bytes(n, nnz, triangles)
+ * bytes (about 4n, plus 14 B per entry and 20n with triangles).
+ * Synchronises; *out is host memory.
+ * Errors: RHG_EINVAL for n < 0, n > 2^31 - 1, nnz < 0, kmin < 1 or a NULL
+ * pointer; RHG_ECAPACITY for a small workspace. */
+size_t rhg_graph_stats_workspace_bytes(int64_t n, int64_t nnz, int triangles);
+rhg_status rhg_graph_stats(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int64_t nnz, double kmin,
+                           int triangles, void *workspace, size_t workspace_bytes, rhg_graph_summary *out,
+                           void *stream);
+
 /* Diagnostics accumulated by the count and emit passes (synchronises). */
 rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out /* host */, void *stream);
 

@@ -45,6 +45,14 @@ class rhg_stats(C.Structure):
                 ("stage_fallbacks", C.c_int64), ("stored", C.c_int64)]
 
 
+class rhg_graph_summary(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("max_degree", C.c_int64), ("hist", C.c_int64 * 33),
+                ("kmin", C.c_double), ("tail_count", C.c_int64), ("gamma_mle", C.c_double),
+                ("assortativity", C.c_double), ("triads", C.c_int64), ("triangles", C.c_int64),
+                ("transitivity", C.c_double), ("avg_local_clustering", C.c_double),
+                ("ascending_rows", C.c_int32), ("reserved", C.c_int32)]
+
+
 class rhg_csr(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
                 ("r", C.c_void_p), ("theta", C.c_void_p), ("params", rhg_params)]
@@ -81,6 +89,8 @@ def load():
         "rhg_sort_rows_workspace_bytes": (C.c_size_t, [i64, i64]),
         "rhg_sort_rows": (i32, [i64, vp, vp, i64, vp, C.c_size_t, vp]),
         "rhg_long_range_workspace_bytes": (C.c_size_t, [i64, i64]),
+        "rhg_graph_stats_workspace_bytes": (C.c_size_t, [i64, i64, i32]),
+        "rhg_graph_stats": (i32, [i64, vp, vp, i64, d, i32, vp, C.c_size_t, P(rhg_graph_summary), vp]),
         "rhg_long_range": (i32, [i64, vp, vp, i64, i64, u64, vp, C.c_size_t, vp, vp, i64, vp, vp]),
         "rhg_index_stats": (i32, [vp, P(rhg_stats), vp]),
         "rhg_index_free": (None, [vp]),
@@ -258,6 +268,30 @@ def rhg_long_range(row_ptr, col_idx, k: int, seed: int, nnz: Optional[int] = Non
     return rp_out, col_out, added
 
 
+def rhg_graph_stats_workspace_bytes(n: int, nnz: int, triangles: bool = True) -> int:
+    return int(load().rhg_graph_stats_workspace_bytes(int(n), int(nnz), 1 if triangles else 0))
+
+
+def rhg_graph_stats(row_ptr, col_idx, kmin: float = 10.0, triangles: bool = True, nnz: Optional[int] = None,
+                    workspace=None, stream=None) -> dict:
+    """Validation statistics of a simple symmetric CSR (see rhg.h); triangles
+    need ascending rows.  Synchronises."""
+    import torch
+    assert row_ptr.dtype == torch.int64 and col_idx.dtype == torch.int32
+    n = row_ptr.numel() - 1
+    if nnz is None:
+        nnz = int(row_ptr[n].item())
+    if workspace is None:
+        workspace = torch.empty(rhg_graph_stats_workspace_bytes(n, nnz, triangles), dtype=torch.uint8,
+                                device=row_ptr.device)
+    out = rhg_graph_summary()
+    _check(load().rhg_graph_stats(n, _ptr(row_ptr), _ptr(col_idx), int(nnz), float(kmin), 1 if triangles else 0,
+                                  _ptr(workspace), workspace.numel(), C.byref(out), _stream(stream)))
+    res = {f: getattr(out, f) for f, _ in rhg_graph_summary._fields_ if f not in ("hist", "reserved")}
+    res["hist"] = list(out.hist)
+    return res
+
+
 def rhg_index_stats(idx: Index, stream=None) -> dict:
     st = rhg_stats()
     _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
@@ -420,7 +454,8 @@ class Batch:
 __all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_workspace_bytes",
            "rhg_build_index", "rhg_count_edges", "rhg_emit_edges", "rhg_sort_rows",
            "rhg_sort_rows_workspace_bytes", "rhg_long_range", "rhg_long_range_workspace_bytes",
-           "long_range_count", "rhg_index_stats", "rhg_generate",
+           "long_range_count", "rhg_graph_stats", "rhg_graph_stats_workspace_bytes", "rhg_index_stats",
+           "rhg_generate",
            "rhg_set_profiling", "rhg_phase_times", "rhg_generate_async", "GraphBuffers", "Batch",
            "expected_col_capacity", "RhgError", "Graph", "Index", "load", "version",
            "LIB_PATH", "PHASES"]

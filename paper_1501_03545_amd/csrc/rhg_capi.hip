@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -355,6 +356,55 @@ rhg_status rhg_sort_rows(int64_t n, const int64_t *row_ptr, int32_t *col_idx, in
     hipStream_t s = (hipStream_t)stream;
     PhaseScope ps(RHG_PHASE_ROWS, s);
     RHG_HIP(launch_sort_rows(row_ptr, col_idx, n, nnz, aux, lcap, rows_tile_bound(nnz, lcap), s));
+    return RHG_OK;
+}
+
+size_t rhg_graph_stats_workspace_bytes(int64_t n, int64_t nnz, int triangles)
+{
+    if (n < 0 || nnz < 0) return 0;
+    return stats_workspace_bytes(n, nnz, triangles ? 1 : 0);
+}
+
+rhg_status rhg_graph_stats(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int64_t nnz, double kmin,
+                           int triangles, void *workspace, size_t workspace_bytes, rhg_graph_summary *out,
+                           void *stream)
+{
+    g_last_error.clear();
+    if (n < 0 || n > (int64_t)INT32_MAX || nnz < 0) return fail(RHG_EINVAL, "rhg_graph_stats: bad n or nnz");
+    if (!(kmin >= 1.0)) return fail(RHG_EINVAL, "rhg_graph_stats: kmin must be at least 1");
+    if (!out || !row_ptr || !workspace || (nnz > 0 && !col_idx)) return fail(RHG_EINVAL, "rhg_graph_stats: NULL argument");
+    if (workspace_bytes < stats_workspace_bytes(n, nnz, triangles ? 1 : 0))
+        return fail(RHG_ECAPACITY, "rhg_graph_stats: workspace smaller than rhg_graph_stats_workspace_bytes");
+    double d[8] = {0};
+    int64_t iv[48] = {0};
+    RHG_HIP(launch_graph_stats(n, row_ptr, col_idx, nnz, kmin, triangles ? 1 : 0, workspace, d, iv,
+                               (hipStream_t)stream));
+    memset(out, 0, sizeof(*out));
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    out->n = n;
+    out->nnz = nnz;
+    out->max_degree = iv[0];
+    for (int b = 0; b < 33; ++b) out->hist[b] = iv[8 + b];
+    out->kmin = kmin;
+    out->tail_count = iv[1];
+    out->gamma_mle = iv[1] > 0 ? 1.0 + (double)iv[1] / d[0] : nan;
+    out->assortativity = nan;
+    if (nnz > 0) {
+        const double M = (double)nnz, ex = d[1] / M, exx = d[2] / M, exy = d[3] / M;
+        const double var = exx - ex * ex;
+        if (var > 0.0) out->assortativity = (exy - ex * ex) / var;
+    }
+    out->triads = iv[2];
+    out->ascending_rows = iv[3] ? 0 : 1;
+    out->triangles = iv[4];
+    out->transitivity = nan;
+    out->avg_local_clustering = nan;
+    if (iv[4] >= 0) {
+        if (iv[2] > 0) out->transitivity = 3.0 * (double)iv[4] / (double)iv[2];
+        if (iv[5] > 0) out->avg_local_clustering = d[4] / (double)iv[5];
+    }
+    if (triangles && iv[4] < 0 && n > 0)
+        return fail(RHG_EINVAL, "rhg_graph_stats: triangles need ascending rows (rhg_sort_rows)");
     return RHG_OK;
 }
 

@@ -191,6 +191,15 @@ size_t rows_aux_bytes(int64_t lcap, int64_t mapcap);
 hipError_t launch_sort_rows(const int64_t *row_ptr, int32_t *col, int64_t n, int64_t maxlen_bound, void *aux,
                             int64_t lcap, int64_t mapcap, hipStream_t s);
 
+// Graph statistics.  out_i: max degree, tail count, triads, unsorted flag,
+// triangles (-1: not counted), vertices of degree >= 2, -, -, then the 33
+// histogram bins; out_d: sum ln(d / (kmin - 1/2)) over the tail, sum d^2,
+// sum d^3, sum over entries of d_u d_v, sum of local clustering.
+// Synchronises.
+size_t stats_workspace_bytes(int64_t n, int64_t nnz, int triangles);
+hipError_t launch_graph_stats(int64_t n, const int64_t *rp, const int32_t *col, int64_t nnz, double kmin,
+                              int triangles, void *workspace, double *out_d, int64_t *out_i, hipStream_t s);
+
 // Long-range augmentation: k extra edges, workspace of lr_workspace_bytes.
 size_t lr_workspace_bytes(int64_t n, int64_t k);
 hipError_t launch_long_range(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t nnz, int64_t k,

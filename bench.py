@@ -120,6 +120,14 @@ def run_gpu(cfg, steps, warmup, tuning=None):
         e1.record(stream)
         torch.cuda.synchronize()
         rows_ms.append(e0.elapsed_time(e1))
+    # validation statistics of the canonical graph (the last row sort left
+    # col ascending): degrees, power-law exponent, assortativity
+    st_ws = torch.empty(P.rhg_graph_stats_workspace_bytes(n, nnz, False), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter()
+    vstats = P.rhg_graph_stats(row_ptr, col[:nnz], kmin=10.0, triangles=False, nnz=nnz, workspace=st_ws)
+    vstats_ms = (time.perf_counter() - t_s) * 1e3
+    del st_ws
     # long-range augmentation (RHG-LR) of the same graph: 0.5 % extra edges
     k_lr = P.long_range_count(nnz // 2)
     lr_ws = torch.empty(P.rhg_long_range_workspace_bytes(n, k_lr), dtype=torch.uint8, device=dev)
@@ -136,8 +144,35 @@ def run_gpu(cfg, steps, warmup, tuning=None):
         lr_ms.append(e0.elapsed_time(e1))
     lr = {"k": k_lr, "added": int(added.item()), "ms": min(lr_ms)}
     del lr_ws, lr_out
+    validation = {"workload": "the n=%d graph above" % n, "ms": vstats_ms, "kmin": 10.0,
+                  "gamma_mle": vstats["gamma_mle"], "assortativity": vstats["assortativity"],
+                  "max_degree": vstats["max_degree"]}
     return dict(ms_per_step=(t1 - t0) * 1000.0 / steps, nnz=nnz, phases=phases, stats=stats,
-                params=p, rows_ms=min(rows_ms), lr=lr)
+                params=p, rows_ms=min(rows_ms), lr=lr, validation=validation)
+
+
+def run_validation_triangles():
+    """Full validation statistics with triangles on the n = 1e7 serving
+    graph (canonical rows)."""
+    import torch
+    import paper_1501_03545_amd as P
+    from paper_1501_03545_amd import workloads as W
+    cfg = dict(W.SERVE_LARGE, seed=1)
+    g = P.rhg_generate(cfg["n"], cfg["avg_degree"], cfg["gamma"], cfg["seed"], canonical_rows=True)
+    nnz = int(g.row_ptr[-1].item())
+    ws = torch.empty(P.rhg_graph_stats_workspace_bytes(cfg["n"], nnz, True), dtype=torch.uint8, device="cuda")
+    best, s = None, None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = P.rhg_graph_stats(g.row_ptr, g.col_idx, kmin=10.0, triangles=True, nnz=nnz, workspace=ws)
+        ms = (time.perf_counter() - t0) * 1e3
+        best = ms if best is None else min(best, ms)
+    return {"workload": "rhg n=%d avg_degree=%g gamma=%g seed=%d, canonical rows" % (
+                cfg["n"], cfg["avg_degree"], cfg["gamma"], cfg["seed"]),
+            "ms": best, "triangles": s["triangles"], "transitivity": s["transitivity"],
+            "avg_local_clustering": s["avg_local_clustering"], "gamma_mle": s["gamma_mle"],
+            "assortativity": s["assortativity"]}
 
 
 def run_batch(count, reps, tuned=True, n_streams=64):
@@ -344,11 +379,14 @@ def main():
                            "timed apart from the step and not in value"},
         "long_range": dict(res["lr"], form="rhg_long_range: ceil(0.005 m) random extra edges merged into the "
                            "emitted CSR (RHG-LR), timed apart from the step and not in value"),
+        "validation": res["validation"],
         "pipeline_floor_frac": (56 * n + 8 * m) / sec / 1e9 / HBM_PEAK_GBS,
         "search_stats": res["stats"],
     }
     if args.calibrate:
         out["copy_calibration"] = copy_calibration()
+    _log("validation statistics with triangles (n=1e7)")
+    out["validation_triangles"] = run_validation_triangles()
     if args.batch > 0:
         import torch
         del res

@@ -819,13 +819,20 @@ __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_
         wave_sync();
         int32_t idk[COPY_K];
         int tagk[COPY_K], posk[COPY_K];
+        // all loads of the chunk first: the wavefront fences below would
+        // otherwise hold each one back until the previous step is done
 #pragma unroll
         for (int k = 0; k < COPY_K; ++k) {
             const int64_t e = c0 + k * 64 + lane;
             const bool valid = e < total;
             idk[k] = valid ? A.store[w0 + e] : 0;
-            const int tg = valid ? (int)A.stag[w0 + e] : 0;
-            tagk[k] = tg;
+            tagk[k] = valid ? (int)A.stag[w0 + e] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < COPY_K; ++k) {
+            const int64_t e = c0 + k * 64 + lane;
+            const bool valid = e < total;
+            const int tg = tagk[k];
             // lanes holding entries of the same query lane in this step
             uint64_t peers = __ballot(valid);
 #pragma unroll

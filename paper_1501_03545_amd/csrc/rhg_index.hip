@@ -41,14 +41,17 @@ __device__ __forceinline__ int band_of(const KeyArgs &A, double r)
     return lo;
 }
 
+// rt (may be NULL): (r, theta) interleaved in sample order, so that the
+// gather after the sort reads each point with one 16-byte access.
 __global__ void __launch_bounds__(256) key_kernel(KeyArgs A, int64_t n, const double *__restrict__ r,
                                                   const double *__restrict__ theta, uint32_t *__restrict__ keys,
-                                                  uint32_t *__restrict__ vals, int validate,
-                                                  unsigned long long *stats)
+                                                  uint32_t *__restrict__ vals, double2 *__restrict__ rt,
+                                                  int validate, unsigned long long *stats)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double ri = r[i], ti = theta[i];
+        if (rt) rt[i] = make_double2(ri, ti);
         if (validate && !(ri >= 0.0 && ri <= A.R && ti >= 0.0 && ti <= RHG_TWO_PI_D))
             atomicAdd(&stats[ST_BAD_INPUT], 1ull);
         const uint32_t b = (uint32_t)band_of(A, ri);
@@ -132,6 +135,7 @@ __global__ void __launch_bounds__(256) dir_empty_kernel(DirArgs A, const int32_t
 // original id as raw bits).
 __global__ void __launch_bounds__(256) gather_kernel(int64_t n, const double *__restrict__ r,
                                                      const double *__restrict__ theta,
+                                                     const double2 *__restrict__ rt,
                                                      const uint32_t *__restrict__ perm, double inv, double sc,
                                                      double *__restrict__ sr, double *__restrict__ st,
                                                      float4 *__restrict__ rec)
@@ -140,9 +144,17 @@ __global__ void __launch_bounds__(256) gather_kernel(int64_t n, const double *__
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
         uint32_t id = perm[p];
         if (id >= (uint64_t)n) id = 0;  // unreachable for a valid permutation; keeps reads in bounds
-        const double ri = r[id];
+        double ri, ti;
+        if (rt) {
+            const double2 x = rt[id];
+            ri = x.x;
+            ti = x.y;
+        } else {
+            ri = r[id];
+            ti = theta[id];
+        }
         sr[p] = ri;
-        st[p] = theta[id];
+        st[p] = ti;
         rec[p] = make_float4((float)(exp(ri) * inv), (float)(exp(-ri) * inv), (float)(sinh(ri) * sc),
                              __int_as_float((int)id));
     }
@@ -167,9 +179,12 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
     ka.band_bits = L.band_bits;
     ka.R = idx->p.R;
     hipError_t e;
+    // The neighbour store is not written before the count pass: when it can
+    // hold 16 bytes per point it carries the interleaved points meanwhile.
+    double2 *rt = (idx->stage && idx->L.stage_cap >= 4 * n) ? (double2 *)idx->stage : nullptr;
     if (n > 0) {
         PhaseScope ps(RHG_PHASE_SORT, s);
-        hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(256), 0, s, ka, n, r, theta, idx->keys, v0,
+        hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(256), 0, s, ka, n, r, theta, idx->keys, v0, rt,
                            validate, idx->stats);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = radix_sort_pairs(idx->keys, v0, k1, v1, n, 32, idx->tmp, s)) != hipSuccess) return e;
@@ -194,8 +209,8 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
     if (n > 0) {
         PhaseScope ps(RHG_PHASE_GATHER, s);
         const double inv = 1.0 / sqrt(2.0 * idx->p.cosh_R), sc = sqrt(2.0 / idx->p.cosh_R);
-        hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, r, theta, v0, inv, sc, idx->sr,
-                           idx->st, idx->rec);
+        hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, r, theta, (const double2 *)rt, v0,
+                           inv, sc, idx->sr, idx->st, idx->rec);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

@@ -66,7 +66,7 @@ void phase_end(void *rec, hipStream_t s)
 }
 
 struct WsPlan {
-    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcnt, hitem, hscal, lkap, woff, wflag, stage,
+    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcand, hcnt, hitem, hscal, lkap, woff, wflag, stage,
         stag, stats, raux, tmp, total, tmp_bytes;
     int64_t max_chunks, rows_lcap, rows_mapcap, rows_nnz_cap;
 };
@@ -96,6 +96,7 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     const int64_t extra = std::min<int64_t>(RHG_HEAVY_EXTRA_CHUNKS, L.heavy_cap * (n / RHG_HEAVY_CHUNK + 1) + 1);
     w.max_chunks = items > 0 ? items + extra : 1;
     w.hplan = take((size_t)(items > 0 ? items : 1) * 8);
+    w.hcand = take((size_t)(items > 0 ? items : 1) * 8);
     w.hcnt = take((size_t)w.max_chunks * 8);
     w.hitem = take((size_t)w.max_chunks * 4);
     w.hscal = take(64);
@@ -247,6 +248,7 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->rec = (float4 *)(base + w.rec);
     idx->heavy_end = (int32_t *)(base + w.heavy_end);
     idx->hplan = (int64_t *)(base + w.hplan);
+    idx->hcand = (int64_t *)(base + w.hcand);
     idx->hcnt = (int64_t *)(base + w.hcnt);
     idx->hitem = (int32_t *)(base + w.hitem);
     idx->hscal = (int64_t *)(base + w.hscal);

@@ -144,6 +144,7 @@ struct rhg_index {
     int64_t *hcnt;         // max_chunks heavy chunks: counts, then their prefix
     int32_t *hitem;        // max_chunks heavy chunks: the item of each
     int64_t *hscal;        // heavy plan scalars
+    int64_t *hcand;        // heavy_cap * B items: candidates, then their prefix
     int64_t heavy_cap;
     int64_t max_chunks;
     float *lkap;           // log expected degree at RHG_KAP_SUB points per band, and at R

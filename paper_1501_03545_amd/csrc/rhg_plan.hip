@@ -217,7 +217,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // inner edge, where the degree is largest.
     L->stage = !(t && t->no_stage) && p.n >= 2;
     L->stage_cap = 0;
-    double slots = 0.0, entries = 0.0;
+    double slots = 0.0, entries = 0.0, heavy = 0.0;
     for (int j = 0; j < B; ++j) {
         for (int sub = 0; sub < RHG_KAP_SUB; ++sub) {
             const double ra = L->E[j] + (L->E[j + 1] - L->E[j]) * sub / RHG_KAP_SUB;
@@ -226,11 +226,16 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
             if (pts <= 0.0) continue;
             const double k = expected_degree(n, a, R, ra);
             entries += pts * k;
+            if (j < jh) heavy += pts * k;
             if (L->stage && j >= jh) slots += (pts + 4.0 * sqrt(pts) + 64.0) * (double)stage_slots(k);
         }
     }
     L->entries_est = p.n >= 2 ? entries : 0.0;
-    if (L->stage) L->stage_cap = (int64_t)std::min(1.02 * slots + 4096.0, 9.0e18);
+    // The heavy queries' tested neighbours go to the top of the store, one
+    // slot per candidate: their windows hold about 1.8 candidates per
+    // neighbour at band width 2, so twice the estimate (the emit pass tests
+    // them again when they do not fit).
+    if (L->stage) L->stage_cap = (int64_t)std::min(1.02 * slots + 2.0 * heavy + 4096.0, 9.0e18);
 }
 
 }  // namespace rhg

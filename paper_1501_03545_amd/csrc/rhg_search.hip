@@ -61,7 +61,8 @@ struct SearchArgs {
     int64_t *hplan;                   // per heavy item: candidates, then chunks, then their prefix
     int64_t *hcnt;                    // per heavy chunk: count, then its prefix
     int32_t *hitem;                   // per heavy chunk: its item
-    int64_t *hscal;                   // [0] candidate total, [1] chunk size
+    int64_t *hscal;                   // [0] candidate total, [1] chunk size, [2] heavy rows stored, [3] their first slot
+    int64_t *hcand;                   // per heavy item: candidates, then their prefix
     unsigned long long *stats;
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
     int32_t *overflow;                // emit pass: set to 1 when 2m > col_cap
@@ -315,6 +316,7 @@ __global__ void __launch_bounds__(256) heavy_plan_len(SearchArgs A)
             len = (it.b0 - it.a0) + (it.b1 - it.a1);
         }
         A.hplan[i] = len;
+        A.hcand[i] = len;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) len += __shfl_xor(len, o, 64);
@@ -342,9 +344,14 @@ __global__ void __launch_bounds__(256) heavy_plan_chunks(SearchArgs A)
     }
 }
 
-template <bool EMIT>
+// One chunk of a heavy item.  With the neighbour store (M_STAGE / M_COPY)
+// and room for it (hscal[2]), the count pass also writes the chunk's
+// accepted neighbours, in order, to the store's top end at the chunk's
+// candidate offset, and the emit pass copies them instead of testing again.
+template <int MODE>
 __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
 {
+    constexpr bool EMIT = MODE == M_EMIT || MODE == M_COPY;
     __shared__ int wave_cnt[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t item = uni64(A.hitem[c]);  // the item holding chunk c
@@ -352,6 +359,20 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
     const int64_t q = item / A.B;
     const int j = (int)(item % A.B);
     const int64_t ch = uni64(A.hscal[1]);
+    const bool hstore = (MODE == M_STAGE || MODE == M_COPY) && uni64(A.hscal[2]) != 0;
+    // first store slot of this chunk
+    const int64_t hbase = hstore ? uni64(A.hscal[3]) + (item ? uni64(A.hcand[item - 1]) : 0) + (c - first) * ch : 0;
+    if (MODE == M_COPY && hstore) {
+        const int64_t qfirst = q ? uni64(A.hplan[q * A.B - 1]) : 0;
+        const int64_t base_c = c ? uni64(A.hcnt[c - 1]) : 0;
+        const int64_t base_q = qfirst ? uni64(A.hcnt[qfirst - 1]) : 0;
+        const int64_t cnt = uni64(A.hcnt[c]) - base_c;
+        const int32_t id = __float_as_int(A.rec[q].w);
+        const int64_t out = row_ptr[id] + (base_c - base_q), row_end = row_ptr[id + 1];
+        for (int64_t i = threadIdx.x; i < cnt; i += 256)
+            if (out + i < row_end) col[out + i] = A.store[hbase + i];
+        return;
+    }
     const ItemRuns it = item_runs(A, q, j);
     const int64_t a0 = uni64(it.a0), b0 = uni64(it.b0), a1 = uni64(it.a1), b1 = uni64(it.b1);
     const int inside = __builtin_amdgcn_readfirstlane(it.inside);
@@ -396,6 +417,10 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
             const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
             const int64_t o = out + total + before + __popcll(bal & lt);
             if (o < row_end) col[o] = cid;
+        }
+        if (MODE == M_STAGE && hstore && acc) {
+            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+            A.store[hbase + total + before + __popcll(bal & lt)] = cid;
         }
         total += blk;
     }
@@ -884,7 +909,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     // (query, band, chunk) order, hubs first; the rest: 256 light queries each
     if ((int)blockIdx.x < A.heavy_blocks) {
         const int64_t nch = A.heavy_cap > 0 ? uni64(A.hplan[A.heavy_cap * A.B - 1]) : 0;
-        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<EMIT>(A, c, row_ptr, col_idx);
+        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<MODE>(A, c, row_ptr, col_idx);
         return;
     }
     const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
@@ -969,6 +994,18 @@ __global__ void __launch_bounds__(256) heavy_chunk_items(SearchArgs A)
     for (int64_t c = b; c < e; ++c) A.hitem[c] = (int32_t)i;
 }
 
+// After both plans: the heavy chunks' neighbours are stored at the top of
+// the neighbour store, one slot per candidate, when that leaves the light
+// wavefronts' slots [0, woff[nw]) untouched.
+__global__ void heavy_store_check(SearchArgs A, int64_t nw)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t off = A.store_cap - A.hscal[0];
+    const bool ok = A.store != nullptr && off >= 0 && A.woff[nw] <= off;
+    A.hscal[2] = ok ? 1 : 0;
+    A.hscal[3] = ok ? off : 0;
+}
+
 // Before the emit pass: flag a col_idx buffer smaller than the graph.
 __global__ void emit_prologue(const int64_t *row_ptr, int64_t n, int64_t cap, int32_t *overflow)
 {
@@ -1032,6 +1069,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.hcnt = idx->hcnt;
     A.hitem = idx->hitem;
     A.hscal = idx->hscal;
+    A.hcand = idx->hcand;
     A.stats = idx->stats;
     A.col_cap = col_cap;
     A.overflow = overflow;
@@ -1059,6 +1097,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
             hipLaunchKernelGGL(heavy_plan_chunks, dim3(g), dim3(256), 0, s, A);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = inclusive_scan_i64(idx->hplan, items, idx->tmp, s)) != hipSuccess) return e;
+            if ((e = inclusive_scan_i64(idx->hcand, items, idx->tmp, s)) != hipSuccess) return e;
             hipLaunchKernelGGL(heavy_chunk_items, dim3(g), dim3(256), 0, s, A);
             hipLaunchKernelGGL(zero_i64, dim3((unsigned)((idx->max_chunks + 255) / 256)), dim3(256), 0, s, idx->hcnt,
                                idx->max_chunks);
@@ -1069,6 +1108,10 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
             hipLaunchKernelGGL(store_plan, dim3((unsigned)((nw * 64 + 255) / 256)), dim3(256), 0, s, A, nw);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = inclusive_scan_i64(idx->woff + 1, nw, idx->tmp, s)) != hipSuccess) return e;
+        }
+        if (items > 0) {
+            hipLaunchKernelGGL(heavy_store_check, dim3(1), dim3(64), 0, s, A, nw);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     } else {
         if (overflow) {

@@ -75,11 +75,14 @@ typedef struct {
     double inner_radius;   /* radius below which all points share one band    */
     int32_t cell_target;   /* mean points per angular cell                    */
     int32_t heavy_points;  /* expected points searched one per workgroup      */
-    int32_t no_stage;      /* 0: the count pass also stores each light query's
+    int32_t no_stage;      /* 0: the count pass also stores each query's
                             * tested neighbours in the workspace and the emit
                             * pass copies them (one search); nonzero: the emit
                             * pass repeats the search (smaller workspace)     */
-    int32_t reserved[3];
+    int32_t no_heavy_store; /* nonzero: store only the light queries'
+                            * neighbours; the emit pass searches the heavy
+                            * queries again (smaller workspace)              */
+    int32_t reserved[2];
 } rhg_tuning;
 
 /* Device-side diagnostics of the last count/emit pass over an index. */

@@ -235,7 +235,8 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // slot per candidate: their windows hold about 1.8 candidates per
     // neighbour at band width 2, so twice the estimate (the emit pass tests
     // them again when they do not fit).
-    if (L->stage) L->stage_cap = (int64_t)std::min(1.02 * slots + 2.0 * heavy + 4096.0, 9.0e18);
+    L->heavy_store = L->stage && !(t && t->no_heavy_store);
+    if (L->stage) L->stage_cap = (int64_t)std::min(1.02 * slots + (L->heavy_store ? 2.0 * heavy : 0.0) + 4096.0, 9.0e18);
 }
 
 }  // namespace rhg

@@ -997,11 +997,11 @@ __global__ void __launch_bounds__(256) heavy_chunk_items(SearchArgs A)
 // After both plans: the heavy chunks' neighbours are stored at the top of
 // the neighbour store, one slot per candidate, when that leaves the light
 // wavefronts' slots [0, woff[nw]) untouched.
-__global__ void heavy_store_check(SearchArgs A, int64_t nw)
+__global__ void heavy_store_check(SearchArgs A, int64_t nw, int allowed)
 {
     if (threadIdx.x != 0) return;
     const int64_t off = A.store_cap - A.hscal[0];
-    const bool ok = A.store != nullptr && off >= 0 && A.woff[nw] <= off;
+    const bool ok = allowed && A.store != nullptr && off >= 0 && A.woff[nw] <= off;
     A.hscal[2] = ok ? 1 : 0;
     A.hscal[3] = ok ? off : 0;
 }
@@ -1110,7 +1110,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
             if ((e = inclusive_scan_i64(idx->woff + 1, nw, idx->tmp, s)) != hipSuccess) return e;
         }
         if (items > 0) {
-            hipLaunchKernelGGL(heavy_store_check, dim3(1), dim3(64), 0, s, A, nw);
+            hipLaunchKernelGGL(heavy_store_check, dim3(1), dim3(64), 0, s, A, nw, L.heavy_store);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     } else {

@@ -98,11 +98,13 @@ def test_stored_neighbours_give_the_rows_of_a_second_search():
     for tun in [{}, {"band_width": 1.0, "heavy_points": 2048}, {"band_width": 3.0, "cell_target": 4}]:
         rp_s, col_s, st_s = run_search(P, params, r, t, tuning=dict(tun) or None)
         rp_d, col_d, st_d = run_search(P, params, r, t, tuning=dict(tun, no_stage=1))
+        # the heavy queries' rows searched again instead of copied
+        rp_h, col_h, st_h = run_search(P, params, r, t, tuning=dict(tun, no_heavy_store=1))
         _say("store", tun, st_s)
         assert st_d["stage_fallbacks"] == 0 and st_d["stored"] == 0
         assert st_s["stored"] > 0
-        assert np.array_equal(rp_s, orp) and np.array_equal(rp_d, orp)
-        assert np.array_equal(col_s, col_d)
+        assert np.array_equal(rp_s, orp) and np.array_equal(rp_d, orp) and np.array_equal(rp_h, orp)
+        assert np.array_equal(col_s, col_d) and np.array_equal(col_s, col_h)
         assert np.array_equal(canonical(rp_s, col_s), ocol)
 
 

@@ -66,7 +66,7 @@ void phase_end(void *rec, hipStream_t s)
 }
 
 struct WsPlan {
-    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcand, hcnt, hitem, hscal, lkap, woff, wflag, stage,
+    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcand, hcnt, hitem, hscal, lkap, woff, wflag, wlist, stage,
         stag, stats, raux, tmp, total, tmp_bytes;
     int64_t max_chunks, rows_lcap, rows_mapcap, rows_nnz_cap;
 };
@@ -101,12 +101,13 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.hitem = take((size_t)w.max_chunks * 4);
     w.hscal = take(64);
     const int64_t nw = (int64_t)((N + 63) / 64);  // wavefronts of 64 sorted positions
-    w.lkap = w.woff = w.wflag = w.stage = w.stag = 0;
+    w.lkap = w.woff = w.wflag = w.wlist = w.stage = w.stag = 0;
     size_t t5 = 0;
     if (L.stage) {
         w.lkap = take((size_t)(RHG_KAP_SUB * L.B + 1) * 4);
         w.woff = take((size_t)(nw + 1) * 8);
         w.wflag = take((size_t)nw * 4);
+        w.wlist = take((size_t)nw * 4);
         w.stage = take((size_t)L.stage_cap * 4);
         w.stag = take((size_t)L.stage_cap);
         t5 = scan_tmp_bytes(nw);
@@ -257,6 +258,7 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->lkap = idx->L.stage ? (float *)(base + w.lkap) : nullptr;
     idx->woff = idx->L.stage ? (int64_t *)(base + w.woff) : nullptr;
     idx->wflag = idx->L.stage ? (int32_t *)(base + w.wflag) : nullptr;
+    idx->wlist = idx->L.stage ? (int32_t *)(base + w.wlist) : nullptr;
     idx->stage = idx->L.stage ? (int32_t *)(base + w.stage) : nullptr;
     idx->stag = idx->L.stage ? (uint8_t *)(base + w.stag) : nullptr;
     idx->stats = (unsigned long long *)(base + w.stats);

@@ -151,6 +151,7 @@ struct rhg_index {
     float *lkap;           // log expected degree at RHG_KAP_SUB points per band, and at R
     int64_t *woff;         // per wavefront of 64 positions: prefix of its store slots
     int32_t *wflag;        // per wavefront: 1 when a slot overflowed in the count pass
+    int32_t *wlist;        // the overflowed wavefronts, in the order they were found
     int32_t *stage;        // the neighbour store (stage_cap slots)
     uint8_t *stag;         // the lane of each stored neighbour (stage_cap)
     unsigned long long *stats;  // ST_COUNT counters

@@ -61,7 +61,8 @@ struct SearchArgs {
     int64_t *hplan;                   // per heavy item: candidates, then chunks, then their prefix
     int64_t *hcnt;                    // per heavy chunk: count, then its prefix
     int32_t *hitem;                   // per heavy chunk: its item
-    int64_t *hscal;                   // [0] candidate total, [1] chunk size, [2] heavy rows stored, [3] their first slot
+    int64_t *hscal;                   // [0] candidate total, [1] chunk size, [2] heavy rows stored, [3] their first slot,
+                                      // [4] overflowed wavefronts
     int64_t *hcand;                   // per heavy item: candidates, then their prefix
     unsigned long long *stats;
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
@@ -71,6 +72,7 @@ struct SearchArgs {
     float *lkap;                      // log expected degree, RHG_KAP_SUB points per band and R
     int64_t *woff;                    // per wavefront: first slot (prefix), then [nw] = total
     int32_t *wflag;                   // per wavefront: 1 = slots overflowed, search again
+    int32_t *wlist;                   // the overflowed wavefronts (count in hscal[4])
     int32_t *store;                   // the store: accepted neighbour ids
     uint8_t *stag;                    // and the lane (query) of each
     int64_t store_cap;
@@ -344,10 +346,10 @@ __global__ void __launch_bounds__(256) heavy_plan_chunks(SearchArgs A)
     }
 }
 
-// One chunk of a heavy item.  With the neighbour store (M_STAGE / M_COPY)
-// and room for it (hscal[2]), the count pass also writes the chunk's
-// accepted neighbours, in order, to the store's top end at the chunk's
-// candidate offset, and the emit pass copies them instead of testing again.
+// One chunk of a heavy item.  With the neighbour store and room for it
+// (hscal[2]), the count pass also writes the chunk's accepted neighbours, in
+// order, to the store's top end at the chunk's candidate offset, and the
+// emit pass copies them (heavy_copy_chunk) instead of testing again.
 template <int MODE>
 __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
 {
@@ -359,20 +361,9 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
     const int64_t q = item / A.B;
     const int j = (int)(item % A.B);
     const int64_t ch = uni64(A.hscal[1]);
-    const bool hstore = (MODE == M_STAGE || MODE == M_COPY) && uni64(A.hscal[2]) != 0;
+    const bool hstore = MODE == M_STAGE && uni64(A.hscal[2]) != 0;
     // first store slot of this chunk
     const int64_t hbase = hstore ? uni64(A.hscal[3]) + (item ? uni64(A.hcand[item - 1]) : 0) + (c - first) * ch : 0;
-    if (MODE == M_COPY && hstore) {
-        const int64_t qfirst = q ? uni64(A.hplan[q * A.B - 1]) : 0;
-        const int64_t base_c = c ? uni64(A.hcnt[c - 1]) : 0;
-        const int64_t base_q = qfirst ? uni64(A.hcnt[qfirst - 1]) : 0;
-        const int64_t cnt = uni64(A.hcnt[c]) - base_c;
-        const int32_t id = __float_as_int(A.rec[q].w);
-        const int64_t out = row_ptr[id] + (base_c - base_q), row_end = row_ptr[id + 1];
-        for (int64_t i = threadIdx.x; i < cnt; i += 256)
-            if (out + i < row_end) col[out + i] = A.store[hbase + i];
-        return;
-    }
     const ItemRuns it = item_runs(A, q, j);
     const int64_t a0 = uni64(it.a0), b0 = uni64(it.b0), a1 = uni64(it.a1), b1 = uni64(it.b1);
     const int inside = __builtin_amdgcn_readfirstlane(it.inside);
@@ -425,6 +416,27 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
         total += blk;
     }
     if (!EMIT && threadIdx.x == 0) A.hcnt[c] = total;
+}
+
+// Emit pass, stored heavy rows: wavefront-wide copy of chunk c's neighbours
+// from the store to its place in the row (the same as heavy_chunk<M_COPY>
+// with the store, one wavefront instead of a workgroup).
+__device__ void heavy_copy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t item = uni64(A.hitem[c]);
+    const int64_t first = item ? uni64(A.hplan[item - 1]) : 0;
+    const int64_t q = item / A.B;
+    const int64_t ch = uni64(A.hscal[1]);
+    const int64_t hbase = uni64(A.hscal[3]) + (item ? uni64(A.hcand[item - 1]) : 0) + (c - first) * ch;
+    const int64_t qfirst = q ? uni64(A.hplan[q * A.B - 1]) : 0;
+    const int64_t base_c = c ? uni64(A.hcnt[c - 1]) : 0;
+    const int64_t base_q = qfirst ? uni64(A.hcnt[qfirst - 1]) : 0;
+    const int64_t cnt = uni64(A.hcnt[c]) - base_c;
+    const int32_t id = __builtin_amdgcn_readfirstlane(__float_as_int(A.rec[q].w));
+    const int64_t out = uni64(row_ptr[id]) + (base_c - base_q), row_end = uni64(row_ptr[id + 1]);
+    for (int64_t i = lane; i < cnt; i += 64)
+        if (out + i < row_end) col[out + i] = A.store[hbase + i];
 }
 
 // ------------------------------------------------------------ light path
@@ -758,7 +770,11 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     if (STORE && lane == 0) {
         const bool over = fill > wlim;
         A.wflag[base >> 6] = over ? 1 : 0;
-        if (over) atomicAdd(&A.stats[ST_STAGE_FALLBACK], 1ull);
+        if (over) {
+            atomicAdd(&A.stats[ST_STAGE_FALLBACK], 1ull);
+            const unsigned long long k = atomicAdd((unsigned long long *)&A.hscal[4], 1ull);
+            A.wlist[k] = (int32_t)(base >> 6);
+        }
         else if (fill) atomicAdd(&A.stats[ST_STORED], (unsigned long long)fill);
     }
     if (!active) return;
@@ -909,16 +925,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     // (query, band, chunk) order, hubs first; the rest: 256 light queries each
     if ((int)blockIdx.x < A.heavy_blocks) {
         const int64_t nch = A.heavy_cap > 0 ? uni64(A.hplan[A.heavy_cap * A.B - 1]) : 0;
+        if (MODE == M_COPY && uni64(A.hscal[2]) != 0) {
+            // stored heavy rows: one wavefront per chunk copies it
+            const int64_t stride = (int64_t)A.heavy_blocks * 4;
+            for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nch; c += stride)
+                heavy_copy_chunk(A, c, row_ptr, col_idx);
+            return;
+        }
         for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<MODE>(A, c, row_ptr, col_idx);
         return;
     }
-    const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
     if (MODE == M_COPY) {
-        // copy_kernel handles the wavefronts whose stored neighbours fit
-        if (base < A.n && __builtin_amdgcn_readfirstlane(A.wflag[base >> 6]))
-            light_wave<M_EMIT>(A, base, row_ptr, col_idx);
+        // copy_kernel handles the wavefronts whose stored neighbours fit; a
+        // pool of wavefronts searches the listed ones again
+        const int64_t nf = uni64(A.hscal[4]);
+        const int64_t stride = ((int64_t)gridDim.x - A.heavy_blocks) * 4;
+        for (int64_t k = ((int64_t)blockIdx.x - A.heavy_blocks) * 4 + (threadIdx.x >> 6); k < nf; k += stride)
+            light_wave<M_EMIT>(A, (int64_t)__builtin_amdgcn_readfirstlane(A.wlist[k]) << 6, row_ptr, col_idx);
     } else {
-        light_wave<MODE == M_COPY ? M_EMIT : MODE>(A, base, row_ptr, col_idx);
+        const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
+        light_wave<MODE>(A, base, row_ptr, col_idx);
     }
 }
 
@@ -981,6 +1007,7 @@ __global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_
         *heavy_end = (int32_t)h;
         row_ptr[0] = 0;
         A.hscal[0] = 0;
+        A.hscal[4] = 0;
     }
 }
 
@@ -1078,6 +1105,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.lkap = idx->lkap;
     A.woff = idx->woff;
     A.wflag = idx->wflag;
+    A.wlist = idx->wlist;
     A.store = idx->stage;
     A.stag = idx->stag;
     A.store_cap = L.stage_cap;
@@ -1130,7 +1158,9 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
-        hipLaunchKernelGGL(search_kernel<M_COPY>, g, b, 0, s, A, row_ptr, col_idx);
+        const int64_t pool = std::min<int64_t>(1024, (n + 255) / 256);  // workgroups for the overflowed wavefronts
+        hipLaunchKernelGGL(search_kernel<M_COPY>, dim3((unsigned)(A.heavy_blocks + pool)), b, 0, s, A, row_ptr,
+                           col_idx);
     } else if (emit) {
         PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
         hipLaunchKernelGGL(search_kernel<M_EMIT>, g, b, 0, s, A, row_ptr, col_idx);

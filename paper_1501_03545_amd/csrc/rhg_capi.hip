@@ -242,6 +242,7 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     char *base = (char *)align_up((size_t)workspace, 256);
     idx->keys = (uint32_t *)(base + w.keys);
     uint32_t *v0 = (uint32_t *)(base + w.v0);
+    idx->ids = v0;
     idx->band_start = (int32_t *)(base + w.band_start);
     idx->dir = (int32_t *)(base + w.dir);
     idx->sr = (double *)(base + w.sr);

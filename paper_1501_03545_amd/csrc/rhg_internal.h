@@ -136,6 +136,7 @@ struct rhg_index {
     rhg::Layout L;
     int64_t n;
     uint32_t *keys;        // sorted keys (n)
+    uint32_t *ids;         // sorted ids (n): the sort's values, equal to the record's id bits
     int32_t *band_start;   // B + 1 sorted positions
     int32_t *dir;          // directory, dir_total entries
     double *sr, *st;       // sorted r, theta (n each)

@@ -53,6 +53,7 @@ struct SearchArgs {
     int use_p32;                      // FP32 screen valid (R small enough)
     int band_bits;                    // top bits of a sort key holding the band
     const uint32_t *keys;             // sorted keys: band, then the top angle bits
+    const uint32_t *ids;              // sorted ids (4 bytes where only the id is needed)
     const int32_t *band_start;
     const int32_t *dir;
     const double *sr, *st;
@@ -389,9 +390,14 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
         int acc = 0;
         int32_t cid = 0;
         if (v < v1 && pos != q) {
-            const float4 fc = A.rec[pos];
-            cid = __float_as_int(fc.w);
-            acc = inside ? 1 : decide(A, rq, tq, fq.x, fq.y, fq.z, pos, A.st[pos], fc.x, fc.y, fc.z, full_poly);
+            if (inside) {  // the whole band is within R: only the id is needed
+                cid = (int32_t)A.ids[pos];
+                acc = 1;
+            } else {
+                const float4 fc = A.rec[pos];
+                cid = __float_as_int(fc.w);
+                acc = decide(A, rq, tq, fq.x, fq.y, fq.z, pos, A.st[pos], fc.x, fc.y, fc.z, full_poly);
+            }
         }
         const uint64_t bal = __ballot(acc);
         if (lane == 0) wave_cnt[wave] = __popcll(bal);
@@ -587,7 +593,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             if (EMIT) {
                 for (int64_t c = s; c < e; ++c) {
                     if (c == p) continue;
-                    if (cnt < lim) out[cnt] = __float_as_int(A.rec[c].w);
+                    if (cnt < lim) out[cnt] = (int32_t)A.ids[c];
                     ++cnt;
                 }
             } else {
@@ -842,7 +848,7 @@ __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_
             const bool self = lp >= s && lp < e;
             for (int64_t c0 = s; c0 < e; c0 += 64) {
                 const int64_t c = c0 + lane;
-                if (c < e && c != lp) col[o + (c - s) - ((self && c > lp) ? 1 : 0)] = __float_as_int(A.rec[c].w);
+                if (c < e && c != lp) col[o + (c - s) - ((self && c > lp) ? 1 : 0)] = (int32_t)A.ids[c];
             }
             o += (e - s) - (self ? 1 : 0);
         }
@@ -1078,6 +1084,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.B = L.B;
     A.band_bits = L.band_bits;
     A.keys = idx->keys;
+    A.ids = idx->ids;
     A.n = idx->n;
     A.heavy_cap = idx->heavy_cap;
     A.max_chunks = idx->max_chunks;

@@ -82,7 +82,10 @@ typedef struct {
     int32_t no_heavy_store; /* nonzero: store only the light queries'
                             * neighbours; the emit pass searches the heavy
                             * queries again (smaller workspace)              */
-    int32_t reserved[2];
+    int32_t fp64_only;     /* nonzero: no FP32 screen, every candidate is
+                            * decided in binary64 (double-double near the
+                            * threshold): the plain path, same edge set      */
+    int32_t reserved;
 } rhg_tuning;
 
 /* Device-side diagnostics of the last count/emit pass over an index. */

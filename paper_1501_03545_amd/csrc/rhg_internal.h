@@ -47,6 +47,7 @@ struct Layout {
     int64_t stage_cap;                // int32 slots of the neighbour store
     double entries_est;               // upper estimate of the graph's entries (2m)
     int heavy_store;                  // the store also takes the heavy queries' neighbours
+    int fp64_only;                    // no FP32 screen
 };
 
 // Expected degree of a point at radius r (threshold model): the other n - 1

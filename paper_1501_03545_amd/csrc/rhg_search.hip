@@ -1092,7 +1092,8 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.R = p.R;
     A.C = p.cosh_R;
     A.C_lo = p.cosh_R_lo;
-    A.use_p32 = 1;  // R < 80 (rhg_plan_radius): the FP32 record neither overflows nor loses range
+    // R < 80 (rhg_plan_radius): the FP32 record neither overflows nor loses range
+    A.use_p32 = L.fp64_only ? 0 : 1;
     A.band_start = idx->band_start;
     A.dir = idx->dir;
     A.sr = idx->sr;

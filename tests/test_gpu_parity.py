@@ -225,6 +225,11 @@ def test_c2_full_graph_invariants_and_sampled_rows():
     assert stats["ties"] == 0
     for a_, i in enumerate(which):
         assert np.array_equal(np.sort(col2[rp2[i]:rp2[i + 1]]), ocol[ptr[a_]:ptr[a_ + 1]])
+    # the plain binary64 path (no FP32 screen), as this configuration names
+    # it, gives the same graph entry for entry
+    rp3, col3, st3 = run_search(P, P.rhg_plan_radius(n, a, R, 2), r_o, t_o, tuning={"fp64_only": 1})
+    assert st3["fp32_undecided"] == 0 and stats["fp32_undecided"] > 0
+    assert np.array_equal(rp3, rp2) and np.array_equal(col3, col2)
 
 
 def test_c3_full_size_points_and_sampled_rows():

@@ -172,14 +172,16 @@ __device__ __forceinline__ int p32(double tq, float eq, float mq, float sq, doub
     return L < P32_ACC ? 1 : (L > P32_REJ ? 0 : 2);
 }
 
-__device__ __forceinline__ int decide(const SearchArgs &A, double rq, double tq, float eq, float mq, float sq,
+// The pair (query at sorted position q, candidate c): the FP32 screen, then
+// the exact test, which reads the query's radius from the index.
+__device__ __forceinline__ int decide(const SearchArgs &A, int64_t q, double tq, float eq, float mq, float sq,
                                       int64_t c, double tc, float ec, float mc, float sc, bool full_poly)
 {
     int v = 2;
     if (A.use_p32) v = p32(tq, eq, mq, sq, tc, ec, mc, sc, full_poly);
     if (v == 2) {
         if (A.use_p32) atomicAdd(&A.stats[ST_FP32_UNDECIDED], 1ull);
-        v = edge_p64(rq, tq, A.sr[c], tc, A.C, A.C_lo, A.stats);
+        v = edge_p64(A.sr[q], tq, A.sr[c], tc, A.C, A.C_lo, A.stats);
     }
     return v;
 }
@@ -371,7 +373,7 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
     const bool full_poly = __builtin_amdgcn_readfirstlane(it.full_poly) != 0;
     const int64_t len0 = b0 - a0, len = len0 + (b1 - a1);
     const int64_t v0 = (c - first) * ch, v1 = min(len, v0 + ch);
-    const double rq = A.sr[q], tq = A.st[q];
+    const double tq = A.st[q];
     const float4 fq = A.rec[q];
     const int32_t id = __float_as_int(fq.w);
     int64_t out = 0, row_end = 0;
@@ -396,7 +398,7 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
             } else {
                 const float4 fc = A.rec[pos];
                 cid = __float_as_int(fc.w);
-                acc = decide(A, rq, tq, fq.x, fq.y, fq.z, pos, A.st[pos], fc.x, fc.y, fc.z, full_poly);
+                acc = decide(A, q, tq, fq.x, fq.y, fq.z, pos, A.st[pos], fc.x, fc.y, fc.z, full_poly);
             }
         }
         const uint64_t bal = __ballot(acc);
@@ -530,6 +532,26 @@ __device__ __forceinline__ int64_t wave_excl_sum64(int64_t v, int lane, int64_t 
 }
 
 
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wavefront's map of its per-query candidate stream (one band), and the
+// stage its candidates are loaded into, STREAM_CHUNK steps at a time.
+constexpr int STREAM_STEPS = 64;
+constexpr int STREAM_CHUNK = 4;
+struct StreamMap {
+    unsigned long long start[STREAM_STEPS];  // bit t % 64 of word t / 64: an owner's first entry is t
+    int4 run[64];  // owners in lane order: (first entry, first run's length | lane << 16, run starts)
+    float4 rec[STREAM_CHUNK][64];  // the step's candidate records, one per lane
+    int32_t tlo[STREAM_CHUNK][64], thi[STREAM_CHUNK][64];  // their angles (binary64 halves)
+    int2 own[STREAM_CHUNK][64];    // (owner lane, candidate position)
+};
+static_assert(STREAM_STEPS == 64, "one word per lane is cleared");
+
 // Light queries: a wavefront of 64 consecutive sorted positions.  Lane j
 // first builds band j's entry of the wave's band table: the union of the
 // lanes' windows (the window of the innermost lane, stretched over the
@@ -549,20 +571,29 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
 {
     constexpr bool EMIT = MODE == M_EMIT;
     constexpr bool STORE = MODE == M_STAGE;
+    __shared__ StreamMap smap[4];
+    StreamMap &SM = smap[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t p = base + lane;
+    // the query's loads do not wait for the heavy/light boundary
+    const bool inb = p < A.n;
+    double rq = 0.0, tq = 0.0;
+    float4 fq = make_float4(0.f, 0.f, 0.f, 1.f);
+    if (inb) {
+        rq = A.sr[p];
+        tq = A.st[p];
+        fq = A.rec[p];
+    }
     const int64_t hend = uni64(*A.heavy_end);
-    const bool active = p < A.n && p >= hend;
+    const bool active = inb && p >= hend;
     if (__ballot(active) == 0) {
         if (STORE && lane == 0 && base < A.n) A.wflag[base >> 6] = 0;
         return;
     }
-    double rq = 0.0, tq = 0.0;
-    float4 fq = make_float4(0.f, 0.f, 0.f, 1.f);
-    if (active) {
-        rq = A.sr[p];
-        tq = A.st[p];
-        fq = A.rec[p];
+    if (!active) {
+        rq = 0.0;
+        tq = 0.0;
+        fq = make_float4(0.f, 0.f, 0.f, 1.f);
     }
     const int32_t id = __float_as_int(fq.w);
     int32_t *out = nullptr;  // EMIT: entry k of the row goes to out[k] while k < lim
@@ -582,35 +613,41 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     const double tmin = wave_min(active ? tq : 1e300), tmax = wave_max(active ? tq : -1e300);
     const double span = tmax - tmin;
 
-    // bands lying wholly inside this lane's circle: taken without tests
+    // bands lying wholly inside this lane's circle: taken without tests.  The
+    // test is exact and monotone in the band's outer edge, so the inside
+    // bands are the first J of them.
     uint64_t full = 0;
     int64_t cnt = 0;
+    int J = 64;  // inactive lanes: neutral in the wave's minimum below
     if (active) {
-        for (int j = 0; j < B; ++j) {
-            const int64_t s = A.band_start[j], e = A.band_start[j + 1];
-            if (s == e || !band_inside(A, rq, j)) continue;
-            full |= 1ull << j;
-            if (EMIT) {
+        J = 0;
+        while (J < B && band_inside(A, rq, J)) {
+            if (A.band_start[J] < A.band_start[J + 1]) full |= 1ull << J;
+            ++J;
+        }
+        if (EMIT) {
+            for (int j = 0; j < J; ++j) {
+                const int64_t s = A.band_start[j], e = A.band_start[j + 1];
                 for (int64_t c = s; c < e; ++c) {
                     if (c == p) continue;
                     if (cnt < lim) out[cnt] = (int32_t)A.ids[c];
                     ++cnt;
                 }
-            } else {
-                cnt += (e - s) - ((p >= s && p < e) ? 1 : 0);
             }
+        } else {
+            const int64_t s = A.band_start[0], e = A.band_start[J];
+            cnt = (e - s) - ((p >= s && p < e) ? 1 : 0);
         }
     }
     // STORE: the wave appends the neighbours its tests accept to its region
     // [w0, w0 + wlim) of the store, in acceptance order, each with the lane
-    // of its query; one coalesced write per step.
+    // of its query; one coalesced write per step.  The region's size is the
+    // wave's sum of the per-query slots, as the store plan scanned it.
     int64_t w0 = 0, wlim = 0, fill = 0;
     if (STORE) {
-        long long slot = active ? (long long)slot_of(A, p) : 0ll;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) slot += __shfl_xor(slot, o, 64);
         w0 = uni64(A.woff[base >> 6]);
-        wlim = (w0 + slot <= A.store_cap) ? uni64(slot) : 0;
+        const int64_t slot = uni64(A.woff[(base >> 6) + 1]) - w0;
+        wlim = (w0 + slot <= A.store_cap) ? slot : 0;
     }
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     auto put = [&](int acc, int32_t cid, int tag) {
@@ -649,12 +686,18 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             }
         }
     }
-    // a band every active lane takes whole needs no tests
+    // a band every active lane takes whole needs no tests: the bands below
+    // the wave's minimum J (found bit by bit with ballots)
     {
-        uint64_t f = active ? full : ~0ull;
+        uint64_t cand = __ballot(active);
+        int mj = 0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) f &= (uint64_t)__shfl_xor((long long)f, o, 64);
-        if (lane < B && ((f >> lane) & 1ull)) mode = 0;
+        for (int b = 6; b >= 0; --b) {
+            const uint64_t zero = __ballot(((J >> b) & 1) == 0) & cand;
+            if (zero) cand = zero;
+            else mj |= 1 << b;
+        }
+        if (lane < mj) mode = 0;
     }
     if ((b0 - a0) + (b1 - a1) == 0) mode = 0;
 
@@ -681,7 +724,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     const float cx = crec[c4], cy = crec[c4 + 1], cz = crec[c4 + 2];
                     const int32_t cid = __float_as_int(crec[c4 + 3]);
                     int acc = 0;
-                    if (me && c != p) acc = decide(A, rq, tq, fq.x, fq.y, fq.z, c, tc, cx, cy, cz, fpj);
+                    if (me && c != p) acc = decide(A, p, tq, fq.x, fq.y, fq.z, c, tc, cx, cy, cz, fpj);
                     if (EMIT && acc && cnt < lim) out[cnt] = cid;
                     if (STORE) put(acc, cid, lane);
                     cnt += acc;
@@ -696,12 +739,11 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     // each lane finds its own runs in band j; the
     // runs of all lanes are then concatenated (lane order) and worked
     // through 64 candidates per step, each candidate tested against the
-    // query of the lane that owns it.  The loads of the next step are issued
-    // before the current step is tested.
+    // query of the lane that owns it.
     for (uint64_t mk = percell; mk; mk &= mk - 1) {
         const int j = __ffsll((unsigned long long)mk) - 1;
         const int64_t s = A.band_start[j], e = A.band_start[j + 1];
-        int64_t ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0;
+        int ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0;  // positions are below 2^31
         double w = 0.0;
         const bool mine = active && !((full >> j) & 1ull);
         if (mine) {
@@ -709,50 +751,67 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             int64_t ra[2] = {0, 0}, rb[2] = {0, 0};
             if (w >= 3.0) { ra[0] = s; rb[0] = e; }
             else window_runs(A, j, tq - w, tq + w, s, e, ra, rb);
-            ra0 = ra[0]; rb0 = rb[0]; ra1 = ra[1]; rb1 = rb[1];
+            ra0 = (int)ra[0]; rb0 = (int)rb[0]; ra1 = (int)ra[1]; rb1 = (int)rb[1];
         }
-        const int64_t len0 = rb0 - ra0, len = len0 + (rb1 - ra1);
+        const int len0 = rb0 - ra0, len = len0 + (rb1 - ra1);
         const int fpl = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
         int64_t total;
-        const int64_t pre = wave_excl_sum64(len, lane, &total);  // this lane's runs: [pre, pre + len)
+        const int64_t pre = wave_excl_sum64((int64_t)len, lane, &total);  // this lane's runs: [pre, pre + len)
         if (total == 0) continue;
-        // owner lane and position of stream entry t (every lane takes part)
-        auto locate = [&](int64_t t, int &l, int64_t &c) {
+        // A stream of at most 64 steps gets a map in LDS: one word per step
+        // with a bit at each owner's first entry, and the owners' runs in
+        // lane order.  The owner of an entry is then the owners starting
+        // before its step plus the bits up to it, and one LDS read.
+        const bool small = total <= 64 * STREAM_STEPS;
+        if (small) {
+            const int nz = __popcll(__ballot(len > 0) & lt_mask);
+            wave_sync();  // the previous band's reads of the map are done
+            SM.start[lane] = 0;
+            wave_sync();
+            if (len > 0) {
+                atomicOr(&SM.start[pre >> 6], 1ull << (pre & 63));
+                SM.run[nz] = make_int4((int)pre, len0 | (lane << 16), ra0, ra1);
+            }
+            wave_sync();
+        }
+        int before = 0;  // owners starting before the step being located
+        // owner lane and position of stream entry t0 + lane, for the steps
+        // t0 = 0, 64, 128, ... in order (every lane takes part)
+        auto locate = [&](int64_t t0, int &l, int &c) {
+            const int64_t t = t0 + lane;
+            if (small) {
+                const uint64_t bits = (uint64_t)uni64((int64_t)SM.start[t0 >> 6]);
+                const uint64_t upto = lane == 63 ? ~0ull : (2ull << lane) - 1;
+                const int4 r = SM.run[before + __popcll(bits & upto) - 1];
+                before += __popcll(bits);
+                l = r.y >> 16;
+                const int l0 = r.y & 0xffff, k = (int)t - r.x;
+                c = (k < l0) ? r.z + k : r.w + (k - l0);
+                return;
+            }
             l = 0;
 #pragma unroll
             for (int step = 32; step > 0; step >>= 1) {
                 const int64_t pv = __shfl(pre, l + step, 64);
                 if (t >= pv) l += step;
             }
-            const int64_t k = t - __shfl(pre, l, 64);
-            const int64_t l0 = __shfl(len0, l, 64), la0 = __shfl(ra0, l, 64), la1 = __shfl(ra1, l, 64);
+            const int k = (int)(t - __shfl(pre, l, 64));
+            const int l0 = __shfl(len0, l, 64), la0 = __shfl(ra0, l, 64), la1 = __shfl(ra1, l, 64);
             c = (k < l0) ? la0 + k : la1 + (k - l0);
         };
-        int ln;
-        int64_t cn;
-        locate(lane, ln, cn);
-        double tn = 0.0;
-        float4 fn = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lane < total) { tn = A.st[cn]; fn = A.rec[cn]; }
-        for (int64_t t0 = 0; t0 < total; t0 += 64) {
-            const int l = ln;
-            const int64_t c = cn;
-            const double tc = tn;
-            const float4 fc = fn;
+        // one step of the stream: entry t0 + lane is candidate c of lane l's
+        // query
+        auto step = [&](int64_t t0, int l, int c, double tc, float4 fc) {
             const bool valid = t0 + lane < total;
-            if (t0 + 64 < total) {
-                locate(t0 + 64 + lane, ln, cn);
-                if (t0 + 64 + lane < total) { tn = A.st[cn]; fn = A.rec[cn]; }
-            }
             // the owner's query
-            const double lr = __shfl(rq, l, 64), lt = __shfl(tq, l, 64), lw = __shfl(w, l, 64);
+            const double lt = __shfl(tq, l, 64), lw = __shfl(w, l, 64);
             const float le = __shfl(fq.x, l, 64), lmq = __shfl(fq.y, l, 64), ls = __shfl(fq.z, l, 64);
-            const int64_t lp = __shfl(p, l, 64);
+            const int64_t lp = base + l;
             const bool lfp = __shfl(fpl, l, 64) != 0;
             int acc = 0;
             const int cid = __float_as_int(fc.w);
             if (valid && c != lp && !(short_angle(lt, tc) > lw))
-                acc = decide(A, lr, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp);
+                acc = decide(A, lp, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp);
             const uint64_t bal = __ballot(acc);
             // this lane's part of the step, as the owner of [pre, pre + len)
             const int64_t lo = pre - t0, hi = pre + len - t0;
@@ -771,6 +830,65 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             }
             if (STORE) put(acc, cid, l);
             cnt += got;
+        };
+        if (small) {
+            // STREAM_CHUNK steps at a time: locate every entry and load its
+            // candidate straight into the LDS stage (one memory round trip for
+            // the chunk, no registers held), then test the steps from LDS
+            const int32_t *const st32 = (const int32_t *)A.st;
+            for (int64_t tc0 = 0; tc0 < total; tc0 += 64 * STREAM_CHUNK) {
+                // every locate (LDS reads) before the first load: a read of
+                // LDS after a load into LDS waits for that load
+                int cs[STREAM_CHUNK];
+#pragma unroll
+                for (int k = 0; k < STREAM_CHUNK; ++k) {
+                    cs[k] = 0;
+                    const int64_t t0 = tc0 + 64 * k;
+                    if (t0 < total) {
+                        int l;
+                        locate(t0, l, cs[k]);
+                        SM.own[k][lane] = make_int2(l, cs[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < STREAM_CHUNK; ++k) {
+                    const int64_t t0 = tc0 + 64 * k, c = cs[k];
+                    if (t0 + lane < total) {
+                        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(A.rec + c),
+                                                         (__attribute__((address_space(3))) void *)SM.rec[k], 16, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(st32 + 2 * c),
+                                                         (__attribute__((address_space(3))) void *)SM.tlo[k], 4, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(st32 + 2 * c + 1),
+                                                         (__attribute__((address_space(3))) void *)SM.thi[k], 4, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < STREAM_CHUNK; ++k) {
+                    const int64_t t0 = tc0 + 64 * k;
+                    if (t0 < total) {
+                        const int2 lc = SM.own[k][lane];
+                        step(t0, lc.x, lc.y, __hiloint2double(SM.thi[k][lane], SM.tlo[k][lane]), SM.rec[k][lane]);
+                    }
+                }
+            }
+            continue;
+        }
+        // a long stream: the loads of the next step are issued before the
+        // current step is tested
+        int ln, cn;
+        locate(0, ln, cn);
+        double tn = 0.0;
+        float4 fn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < total) { tn = A.st[cn]; fn = A.rec[cn]; }
+        for (int64_t t0 = 0; t0 < total; t0 += 64) {
+            const int l = ln, c = cn;
+            const double tc = tn;
+            const float4 fc = fn;
+            if (t0 + 64 < total) {
+                locate(t0 + 64, ln, cn);
+                if (t0 + 64 + lane < total) { tn = A.st[cn]; fn = A.rec[cn]; }
+            }
+            step(t0, l, c, tc, fc);
         }
     }
     if (STORE && lane == 0) {
@@ -806,13 +924,6 @@ struct CopyStage {
     int32_t cnt[64];
 };
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_ptr, int32_t *col)
 {
     __shared__ CopyStage stage[4];
@@ -829,12 +940,14 @@ __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_
         const int32_t id = __float_as_int(A.rec[p].w);
         dst = row_ptr[id];
         deg = row_ptr[id + 1] - dst;
-        for (int j = 0; j < A.B; ++j) {
-            const int64_t s = A.band_start[j], e = A.band_start[j + 1];
-            if (s == e || !band_inside(A, rq, j)) continue;
-            full |= 1ull << j;
-            fullc += (e - s) - ((p >= s && p < e) ? 1 : 0);
+        // the inside bands are the first J (the test is monotone in the edge)
+        int J = 0;
+        while (J < A.B && band_inside(A, rq, J)) {
+            if (A.band_start[J] < A.band_start[J + 1]) full |= 1ull << J;
+            ++J;
         }
+        const int64_t s = A.band_start[0], e = A.band_start[J];
+        fullc = (e - s) - ((p >= s && p < e) ? 1 : 0);
     }
     // inside bands: the whole wave copies one row's bands at a time
     for (uint64_t lm = __ballot(active && full != 0); lm; lm &= lm - 1) {

@@ -85,7 +85,10 @@ typedef struct {
     int32_t fp64_only;     /* nonzero: no FP32 screen, every candidate is
                             * decided in binary64 (double-double near the
                             * threshold): the plain path, same edge set      */
-    int32_t reserved;
+    int32_t no_stream_stage; /* nonzero: a wavefront's per-query candidate
+                            * streams are always read through registers one
+                            * step ahead, never staged in LDS (the path the
+                            * longest streams take); same bytes out         */
 } rhg_tuning;
 
 /* Device-side diagnostics of the last count/emit pass over an index. */

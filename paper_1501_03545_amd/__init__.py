@@ -37,7 +37,7 @@ class rhg_params(C.Structure):
 class rhg_tuning(C.Structure):
     _fields_ = [("band_width", C.c_double), ("inner_radius", C.c_double),
                 ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("no_stage", C.c_int32),
-                ("no_heavy_store", C.c_int32), ("fp64_only", C.c_int32), ("reserved", C.c_int32)]
+                ("no_heavy_store", C.c_int32), ("fp64_only", C.c_int32), ("no_stream_stage", C.c_int32)]
 
 
 class rhg_stats(C.Structure):
@@ -141,6 +141,7 @@ def _tuning(t: Optional[dict]):
     tu.no_stage = 1 if t.get("no_stage") else 0
     tu.no_heavy_store = 1 if t.get("no_heavy_store") else 0
     tu.fp64_only = 1 if t.get("fp64_only") else 0
+    tu.no_stream_stage = 1 if t.get("no_stream_stage") else 0
     return C.byref(tu)
 
 

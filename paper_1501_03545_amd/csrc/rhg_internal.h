@@ -48,6 +48,7 @@ struct Layout {
     double entries_est;               // upper estimate of the graph's entries (2m)
     int heavy_store;                  // the store also takes the heavy queries' neighbours
     int fp64_only;                    // no FP32 screen
+    int no_stream_stage;              // per-query streams never staged in LDS
 };
 
 // Expected degree of a point at radius r (threshold model): the other n - 1

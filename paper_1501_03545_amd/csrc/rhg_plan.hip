@@ -237,6 +237,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // them again when they do not fit).
     L->heavy_store = L->stage && !(t && t->no_heavy_store);
     L->fp64_only = (t && t->fp64_only) ? 1 : 0;
+    L->no_stream_stage = (t && t->no_stream_stage) ? 1 : 0;
     if (L->stage) L->stage_cap = (int64_t)std::min(1.02 * slots + (L->heavy_store ? 2.0 * heavy : 0.0) + 4096.0, 9.0e18);
 }
 

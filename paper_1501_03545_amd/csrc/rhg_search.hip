@@ -51,6 +51,7 @@ struct SearchArgs {
     double R;
     double C, C_lo;                   // cosh R as double-double
     int use_p32;                      // FP32 screen valid (R small enough)
+    int stream_stage;                 // per-query streams of <= 64 steps staged in LDS
     int band_bits;                    // top bits of a sort key holding the band
     const uint32_t *keys;             // sorted keys: band, then the top angle bits
     const uint32_t *ids;              // sorted ids (4 bytes where only the id is needed)
@@ -762,7 +763,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         // with a bit at each owner's first entry, and the owners' runs in
         // lane order.  The owner of an entry is then the owners starting
         // before its step plus the bits up to it, and one LDS read.
-        const bool small = total <= 64 * STREAM_STEPS;
+        const bool small = A.stream_stage && total <= 64 * STREAM_STEPS;
         if (small) {
             const int nz = __popcll(__ballot(len > 0) & lt_mask);
             wave_sync();  // the previous band's reads of the map are done
@@ -1207,6 +1208,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.C_lo = p.cosh_R_lo;
     // R < 80 (rhg_plan_radius): the FP32 record neither overflows nor loses range
     A.use_p32 = L.fp64_only ? 0 : 1;
+    A.stream_stage = L.no_stream_stage ? 0 : 1;
     A.band_start = idx->band_start;
     A.dir = idx->dir;
     A.sr = idx->sr;

@@ -100,11 +100,14 @@ def test_stored_neighbours_give_the_rows_of_a_second_search():
         rp_d, col_d, st_d = run_search(P, params, r, t, tuning=dict(tun, no_stage=1))
         # the heavy queries' rows searched again instead of copied
         rp_h, col_h, st_h = run_search(P, params, r, t, tuning=dict(tun, no_heavy_store=1))
+        # per-query candidate streams read through registers, never staged in LDS
+        rp_r, col_r, _ = run_search(P, params, r, t, tuning=dict(tun, no_stream_stage=1))
         _say("store", tun, st_s)
         assert st_d["stage_fallbacks"] == 0 and st_d["stored"] == 0
         assert st_s["stored"] > 0
         assert np.array_equal(rp_s, orp) and np.array_equal(rp_d, orp) and np.array_equal(rp_h, orp)
-        assert np.array_equal(col_s, col_d) and np.array_equal(col_s, col_h)
+        assert np.array_equal(rp_r, orp)
+        assert np.array_equal(col_s, col_d) and np.array_equal(col_s, col_h) and np.array_equal(col_s, col_r)
         assert np.array_equal(canonical(rp_s, col_s), ocol)
 
 
@@ -230,6 +233,10 @@ def test_c2_full_graph_invariants_and_sampled_rows():
     rp3, col3, st3 = run_search(P, P.rhg_plan_radius(n, a, R, 2), r_o, t_o, tuning={"fp64_only": 1})
     assert st3["fp32_undecided"] == 0 and stats["fp32_undecided"] > 0
     assert np.array_equal(rp3, rp2) and np.array_equal(col3, col2)
+    # per-query candidate streams through registers only (the path of the
+    # longest streams) instead of the LDS stage: the same bytes
+    rp4, col4, _ = run_search(P, P.rhg_plan_radius(n, a, R, 2), r_o, t_o, tuning={"no_stream_stage": 1})
+    assert np.array_equal(rp4, rp2) and np.array_equal(col4, col2)
 
 
 def test_c3_full_size_points_and_sampled_rows():

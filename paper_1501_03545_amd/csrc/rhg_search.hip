@@ -358,7 +358,10 @@ template <int MODE>
 __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
 {
     constexpr bool EMIT = MODE == M_EMIT || MODE == M_COPY;
-    __shared__ int wave_cnt[4];
+    // per-wave acceptance counts, double-buffered so that one barrier per
+    // step suffices: a buffer is rewritten two steps later, after every wave
+    // has passed the next step's barrier
+    __shared__ int wave_cnt[2][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t item = uni64(A.hitem[c]);  // the item holding chunk c
     const int64_t first = item ? uni64(A.hplan[item - 1]) : 0;
@@ -387,32 +390,44 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
         row_end = row_ptr[id + 1];
     }
     int64_t total = 0;
+    // the candidate of entry v (its id alone inside the circle); the loads of
+    // the next 256 entries are issued before this step's tests
+    auto fetch = [&](int64_t v, float4 &fc, double &tc) {
+        fc = make_float4(0.f, 0.f, 0.f, 0.f);
+        tc = 0.0;
+        if (v < v1) {
+            const int64_t pos = (v < len0) ? a0 + v : a1 + (v - len0);
+            if (inside) fc.w = __int_as_float((int32_t)A.ids[pos]);
+            else {
+                fc = A.rec[pos];
+                tc = A.st[pos];
+            }
+        }
+    };
+    float4 fn;
+    double tn;
+    fetch(v0 + threadIdx.x, fn, tn);
     for (int64_t vb = v0; vb < v1; vb += 256) {
         const int64_t v = vb + threadIdx.x;
         const int64_t pos = (v < len0) ? a0 + v : a1 + (v - len0);
+        const float4 fc = fn;
+        const double tc = tn;
+        if (vb + 256 < v1) fetch(v + 256, fn, tn);
         int acc = 0;
-        int32_t cid = 0;
-        if (v < v1 && pos != q) {
-            if (inside) {  // the whole band is within R: only the id is needed
-                cid = (int32_t)A.ids[pos];
-                acc = 1;
-            } else {
-                const float4 fc = A.rec[pos];
-                cid = __float_as_int(fc.w);
-                acc = decide(A, q, tq, fq.x, fq.y, fq.z, pos, A.st[pos], fc.x, fc.y, fc.z, full_poly);
-            }
-        }
+        const int32_t cid = __float_as_int(fc.w);
+        if (v < v1 && pos != q)
+            acc = inside ? 1 : decide(A, q, tq, fq.x, fq.y, fq.z, pos, tc, fc.x, fc.y, fc.z, full_poly);
         const uint64_t bal = __ballot(acc);
-        if (lane == 0) wave_cnt[wave] = __popcll(bal);
+        const int buf = (int)(((vb - v0) >> 8) & 1);
+        if (lane == 0) wave_cnt[buf][wave] = __popcll(bal);
         __syncthreads();
         int before = 0, blk = 0;
 #pragma unroll
         for (int w2 = 0; w2 < 4; ++w2) {
-            const int x = wave_cnt[w2];
+            const int x = wave_cnt[buf][w2];
             if (w2 < wave) before += x;
             blk += x;
         }
-        __syncthreads();
         if (EMIT && acc) {
             const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
             const int64_t o = out + total + before + __popcll(bal & lt);
@@ -424,6 +439,9 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
         }
         total += blk;
     }
+    // the next chunk starts again at buffer 0: every wave has read this one's
+    // counts first
+    __syncthreads();
     if (!EMIT && threadIdx.x == 0) A.hcnt[c] = total;
 }
 

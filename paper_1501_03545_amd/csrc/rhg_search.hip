@@ -1063,13 +1063,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     // (query, band, chunk) order, hubs first; the rest: 256 light queries each
     if ((int)blockIdx.x < A.heavy_blocks) {
         const int64_t nch = A.heavy_cap > 0 ? uni64(A.hplan[A.heavy_cap * A.B - 1]) : 0;
-        if (MODE == M_COPY && uni64(A.hscal[2]) != 0) {
-            // stored heavy rows: one wavefront per chunk copies it
-            const int64_t stride = (int64_t)A.heavy_blocks * 4;
-            for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nch; c += stride)
-                heavy_copy_chunk(A, c, row_ptr, col_idx);
-            return;
-        }
+        if (MODE == M_COPY && uni64(A.hscal[2]) != 0) return;  // stored heavy rows: copy_kernel copies them
         for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<MODE>(A, c, row_ptr, col_idx);
         return;
     }
@@ -1086,14 +1080,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     }
 }
 
-// Emit pass with the neighbour store: copy the rows of every wavefront of
-// 64 light queries whose stored neighbours fit their slots.  Kept apart from
-// search_kernel so that its small register footprint gives full occupancy.
+// Emit pass with the neighbour store: workgroups [0, heavy_blocks) copy the
+// stored heavy rows (one wavefront per chunk), the rest copy the rows of
+// every wavefront of 64 light queries whose stored neighbours fit their
+// slots.  Kept apart from search_kernel so that its small register
+// footprint gives full occupancy.
 __global__ void __launch_bounds__(256) copy_kernel(SearchArgs A, const int64_t *__restrict__ row_ptr,
                                                    int32_t *__restrict__ col_idx)
 {
     if (A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
-    const int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+    if ((int)blockIdx.x < A.heavy_blocks) {
+        if (uni64(A.hscal[2]) == 0) return;  // not stored: searched again by search_kernel<M_COPY>
+        const int64_t nch = uni64(A.hplan[A.heavy_cap * A.B - 1]);
+        const int64_t stride = (int64_t)A.heavy_blocks * 4;
+        for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nch; c += stride)
+            heavy_copy_chunk(A, c, row_ptr, col_idx);
+        return;
+    }
+    const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
     if (base >= A.n || __builtin_amdgcn_readfirstlane(A.wflag[base >> 6])) return;
     copy_wave(A, base, row_ptr, col_idx);
 }
@@ -1295,7 +1299,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     if (emit && store) {
         {
             PhaseScope ps(RHG_PHASE_COPY, s);
-            hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), b, 0, s, A, row_ptr, col_idx);
+            hipLaunchKernelGGL(copy_kernel, g, b, 0, s, A, row_ptr, col_idx);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         PhaseScope ps(RHG_PHASE_EMIT_PASS, s);

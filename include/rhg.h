@@ -101,6 +101,11 @@ typedef struct {
                               * pass searched them again                      */
     int64_t stored;          /* neighbours the count pass stored (copied by
                               * the emit pass)                                */
+    int64_t register_streams; /* per-query candidate streams (one per light
+                              * wavefront and band) read through registers:
+                              * those longer than 4096 entries, or all of
+                              * them with no_stream_stage; the rest are
+                              * staged in LDS                                 */
 } rhg_stats;
 
 typedef struct rhg_index rhg_index;  /* opaque, host-side handle */

@@ -42,7 +42,8 @@ class rhg_tuning(C.Structure):
 
 class rhg_stats(C.Structure):
     _fields_ = [("fp32_undecided", C.c_int64), ("dd_fallbacks", C.c_int64), ("ties", C.c_int64),
-                ("stage_fallbacks", C.c_int64), ("stored", C.c_int64)]
+                ("stage_fallbacks", C.c_int64), ("stored", C.c_int64),
+                ("register_streams", C.c_int64)]
 
 
 class rhg_graph_summary(C.Structure):
@@ -299,7 +300,7 @@ def rhg_index_stats(idx: Index, stream=None) -> dict:
     st = rhg_stats()
     _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
     return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties,
-            "stage_fallbacks": st.stage_fallbacks, "stored": st.stored}
+            "stage_fallbacks": st.stage_fallbacks, "stored": st.stored, "register_streams": st.register_streams}
 
 
 PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count", "scan", "copy", "emit", "rows"]

@@ -452,6 +452,7 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
     out->ties = (int64_t)h[ST_TIES];
     out->stage_fallbacks = (int64_t)h[ST_STAGE_FALLBACK];
     out->stored = (int64_t)h[ST_STORED];
+    out->register_streams = (int64_t)h[ST_REG_STREAMS];
     if (h[ST_EMIT_MISMATCH]) return fail(RHG_EINTERNAL, "emit pass disagreed with the count pass");
     return RHG_OK;
 }

@@ -127,7 +127,7 @@ struct PhaseScope {
 
 // Device-side counters (one 64-bit word each).
 enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4,
-       ST_STAGE_FALLBACK = 5, ST_STORED = 6, ST_COUNT = 8 };
+       ST_STAGE_FALLBACK = 5, ST_STORED = 6, ST_REG_STREAMS = 7, ST_COUNT = 8 };
 
 }  // namespace rhg
 

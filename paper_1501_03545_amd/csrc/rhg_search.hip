@@ -894,6 +894,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         }
         // a long stream: the loads of the next step are issued before the
         // current step is tested
+        if (lane == 0) atomicAdd(&A.stats[ST_REG_STREAMS], 1ull);
         int ln, cn;
         locate(0, ln, cn);
         double tn = 0.0;

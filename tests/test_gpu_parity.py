@@ -123,11 +123,18 @@ def test_store_overflow_falls_back_to_search():
     orp, ocol, _, nt = O.csr(r, t, R)
     rp_s, col_s, st_s = run_search(P, params, r, t)
     rp_d, col_d, _ = run_search(P, params, r, t, tuning={"no_stage": 1})
-    _say("crowded", st_s)
+    rp_r, col_r, st_r = run_search(P, params, r, t, tuning={"no_stream_stage": 1})
+    _say("crowded", st_s, "register path only:", st_r)
     assert st_s["stage_fallbacks"] > 0
     assert np.array_equal(rp_s, orp)
     assert np.array_equal(col_s, col_d)
     assert np.array_equal(canonical(rp_s, col_s), ocol)
+    # the crowded sector's longest streams (over 4096 entries) take the
+    # register path even by default; with no_stream_stage every stream does,
+    # with the same bytes
+    assert st_s["register_streams"] > 0
+    assert st_r["register_streams"] > st_s["register_streams"]
+    assert np.array_equal(rp_r, orp) and np.array_equal(col_r, col_s)
 
 
 def test_search_degenerate_inputs():

@@ -70,8 +70,6 @@ struct SearchArgs {
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
     int32_t *overflow;                // emit pass: set to 1 when 2m > col_cap
     // neighbour store (count pass writes, emit pass copies)
-    double alpha, nd;                 // alpha and n, for the expected-degree table
-    float *lkap;                      // log expected degree, RHG_KAP_SUB points per band and R
     int64_t *woff;                    // per wavefront: first slot (prefix), then [nw] = total
     int32_t *wflag;                   // per wavefront: 1 = slots overflowed, search again
     int32_t *wlist;                   // the overflowed wavefronts (count in hscal[4])
@@ -523,20 +521,6 @@ __device__ __forceinline__ float lane_float(float v, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-
-// Slots of the neighbour store for the light query at sorted position p:
-// its expected degree, interpolated (log-linear) in the table at
-// RHG_KAP_SUB points per band, with the margin of stage_slots.
-__device__ __forceinline__ int64_t slot_of(const SearchArgs &A, int64_t p)
-{
-    const int j = A.band_bits ? (int)(A.keys[p] >> (32 - A.band_bits)) : 0;
-    const double u = (A.sr[p] - A.E[j]) / (A.E[j + 1] - A.E[j]) * RHG_KAP_SUB;
-    const int sub = min(RHG_KAP_SUB - 1, max(0, (int)u));
-    const double t = fmin(1.0, fmax(0.0, u - sub));
-    const int i = j * RHG_KAP_SUB + sub;
-    const double lk = (double)A.lkap[i] + t * ((double)A.lkap[i + 1] - (double)A.lkap[i]);
-    return stage_slots(exp(lk));
-}
 
 __device__ __forceinline__ int64_t wave_excl_sum64(int64_t v, int lane, int64_t *total)
 {
@@ -1103,43 +1087,6 @@ __global__ void __launch_bounds__(256) copy_kernel(SearchArgs A, const int64_t *
     copy_wave(A, base, row_ptr, col_idx);
 }
 
-// Expected-degree table of the neighbour store: log of the expected degree
-// at RHG_KAP_SUB equally spaced radii per band, and at R.  One wavefront per
-// radius, two quadrature nodes per lane.
-__global__ void __launch_bounds__(256) store_table(SearchArgs A)
-{
-    const int i = (int)(blockIdx.x * 4 + (threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int last = RHG_KAP_SUB * A.B;
-    if (i > last) return;  // whole wavefronts leave together
-    double r = A.R;
-    if (i < last) {
-        const int j = i / RHG_KAP_SUB, sub = i % RHG_KAP_SUB;
-        r = A.E[j] + (A.E[j + 1] - A.E[j]) * sub / RHG_KAP_SUB;
-    }
-    double part = 0.0;
-    if (r > 0.0) part = degree_node(A.alpha, A.R, r, lane) + degree_node(A.alpha, A.R, r, lane + 64);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-    if (lane == 0) {
-        const double k = (A.nd - 1.0) * fmin(1.0, degree_inner(A.alpha, A.R, r) + part);
-        A.lkap[i] = (float)log(fmax(k, 1e-3));
-    }
-}
-
-// Slots per wavefront of 64 sorted positions (light queries only); the
-// host scans woff[1..nw] into the wavefronts' first slots.
-__global__ void __launch_bounds__(256) store_plan(SearchArgs A, int64_t nw)
-{
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t hend = *A.heavy_end;
-    int64_t slot = (p < A.n && p >= hend) ? slot_of(A, p) : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) slot += __shfl_xor(slot, o, 64);
-    const int64_t w = p >> 6;
-    if ((threadIdx.x & 63) == 0 && w < nw) A.woff[w + 1] = slot;
-    if (p == 0) A.woff[0] = 0;
-}
-
 // Before the count pass: heavy_end = the first light position (the end of
 // the heavy bands, capped); zero the plan's candidate total.
 __global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_t *row_ptr)
@@ -1246,9 +1193,6 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.stats = idx->stats;
     A.col_cap = col_cap;
     A.overflow = overflow;
-    A.alpha = p.alpha;
-    A.nd = (double)idx->n;
-    A.lkap = idx->lkap;
     A.woff = idx->woff;
     A.wflag = idx->wflag;
     A.wlist = idx->wlist;
@@ -1276,12 +1220,6 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
             hipLaunchKernelGGL(zero_i64, dim3((unsigned)((idx->max_chunks + 255) / 256)), dim3(256), 0, s, idx->hcnt,
                                idx->max_chunks);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        if (store) {
-            hipLaunchKernelGGL(store_table, dim3((unsigned)((RHG_KAP_SUB * L.B + 1 + 3) / 4)), dim3(256), 0, s, A);
-            hipLaunchKernelGGL(store_plan, dim3((unsigned)((nw * 64 + 255) / 256)), dim3(256), 0, s, A, nw);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if ((e = inclusive_scan_i64(idx->woff + 1, nw, idx->tmp, s)) != hipSuccess) return e;
         }
         if (items > 0) {
             hipLaunchKernelGGL(heavy_store_check, dim3(1), dim3(64), 0, s, A, nw, L.heavy_store);

@@ -141,3 +141,41 @@ def test_long_range_workspace_and_argument_checks_are_host_only():
     assert lib.rhg_long_range(10, None, fake, 0, 1, 1, fake, big, fake, fake, 10, fake, None) == P.RHG_EINVAL
     assert lib.rhg_long_range(10, fake, fake, 20, 5, 1, fake, big, fake, fake, 29, fake, None) == P.RHG_ECAPACITY
     assert lib.rhg_long_range(10, fake, fake, 20, 5, 1, fake, 64, fake, fake, 30, fake, None) == P.RHG_ECAPACITY
+
+
+def _header_structs():
+    """Field (name, type, pointer, count) lists of every `typedef struct {...}
+    NAME;` in include/rhg.h, comments removed."""
+    src = open(os.path.join(ROOT, "include", "rhg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", src, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            ty, rest = re.match(r"(\w+)\s+(.*)", decl).groups()
+            for item in rest.split(","):
+                m = re.match(r"(\*?)\s*(\w+)(?:\[(\d+)\])?$", item.strip())
+                fields.append((m.group(2), ty, bool(m.group(1)), int(m.group(3) or 1)))
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_match_the_header():
+    """Every struct the binding mirrors has the header's fields, in order, with
+    the same sizes (so the same offsets under natural alignment)."""
+    scalar = {"int64_t": C.c_int64, "uint64_t": C.c_uint64, "int32_t": C.c_int32, "double": C.c_double}
+    hs = _header_structs()
+    for name in ("rhg_params", "rhg_tuning", "rhg_stats", "rhg_graph_summary", "rhg_csr"):
+        cls = getattr(P, name)
+        assert [f[0] for f in cls._fields_] == [h[0] for h in hs[name]], name
+        for (fname, ftype), (_, hty, ptr, cnt) in zip(cls._fields_, hs[name]):
+            if ptr:
+                want = C.sizeof(C.c_void_p)
+            elif hty in scalar:
+                want = C.sizeof(scalar[hty]) * cnt
+            else:
+                want = C.sizeof(getattr(P, hty)) * cnt
+            assert C.sizeof(ftype) == want, (name, fname)

@@ -333,12 +333,14 @@ rhg_status rhg_set_profiling(int on);
 
 /* Average duration in ms and number of recorded launches of each phase
  * since profiling was last turned on (synchronises on the events).  Phases:
- * 0 sample, 1 keys+sort, 2 index (band starts + directory), 3 gather,
- * 4 plan (the small kernels around the searches: heavy-work plan, store
- * slots, their scans, heavy degrees, capacity check), 5 count (the search
- * kernel of the count pass), 6 scan (row offsets), 7 copy (the kernel
- * copying stored neighbours), 8 emit (the search kernel of the emit pass),
- * 9 rows (the row sort of canonical rows).  Each of 5, 7 and 8 brackets
+ * 0 sample, 1 keys+sort, 2 index (band starts + directory), 3 gather (with
+ * the neighbour store's slot plan and its scan), 4 plan (the small kernels
+ * around the searches: heavy-work plan, its scans, heavy degrees, capacity
+ * check), 5 count (the search kernel of the count pass), 6 scan (row
+ * offsets), 7 copy (the kernel copying stored neighbours, heavy and light
+ * rows), 8 emit (the search kernel of the emit pass: wavefronts whose store
+ * overflowed, or every query without the store), 9 rows (the row sort of
+ * canonical rows).  Each of 5, 7 and 8 brackets
  * exactly one kernel launch.  avg_ms, count: host arrays of at least 10
  * entries (cap). */
 rhg_status rhg_phase_times(double *avg_ms /* host */, int64_t *count /* host */, int cap);

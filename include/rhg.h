@@ -91,7 +91,8 @@ typedef struct {
                             * longest streams take); same bytes out         */
 } rhg_tuning;
 
-/* Device-side diagnostics of the last count/emit pass over an index. */
+/* Device-side diagnostics of the count and emit passes over an index,
+ * summed since the index was built (rhg_build_index clears them). */
 typedef struct {
     int64_t fp32_undecided;  /* pairs the FP32 screen passed to FP64          */
     int64_t dd_fallbacks;    /* pairs FP64 passed to double-double            */

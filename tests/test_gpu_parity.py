@@ -293,3 +293,28 @@ def test_c3_full_size_points_and_sampled_rows():
         mine = np.sort(col[rp[i]:rp[i + 1]].cpu().numpy())
         assert np.array_equal(mine, ocol[ptr[a_]:ptr[a_ + 1]]), (i, deg[i])
     _say("C3 rows checked", len(which), "degrees", deg[which].tolist())
+
+
+def test_count_and_emit_twice_on_one_index():
+    """The store's slot plan is made when the index is built: counting and
+    emitting a second time on the same index gives the same bytes."""
+    import torch
+    n, k, g = 30_000, 16.0, 2.4
+    params, a, R = _params_for(n, k, g, 77)
+    r, t, _ = O.sample(77, a, R, n)
+    idx = P.rhg_build_index(params, torch.from_numpy(r).cuda(), torch.from_numpy(t).cuda())
+    out = []
+    for _ in range(2):
+        rp = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        P.rhg_count_edges(idx, rp)
+        nnz = int(rp[-1].item())
+        col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+        P.rhg_emit_edges(idx, rp, col)
+        torch.cuda.synchronize()
+        out.append((rp.cpu().numpy(), col.cpu().numpy(), P.rhg_index_stats(idx)))
+    idx.free()
+    _say("twice:", out[0][2], out[1][2])
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2]["stage_fallbacks"] == 0 and out[0][2]["stored"] > 0
+    orp, ocol, _, _ = O.csr(r, t, R)
+    assert np.array_equal(out[1][0], orp) and np.array_equal(canonical(out[1][0], out[1][1]), ocol)

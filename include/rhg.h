@@ -121,7 +121,9 @@ typedef struct rhg_index rhg_index;  /* opaque, host-side handle */
  * degree is <= avg_degree, Eq. (22) being read with the middle term
  * (pi - 1) * zeta/alpha, zeta = 1, and evaluated in double-double.
  * Errors: RHG_EINVAL if n < 0 or n > 2^31 - 1, gamma <= 2 or NaN,
- * avg_degree <= 0 or NaN, or avg_degree >= n - 1 when n >= 2;
+ * avg_degree <= 0 or NaN, or avg_degree >= n - 1 when n >= 2, or if the
+ * solved R is 80 or more (the range of the search's FP32 records and of
+ * the screen's error bound; every call taking rhg_params refuses it too);
  * RHG_ENOROOT if the target exceeds the peak of Eq. (22).
  * n = 0 or 1 is valid (R is then that of n = 2 and the graph is empty). */
 rhg_status rhg_plan(int64_t n, double avg_degree, double gamma, uint64_t seed,
@@ -130,6 +132,16 @@ rhg_status rhg_plan(int64_t n, double avg_degree, double gamma, uint64_t seed,
 /* Same with alpha and R given directly (0.5 < alpha, 0 < R < 80). */
 rhg_status rhg_plan_radius(int64_t n, double alpha, double R, uint64_t seed,
                            rhg_params *out /* host */);
+
+/* The radial band layout the index would use for these parameters and
+ * tuning (NULL = automatic): the flat-array form of the polar quadtree's
+ * rings (Sec. 3.1).  Band j holds E[j] <= r < E[j+1] (the last band also
+ * r = R).  *bands receives B; edges (host, cap doubles) receives
+ * E[0 .. min(B + 1, cap)).  Host only, no device work; for tests and tools
+ * that place points on band edges.  Errors: RHG_EINVAL for NULL pointers
+ * or invalid params. */
+rhg_status rhg_layout_bands(const rhg_params *p /* host */, const rhg_tuning *t /* host, may be NULL */,
+                            double *edges /* host */, int cap, int *bands /* host */);
 
 /* ------------------------------------------------------------------ */
 /* Sampling (Algorithm 1, angular and radial draws; Eq. (1)).          */
@@ -192,8 +204,12 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
  * the index's own scratch), so col_idx is the same bytes for every tuning.
  * col_capacity is the number of int32 slots in col_idx; the call reads
  * row_ptr[n] back (one synchronisation) and returns RHG_ECAPACITY if it
- * exceeds col_capacity, or if canonical rows are asked for a graph whose mean
- * degree passes 4096 (sort such a graph with rhg_sort_rows instead). */
+ * exceeds col_capacity, or if canonical rows are asked for a graph with more
+ * entries than the index's row-sort scratch was sized for (twice the
+ * planner's upper estimate of 2m, plus 2^23; sort such a graph with
+ * rhg_sort_rows instead).  The copy and emit kernels check every row they
+ * write against its count; a disagreement is RHG_EINTERNAL from the next
+ * rhg_index_stats (rhg_generate checks it itself). */
 rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx,
                           int64_t col_capacity, int canonical_rows, void *stream);
 
@@ -314,10 +330,12 @@ typedef struct {
 } rhg_csr;
 
 /* Plans, samples, indexes, counts, scans and emits one graph.  All device
- * memory (points, index workspace, CSR) comes from `alloc`; the only host
- * synchronisation is the 8-byte read of 2m before col_idx is allocated.
+ * memory (points, index workspace, CSR) comes from `alloc`; the host
+ * synchronises for the 8-byte read of 2m before col_idx is allocated and
+ * for the 8-byte read of the emit pass's row-length check at the end.
  * canonical_rows as for rhg_emit_edges.
- * Errors: those of rhg_plan, and RHG_ENOMEM if `alloc` returns NULL. */
+ * Errors: those of rhg_plan, RHG_ENOMEM if `alloc` returns NULL, and
+ * RHG_EINTERNAL if an emitted row's length disagrees with its count. */
 rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t seed,
                         const rhg_tuning *t /* host, may be NULL */,
                         rhg_alloc_fn alloc, void *alloc_ctx, int canonical_rows,
@@ -360,7 +378,9 @@ const char *rhg_phase_name(int phase);
  * row_ptr: n + 1 int64; col_idx: col_capacity int32 slots.  *overflow
  * (device int32) is set to 1 when 2m > col_capacity -- then row_ptr is
  * valid but col_idx is left unwritten, and the caller can emit again into a
- * buffer of row_ptr[n] slots -- and to 0 otherwise. */
+ * buffer of row_ptr[n] slots -- and to 0 otherwise.  After the emit, bit 1
+ * (value 2) is added when an emitted row's length disagreed with its count
+ * (an internal error; the rows are then not to be trusted). */
 rhg_status rhg_generate_async(const rhg_params *p /* host */, const rhg_tuning *t /* host, may be NULL */,
                               double *r, double *theta, void *workspace, size_t workspace_bytes,
                               int64_t *row_ptr, int32_t *col_idx, int64_t col_capacity,

@@ -84,6 +84,7 @@ def load():
         "rhg_plan_radius": (i32, [i64, d, d, u64, P(rhg_params)]),
         "rhg_sample_points": (i32, [P(rhg_params), vp, vp, vp]),
         "rhg_index_workspace_bytes": (C.c_size_t, [P(rhg_params), P(rhg_tuning)]),
+        "rhg_layout_bands": (i32, [P(rhg_params), P(rhg_tuning), P(C.c_double), i32, P(C.c_int)]),
         "rhg_build_index": (i32, [P(rhg_params), vp, vp, P(rhg_tuning), vp, C.c_size_t, i32, P(vp), vp]),
         "rhg_count_edges": (i32, [vp, vp, vp]),
         "rhg_emit_edges": (i32, [vp, vp, vp, i64, i32, vp]),
@@ -167,6 +168,14 @@ def rhg_sample_points(p: rhg_params, r, theta, stream=None):
     assert r.dtype == theta.dtype and r.is_cuda and theta.is_cuda
     assert r.numel() >= p.n and theta.numel() >= p.n and r.is_contiguous() and theta.is_contiguous()
     _check(load().rhg_sample_points(C.byref(p), _ptr(r), _ptr(theta), _stream(stream)))
+
+
+def rhg_layout_bands(p: rhg_params, tuning: Optional[dict] = None):
+    """Band edges E[0..B] of the index layout for these parameters (host only)."""
+    buf = (C.c_double * 65)()
+    b = C.c_int()
+    _check(load().rhg_layout_bands(C.byref(p), _tuning(tuning), buf, 65, C.byref(b)))
+    return [buf[j] for j in range(b.value + 1)]
 
 
 def rhg_index_workspace_bytes(p: rhg_params, tuning: Optional[dict] = None) -> int:
@@ -435,12 +444,19 @@ class Batch:
         the original buffer on later launches, so call this after each."""
         import torch
         torch.cuda.synchronize()
-        bad = torch.nonzero(self.overflow[:len(self.bufs)]).flatten().tolist()
+        flags = self.overflow[:len(self.bufs)].cpu()
+        broken = torch.nonzero(flags & 2).flatten().tolist()
+        if broken:
+            raise RhgError(RHG_EINTERNAL, "emit pass disagreed with the count pass for graphs %s" % broken)
+        bad = torch.nonzero(flags & 1).flatten().tolist()
         for i in bad:
             b = self.bufs[i]
             b.col = torch.empty(int(b.row_ptr[-1].item()), dtype=torch.int32, device=b.r.device)
             flag = torch.zeros(1, dtype=torch.int32, device=b.r.device)
             rhg_generate_async(b.params, b.r, b.theta, b.ws, b.row_ptr, b.col, flag, tuning=b.tuning, stream=stream)
+            torch.cuda.synchronize()
+            if int(flag.item()) != 0:
+                raise RhgError(RHG_EINTERNAL, "refill of graph %d reported flag %d" % (i, int(flag.item())))
         return bad
 
     def destroy(self):

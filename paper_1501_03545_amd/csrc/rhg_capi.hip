@@ -191,8 +191,11 @@ static rhg_status check_params(const rhg_params *p, const char *who)
 {
     if (!p) return fail(RHG_EINVAL, std::string(who) + ": params is NULL");
     if (p->n < 0 || p->n > 2147483647LL) return fail(RHG_EINVAL, std::string(who) + ": n out of range");
-    if (!(p->alpha > 0.5) || !(p->R > 0.0) || !(p->R < 300.0) || !(p->cosh_R >= 1.0) || !(p->cosh_aR_m1 > 0.0))
+    if (!(p->alpha > 0.5) || !(p->R > 0.0) || !(p->cosh_R >= 1.0) || !(p->cosh_aR_m1 > 0.0))
         return fail(RHG_EINVAL, std::string(who) + ": params were not filled by rhg_plan");
+    // the search's FP32 records (e^r / sqrt(2 cosh R) and its kin) and the
+    // screen's error bound need R < 80
+    if (!(p->R < 80.0)) return fail(RHG_EINVAL, std::string(who) + ": R must be below 80");
     return RHG_OK;
 }
 
@@ -204,6 +207,19 @@ rhg_status rhg_sample_points(const rhg_params *p, double *r, double *theta, void
     if (p->n > 0 && (!r || !theta)) return fail(RHG_EINVAL, "rhg_sample_points: NULL output");
     PhaseScope ps(RHG_PHASE_SAMPLE, (hipStream_t)stream);
     RHG_HIP(launch_sample(*p, r, theta, (hipStream_t)stream));
+    return RHG_OK;
+}
+
+rhg_status rhg_layout_bands(const rhg_params *p, const rhg_tuning *t, double *edges, int cap, int *bands)
+{
+    g_last_error.clear();
+    rhg_status st = check_params(p, "rhg_layout_bands");
+    if (st != RHG_OK) return st;
+    if (!edges || !bands || cap < 0) return fail(RHG_EINVAL, "rhg_layout_bands: NULL output");
+    Layout L;
+    make_layout(*p, t, &L);
+    *bands = L.B;
+    for (int j = 0; j <= L.B && j < cap; ++j) edges[j] = L.E[j];
     return RHG_OK;
 }
 
@@ -613,7 +629,13 @@ rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t see
         rhg_index_free(idx);
         return st;
     }
+    // the emit and copy kernels' row-length check (one more 8-byte read)
+    unsigned long long mismatch = 0;
+    e = hipMemcpyAsync(&mismatch, idx->stats + ST_EMIT_MISMATCH, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     rhg_index_free(idx);
+    if (e != hipSuccess) return check_hip(e, "rhg_generate (consistency check)");
+    if (mismatch) return fail(RHG_EINTERNAL, "rhg_generate: the emit pass disagreed with the count pass");
     out->n = n;
     out->nnz = nnz;
     out->row_ptr = row_ptr;

@@ -128,6 +128,8 @@ rhg_status plan(int64_t n, double kbar, double gamma, uint64_t seed, rhg_params 
     if (n >= 2) {
         rhg_status s = solve_radius((double)n, p.alpha, kbar, &p.R);
         if (s != RHG_OK) return s;
+        if (!(p.R < 80.0))
+            return fail(RHG_EINVAL, "rhg_plan: the requested degree needs R >= 80, beyond the search's range");
     } else {
         p.R = 1.0;  // no pairs: any radius gives the empty graph
     }

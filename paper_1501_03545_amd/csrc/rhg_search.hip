@@ -15,9 +15,15 @@
 //   P32  cosh d / cosh R = e'_q m'_c + m'_q e'_c + s'_q s'_c sin^2(dtheta/2)
 //        with per-point FP32 values e' = e^r/sqrt(2 cosh R),
 //        m' = e^-r/sqrt(2 cosh R), s' = sinh r sqrt(2/cosh R) and dtheta
-//        formed in FP64 then rounded; every term is non-negative, so the
-//        value is within 19 * 2^-24 (relative) of the exact ratio.  Values
-//        outside 1 -/+ 2^-18 are final.
+//        formed in FP64 then rounded.  Every term is non-negative, so the
+//        relative error of the sum is the largest of its terms': with
+//        u = 2^-24, at most 21 u where the degree-11 sine polynomial runs
+//        (record roundings 3 u, angle cast u, five Horner FMAs with rounded
+//        coefficients and a rounded x^2 4.7 u at x = pi/2, truncation
+//        0.96 u, the products s*s, s'*s' and the final FMAs), and at most
+//        12 u on the two-term branch (angle below 2^-5).  Underflow adds at
+//        most 2^-34 absolute for R < 80.  Values outside 1 -/+ 2^-18 (64 u)
+//        are final.
 //   P64  the same sum in FP64 from r and theta (margin 2^-30), and
 //   DD   double-double for the rest.
 //
@@ -196,16 +202,20 @@ __device__ __forceinline__ bool band_inside(const SearchArgs &A, double rq, int 
 }
 
 // Conservative half-width of band j's window for a query with FP32 record
-// (eq, mq, sq); >= 3 means "scan the whole band".  X = (1 - cosh(r_q -
-// E[j])/C) / (2 sinh r_q sinh E[j] / C) from the normalised record; for
-// X <= 1/4, 2 asin(sqrt X) <= 2 sqrt(X) (1 + X/5).  The FP32 rounding of X
-// (a few 1e-7 relative; the band edges keep cosh(r_q - E[j]) / C <= e^-E[1])
-// is covered by the factor 1 + 2^-12 and the 2^-40 absolute pad.
+// (eq, mq, sq); >= 3 means "scan the whole band".  X = (1 - N) / (s'_q
+// s'(E[j])), N = cosh(r_q - E[j]) / C, from the normalised record; for
+// X <= 1/4, 2 asin(sqrt X) <= 2 sqrt(X) (1 + X/5).  N carries at most 4 u
+// relative error (u = 2^-24), so with 1 - N >= 1/64 (else the whole band)
+// the computed X is within 260 u of the exact one and the window within
+// about 135 u; the factor 1 + 2^-12 (4096 u) and the 2^-40 absolute pad
+// (which also covers the binary64 angle arithmetic of the window ends)
+// keep it conservative.
 __device__ __forceinline__ double window_w(const SearchArgs &A, float eq, float mq, float sq, int j)
 {
     const float shl = A.sh_lo[j];
     if (A.E[j] < 0.25 || shl == 0.0f || sq == 0.0f) return 4.0;  // ill-conditioned near the centre
     const float num = 1.0f - fmaf(eq, A.em_lo[j], mq * A.ep_lo[j]);
+    if (!(num >= 0x1p-6f)) return 4.0;  // N near 1: cancellation in 1 - N (also catches NaN)
     const float X = num / (sq * shl);
     if (!(X < 0.25f)) {
         if (!(X < 0.999f)) return 4.0;  // also catches NaN
@@ -441,6 +451,9 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
     // counts first
     __syncthreads();
     if (!EMIT && threadIdx.x == 0) A.hcnt[c] = total;
+    // the emit pass finds exactly what the count pass counted in this chunk
+    if (EMIT && threadIdx.x == 0 && total != A.hcnt[c] - (c ? A.hcnt[c - 1] : 0))
+        atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
 }
 
 // Emit pass, stored heavy rows: wavefront-wide copy of chunk c's neighbours
@@ -493,8 +506,11 @@ __device__ __forceinline__ int wave_excl_sum(int v, int lane, int *total)
 // Upper bound of band j's window for a query with normalised record
 // (e', m', s'): dropping the non-negative cosh(r_q - E[j]) / cosh R term
 // gives X <= 1 / (s'_q s'(E[j])), so sqrt X <= rs_q * rs_j with the reciprocal
-// square roots computed once per query and per band.  Above X = 1/4 it falls
-// back to window_w.
+// square roots computed once per query and per band.  rs_j is raised by
+// 2^-20 (16 u), more than the 1-ulp reciprocal square root of the query, the
+// record roundings and the product lose, so rs_q * rs_j >= sqrt X; the
+// polynomial's roundings (3 u) are covered by the factor 1 + 2^-12.  Above
+// X = 1/4 it falls back to window_w.
 __device__ __forceinline__ double window_fast(const SearchArgs &A, float rsq, float eq, float mq, float sq, int j)
 {
     if (A.rs_lo[j] == 0.0f || A.E[j] < 0.25) return window_w(A, eq, mq, sq, j);
@@ -1032,6 +1048,8 @@ __device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_
         at += mine;
         wave_sync();  // the stage is rewritten by the next chunk
     }
+    // every row must come out exactly as long as the count pass counted it
+    if (active && at != dst + deg) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
 }
 
 // ------------------------------------------------------------ kernels
@@ -1129,6 +1147,13 @@ __global__ void emit_prologue(const int64_t *row_ptr, int64_t n, int64_t cap, in
     if (threadIdx.x == 0 && overflow) *overflow = (cap >= 0 && row_ptr[n] > cap) ? 1 : 0;
 }
 
+// After the emit pass: bit 1 of the flag reports rows that the emit or copy
+// kernels found longer or shorter than the count pass had counted them.
+__global__ void emit_epilogue(const unsigned long long *stats, int32_t *overflow)
+{
+    if (threadIdx.x == 0 && stats[ST_EMIT_MISMATCH]) *overflow |= 2;
+}
+
 __global__ void __launch_bounds__(256) zero_i64(int64_t *p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1176,8 +1201,9 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.R = p.R;
     A.C = p.cosh_R;
     A.C_lo = p.cosh_R_lo;
-    // R < 80 (rhg_plan_radius): the FP32 record neither overflows nor loses range
-    A.use_p32 = L.fp64_only ? 0 : 1;
+    // The FP32 record stays finite and the screen's bound holds for R < 80,
+    // the range every entry point accepts.
+    A.use_p32 = (!L.fp64_only && p.R < 80.0) ? 1 : 0;
     A.stream_stage = L.no_stream_stage ? 0 : 1;
     A.band_start = idx->band_start;
     A.dir = idx->dir;
@@ -1256,6 +1282,10 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
             hipLaunchKernelGGL(search_kernel<M_COUNT>, g, b, 0, s, A, row_ptr, col_idx);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (emit && overflow) {
+        hipLaunchKernelGGL(emit_epilogue, dim3(1), dim3(64), 0, s, (const unsigned long long *)idx->stats, overflow);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (!emit && items > 0) {
         PhaseScope ps(RHG_PHASE_PLAN, s);
         if ((e = inclusive_scan_i64(idx->hcnt, idx->max_chunks, idx->tmp, s)) != hipSuccess) return e;

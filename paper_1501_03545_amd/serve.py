@@ -214,6 +214,9 @@ class GpuExecutor:
         buf, host, ev, params, tuning = self.state[req.rid]
         if not ev.query():
             return False
+        if int(host[1]) & 2:
+            import paper_1501_03545_amd as P
+            raise P.RhgError(P.RHG_EINTERNAL, "request %d: emit pass disagreed with the count pass" % req.rid)
         if int(host[1]) != 0:
             self.retries += 1
             with self.torch.cuda.stream(self.streams[slot]):

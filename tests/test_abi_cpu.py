@@ -179,3 +179,39 @@ def test_binding_structs_match_the_header():
             else:
                 want = C.sizeof(getattr(P, hty)) * cnt
             assert C.sizeof(ftype) == want, (name, fname)
+
+
+def test_radius_range_is_refused_before_any_device_work():
+    """The search's FP32 records and the screen's error bound hold for
+    R < 80; a hand-filled rhg_params beyond that is refused by every call
+    that takes one (host-side checks, no device work), and the planner
+    refuses to produce one."""
+    import ctypes as C
+    lib = P.load()
+    p = P.rhg_plan_radius(1000, 0.75, 79.5, 1)
+    E = P.rhg_layout_bands(p)
+    assert E[0] == 0.0 and E[-1] == 79.5
+    p.R = 85.0  # hand-filled: cosh fields stay as they were
+    fake = C.c_void_p(0x1000)
+    assert lib.rhg_sample_points(C.byref(p), fake, fake, None) == P.RHG_EINVAL
+    assert b"R must be below 80" in lib.rhg_last_error()
+    out = C.c_void_p()
+    assert lib.rhg_build_index(C.byref(p), fake, fake, None, fake, 1 << 40, 0, C.byref(out), None) == P.RHG_EINVAL
+    flag = C.c_void_p(0x2000)
+    assert lib.rhg_generate_async(C.byref(p), None, fake, fake, fake, 1 << 40, fake, fake, 10, flag, None) == P.RHG_EINVAL
+    b = C.c_int()
+    buf = (C.c_double * 65)()
+    assert lib.rhg_layout_bands(C.byref(p), None, buf, 65, C.byref(b)) == P.RHG_EINVAL
+    with pytest.raises(P.RhgError):
+        P.rhg_plan_radius(1000, 0.75, 80.0, 1)
+    # a degree so small that Eq. (22) would need R >= 80
+    with pytest.raises(P.RhgError) as ei:
+        P.rhg_plan(2_000_000_000, 1e-12, 2.5, 1)
+    assert ei.value.status in (P.RHG_EINVAL, P.RHG_ENOROOT)
+
+
+def test_layout_bands_follow_the_tuning():
+    p = P.rhg_plan(10**6, 10.0, 2.7, 2)
+    E = P.rhg_layout_bands(p, {"inner_radius": 10.0, "band_width": 2.0})
+    assert E[:2] == [0.0, 10.0] and E[-1] == p.R
+    assert all(0.0 < b - a <= 2.0 + 1e-12 for a, b in zip(E[1:], E[2:]))

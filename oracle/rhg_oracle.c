@@ -243,18 +243,27 @@ static int edge_quad(double ri, double ti, double rj, double tj, double R, orc_s
     return L <= C;
 }
 
-static int edge64(double ri, double ti, double rj, double tj, double R, double coshR, orc_stats *st)
+/* shi, shj: sinh(ri), sinh(rj) as the libm returns them (the callers that
+ * test one point against many pass them in from a table of the same values,
+ * which leaves every operation and its result unchanged). */
+static int edge64s(double ri, double ti, double shi, double rj, double tj, double shj, double R, double coshR,
+                   orc_stats *st)
 {
     double tmax = ti > tj ? ti : tj, tmin = ti > tj ? tj : ti;
     double d = tmax - tmin;
     /* the short way round; TWO_PI_D - tmax is exact (tmax > pi) */
     if (d > M_PI) d = ((TWO_PI_D - tmax) + tmin) + TWO_PI_RES_D;
     double s = sin(0.5 * d);
-    double L = cosh(ri - rj) + 2.0 * sinh(ri) * sinh(rj) * s * s;
+    double L = cosh(ri - rj) + 2.0 * shi * shj * s * s;
     if (L < coshR * (1.0 - 1e-9)) return 1;
     if (L > coshR * (1.0 + 1e-9)) return 0;
     st->quad++;
     return edge_quad(ri, ti, rj, tj, R, st);
+}
+
+static int edge64(double ri, double ti, double rj, double tj, double R, double coshR, orc_stats *st)
+{
+    return edge64s(ri, ti, sinh(ri), rj, tj, sinh(rj), R, coshR, st);
 }
 
 /* Single pair decision (i != j assumed by the caller). */
@@ -323,35 +332,122 @@ void orc_csr_fill(int64_t n, const double *r, const double *theta, double R,
 
 /* Neighbours of the vertices in rows[0..nrows), ascending, each row tested
  * against all n points.  out_ptr gets nrows + 1 offsets into out (capacity
- * cap); returns -1 if cap is too small, else the total neighbour count. */
+ * cap); returns -1 if cap is too small, else the total neighbour count.
+ * Rows are taken ORC_ROW_BLOCK at a time; the threads split the vertices
+ * into contiguous static ranges and keep their hits in thread order, so each
+ * row comes out ascending when the threads' lists are joined in order. */
+#define ORC_ROW_BLOCK 32
+typedef struct { int64_t *v; int64_t len, cap; } orc_list;
+
+static void list_push(orc_list *l, int64_t x)
+{
+    if (l->len == l->cap) {
+        l->cap = l->cap ? 2 * l->cap : 1024;
+        l->v = (int64_t *)realloc(l->v, (size_t)l->cap * sizeof(int64_t));
+    }
+    l->v[l->len++] = x;
+}
+
 int64_t orc_rows(int64_t n, const double *r, const double *theta, double R,
                  const int64_t *rows, int64_t nrows, int64_t *out_ptr, int32_t *out,
                  int64_t cap, int nthreads, int64_t stats[2])
 {
     double coshR = orc_cosh(R);
-    uint8_t *flag = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
     int64_t q = 0, t = 0, total = 0, overflow = 0;
     if (nthreads > 0) omp_set_num_threads(nthreads);
+    const int T = omp_get_max_threads();
+    double *sh = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    orc_list *hits = (orc_list *)calloc((size_t)T, sizeof(orc_list));
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) sh[j] = sinh(r[j]);
     out_ptr[0] = 0;
-    for (int64_t a = 0; a < nrows; ++a) {
-        int64_t i = rows[a];
-        /* test row i against every vertex, in parallel over the vertices */
-        #pragma omp parallel for schedule(static) reduction(+:q,t)
-        for (int64_t j = 0; j < n; ++j) {
+    for (int64_t a0 = 0; a0 < nrows; a0 += ORC_ROW_BLOCK) {
+        const int64_t nb = nrows - a0 < ORC_ROW_BLOCK ? nrows - a0 : ORC_ROW_BLOCK;
+        /* hits are (row in block) * 2^40 + j, in ascending j per thread */
+        #pragma omp parallel num_threads(T) reduction(+:q,t)
+        {
+            orc_list *l = &hits[omp_get_thread_num()];
+            l->len = 0;
             orc_stats st = {0, 0};
-            flag[j] = (uint8_t)(j != i && edge64(r[i], theta[i], r[j], theta[j], R, coshR, &st));
+            #pragma omp for schedule(static)
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t b = 0; b < nb; ++b) {
+                    const int64_t i = rows[a0 + b];
+                    if (j != i && edge64s(r[i], theta[i], sh[i], r[j], theta[j], sh[j], R, coshR, &st))
+                        list_push(l, (b << 40) | j);
+                }
             q += st.quad; t += st.ties;
         }
-        for (int64_t j = 0; j < n; ++j) {
-            if (!flag[j]) continue;
-            if (total < cap) out[total] = (int32_t)j; else overflow = 1;
-            ++total;
+        for (int64_t b = 0; b < nb; ++b) {
+            for (int th = 0; th < T; ++th)
+                for (int64_t k = 0; k < hits[th].len; ++k) {
+                    if ((hits[th].v[k] >> 40) != b) continue;
+                    if (total < cap) out[total] = (int32_t)(hits[th].v[k] & ((1LL << 40) - 1));
+                    else overflow = 1;
+                    ++total;
+                }
+            out_ptr[a0 + b + 1] = total;
         }
-        out_ptr[a + 1] = total;
     }
-    free(flag);
+    for (int th = 0; th < T; ++th) free(hits[th].v);
+    free(hits);
+    free(sh);
     if (stats) { stats[0] += q; stats[1] += t; }
     return overflow ? -1 : total;
+}
+
+/* Whole-graph summary without storing the graph: every pair i < j is tested
+ * once; deg[] gets the degrees and fp[0], fp[1] the wrapping sum and the xor,
+ * over the edges, of mix64(i * 2^32 + j) -- an order-independent fingerprint
+ * of the edge set.  mix64 is the finaliser of Steele, Lea and Flood's
+ * SplitMix64 ("Fast splittable pseudorandom number generators", OOPSLA 2014). */
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_mix64(uint64_t z) { return mix64(z); }
+
+void orc_pair_scan(int64_t n, const double *r, const double *theta, double R, int32_t *deg,
+                   uint64_t fp[2], int nthreads, int64_t stats[2])
+{
+    double coshR = orc_cosh(R);
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const int T = omp_get_max_threads();
+    double *sh = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    int32_t *part = (int32_t *)calloc((size_t)T * (size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    uint64_t fsum = 0, fxor = 0;
+    int64_t q = 0, t = 0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) sh[j] = sinh(r[j]);
+    #pragma omp parallel num_threads(T) reduction(+:q,t,fsum) reduction(^:fxor)
+    {
+        int32_t *d = part + (size_t)omp_get_thread_num() * (size_t)n;
+        orc_stats st = {0, 0};
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j)
+                if (edge64s(r[i], theta[i], sh[i], r[j], theta[j], sh[j], R, coshR, &st)) {
+                    d[i]++;
+                    d[j]++;
+                    const uint64_t h = mix64(((uint64_t)i << 32) | (uint64_t)j);
+                    fsum += h;
+                    fxor ^= h;
+                }
+        q += st.quad; t += st.ties;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t c = 0;
+        for (int th = 0; th < T; ++th) c += part[(size_t)th * (size_t)n + i];
+        deg[i] = c;
+    }
+    free(part);
+    free(sh);
+    fp[0] = fsum;
+    fp[1] = fxor;
+    if (stats) { stats[0] += q; stats[1] += t; }
 }
 
 int orc_max_threads(void) { return omp_get_max_threads(); }

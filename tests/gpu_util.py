@@ -66,3 +66,34 @@ def pipeline_compare(g, r_o, t_o, R, orp, ocol):
     a = set((np.repeat(np.arange(n), np.diff(rp)) * n + col).tolist())
     b = set((np.repeat(np.arange(n), np.diff(orp)) * n + ocol).tolist())
     return len(a ^ b)
+
+
+def oracle_check(O, g, d, full_limit=20_000, rows=24):
+    """One generated graph g (theta, r, row_ptr, col_idx on the device) of
+    request d against the oracle: the points bit for bit, then the whole edge
+    set for n <= full_limit, else `rows` rows (stratified by radius, plus the
+    largest degrees) each tested against all n points.  Returns what it
+    checked."""
+    n, k, gamma, seed = d["n"], d["avg_degree"], d["gamma"], d["seed"]
+    a, R = O.solve_R(n, k, gamma)
+    assert (a, R) == (g.params.alpha, g.params.R)
+    if n <= full_limit:
+        _, _, r_o, t_o, orp, ocol, st = O.generate(n, k, gamma, seed)
+        assert st["ties"] == 0
+        assert pipeline_compare(g, r_o, t_o, R, orp, ocol) == 0
+        return "full"
+    r_o, t_o, hard = O.sample(seed, a, R, n)
+    assert hard == 0
+    assert np.array_equal(g.theta.cpu().numpy(), t_o)
+    assert np.array_equal(g.r.cpu().numpy(), r_o)
+    rp = g.row_ptr.cpu().numpy()
+    col = g.col_idx.cpu().numpy()
+    deg = np.diff(rp)
+    order = np.argsort(r_o, kind="stable")
+    which = np.unique(np.concatenate([order[np.linspace(0, n - 1, rows - rows // 3).astype(np.int64)],
+                                      np.argsort(deg)[-(rows // 3):]]).astype(np.int64))
+    ptr, ocol, _, nt = O.rows(r_o, t_o, R, which)
+    assert nt == 0
+    for a_, i in enumerate(which):
+        assert np.array_equal(np.sort(col[rp[i]:rp[i + 1]]), ocol[ptr[a_]:ptr[a_ + 1]]), (d, i)
+    return "rows"

@@ -11,7 +11,7 @@ import pytest
 import oracle as O
 import paper_1501_03545_amd as P
 from paper_1501_03545_amd import workloads as W
-from gpu_util import pipeline_compare
+from gpu_util import oracle_check, pipeline_compare
 
 pytestmark = pytest.mark.gpu
 
@@ -69,17 +69,15 @@ def test_batch_equals_graphs_alone_and_oracle():
     torch.cuda.synchronize()
     assert batch.fix_overflows() == []
     torch.cuda.synchronize()
-    checked = 0
+    kinds = []
     for g, b in enumerate(bufs):
         assert _same(b, _alone(b)), "graph %d differs from the same graph generated alone" % g
-        if b.params.n <= 6000:
-            d = draws[g]
-            _say("oracle", g, d)
-            a, R, r_o, t_o, orp, ocol, st = O.generate(d["n"], d["avg_degree"], d["gamma"], d["seed"])
-            assert (a, R) == (b.params.alpha, b.params.R)
-            assert pipeline_compare(b.graph(), r_o, t_o, R, orp, ocol) == 0
-            checked += 1
-    assert checked >= 5
+        # every graph against the oracle: whole graphs up to n = 20000,
+        # sampled rows against all points above
+        _say("oracle", g, draws[g])
+        kinds.append(oracle_check(O, b.graph(), draws[g]))
+    _say("oracle checks", {k: kinds.count(k) for k in set(kinds)})
+    assert kinds.count("full") >= 10
 
 
 def test_batch_overflow_flags_and_replays():

@@ -281,18 +281,24 @@ def test_c3_full_size_points_and_sampled_rows():
     assert hard == 0
     assert np.array_equal(tg, t_o)
     assert np.array_equal(rg, r_o)
+    # 512 rows stratified by radius quantile, the 32 innermost points (the
+    # hubs), the 32 largest degrees and 32 random rows, each against all 1e8
+    # points by brute force
     rng = np.random.default_rng(33)
-    qs = np.quantile(r_o, [0.0, 0.001, 0.01, 0.1, 0.5, 0.9, 1.0])
-    strat = [int(np.argmin(np.abs(r_o - q))) for q in qs]
-    top = np.argpartition(deg, -6)[-6:].tolist()
-    which = np.unique(np.array(strat + top + rng.integers(0, n, 6).tolist(), dtype=np.int64))
+    order = np.argsort(r_o, kind="stable")
+    strat = order[np.linspace(0, n - 1, 512).astype(np.int64)]
+    inner = order[:32]
+    top = np.argpartition(deg, -32)[-32:]
+    which = np.unique(np.concatenate([strat, inner, top, rng.integers(0, n, 32)]).astype(np.int64))
+    del order
+    _say("C3 brute-force rows", len(which))
     ptr, ocol, _, nt = O.rows(r_o, t_o, R, which)
     assert nt == 0
     rp = row_ptr.cpu().numpy()
     for a_, i in enumerate(which):
         mine = np.sort(col[rp[i]:rp[i + 1]].cpu().numpy())
         assert np.array_equal(mine, ocol[ptr[a_]:ptr[a_ + 1]]), (i, deg[i])
-    _say("C3 rows checked", len(which), "degrees", deg[which].tolist())
+    _say("C3 rows checked", len(which), "entries", int(ptr[-1]), "max degree", int(deg[which].max()))
 
 
 def test_count_and_emit_twice_on_one_index():

@@ -5,7 +5,9 @@ import sys
 
 import pytest
 
+import oracle as O
 import paper_1501_03545_amd as P
+from gpu_util import oracle_check
 from paper_1501_03545_amd import serve as S
 from paper_1501_03545_amd import workloads as W
 
@@ -54,8 +56,14 @@ def test_results_in_the_mix_equal_results_alone():
     _say("mix", st)
     assert st["requests"] == len(stream) and st["rejected"] == 0
     assert st["max_inflight"] >= 8, "requests did not overlap"
+    kinds = []
     for rid, (_, d) in enumerate(stream):
         assert _same(srv.kept[rid], _alone(d)), (rid, d)
+        # and every served result against the oracle: whole graphs up to
+        # n = 20000, sampled rows against all points above
+        kinds.append(oracle_check(O, srv.kept[rid].graph(), d))
+    _say("oracle checks", {k: kinds.count(k) for k in set(kinds)})
+    assert kinds.count("full") >= 10
     srv.kept.clear()
 
 

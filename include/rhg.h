@@ -75,13 +75,14 @@ typedef struct {
     double inner_radius;   /* radius below which all points share one band    */
     int32_t cell_target;   /* mean points per angular cell                    */
     int32_t heavy_points;  /* expected points searched one per workgroup      */
-    int32_t no_stage;      /* 0: the count pass also stores each query's
-                            * tested neighbours in the workspace and the emit
-                            * pass copies them (one search); nonzero: the emit
-                            * pass repeats the search (smaller workspace)     */
-    int32_t no_heavy_store; /* nonzero: store only the light queries'
-                            * neighbours; the emit pass searches the heavy
-                            * queries again (smaller workspace)              */
+    int32_t sweep_max;     /* a wavefront's union window (all its queries'
+                            * windows in one band) of at most this many
+                            * candidates is read once and swept by every
+                            * lane; 0: automatic (512); negative: swept only
+                            * where the queries' windows overlap           */
+    int32_t sweep_linear;  /* nonzero: lanes filter every candidate of a
+                            * swept chunk instead of binary-searching their
+                            * window's start (slower; same bytes out)       */
     int32_t fp64_only;     /* nonzero: no FP32 screen, every candidate is
                             * decided in binary64 (double-double near the
                             * threshold): the plain path, same edge set      */
@@ -97,11 +98,10 @@ typedef struct {
     int64_t fp32_undecided;  /* pairs the FP32 screen passed to FP64          */
     int64_t dd_fallbacks;    /* pairs FP64 passed to double-double            */
     int64_t ties;            /* pairs double-double could not separate        */
-    int64_t stage_fallbacks; /* wavefronts of 64 light queries whose stored
-                              * neighbours overflowed their slots; the emit
-                              * pass searched them again                      */
-    int64_t stored;          /* neighbours the count pass stored (copied by
-                              * the emit pass)                                */
+    int64_t swept;           /* candidates the count passes read into swept
+                              * chunks (light queries)                        */
+    int64_t tests;           /* pair tests of the count passes' light queries
+                              * (the candidates inside a query's window)      */
     int64_t register_streams; /* per-query candidate streams (one per light
                               * wavefront and band) read through registers:
                               * those longer than 4096 entries, or all of
@@ -183,9 +183,8 @@ rhg_status rhg_build_index(const rhg_params *p /* host */, const double *r,
 
 /* Runs the neighbour search and writes the CSR row offsets: row_ptr[0] = 0,
  * row_ptr[i + 1] - row_ptr[i] = deg(i) (device, n + 1 int64); row_ptr[n] =
- * 2m.  Unless the tuning sets no_stage, the neighbours found by per-point
- * tests are also stored in the index workspace, in slots sized by the
- * expected degree at the point's radius, for rhg_emit_edges.  Asynchronous. */
+ * 2m.  Nothing but the degrees is kept: the emit pass searches again.
+ * Asynchronous. */
 rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
 
 /* ------------------------------------------------------------------ */
@@ -193,21 +192,18 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
 /* ------------------------------------------------------------------ */
 
 /* Writes the neighbours of vertex i to col_idx[row_ptr[i] .. row_ptr[i+1])
- * (device, int32): stored neighbours are copied, and the search is repeated
- * for the heavy queries and for stored slots that overflowed (or for every
- * query with no_stage).  row_ptr must be the output of rhg_count_edges on the
- * same index, and the call must follow that count pass (it reads what the
- * count pass stored).  Each undirected edge appears in both rows; there are
- * no self-loops.  canonical_rows = 0: rows are in search order,
- * deterministic for a given tuning and the same with and without staging.
- * canonical_rows = 1: every row is then sorted ascending (rhg_sort_rows on
- * the index's own scratch), so col_idx is the same bytes for every tuning.
- * col_capacity is the number of int32 slots in col_idx; the call reads
- * row_ptr[n] back (one synchronisation) and returns RHG_ECAPACITY if it
- * exceeds col_capacity, or if canonical rows are asked for a graph with more
- * entries than the index's row-sort scratch was sized for (twice the
- * planner's upper estimate of 2m, plus 2^23; sort such a graph with
- * rhg_sort_rows instead).  The copy and emit kernels check every row they
+ * (device, int32) by repeating the count pass's search in the same order.
+ * row_ptr must be the output of rhg_count_edges on the same index.  Each
+ * undirected edge appears in both rows; there are no self-loops.
+ * canonical_rows = 0: rows are in search order, deterministic for a given
+ * tuning.  canonical_rows = 1: every row is then sorted ascending
+ * (rhg_sort_rows on the index's own scratch), so col_idx is the same bytes
+ * for every tuning.  col_capacity is the number of int32 slots in col_idx;
+ * the call reads row_ptr[n] back (one synchronisation) and returns
+ * RHG_ECAPACITY if it exceeds col_capacity, or if canonical rows are asked
+ * for a graph with more entries than the index's row-sort scratch was sized
+ * for (twice the planner's upper estimate of 2m, plus 2^23; sort such a
+ * graph with rhg_sort_rows instead).  The emit kernels check every row they
  * write against its count; a disagreement is RHG_EINTERNAL from the next
  * rhg_index_stats (rhg_generate checks it itself). */
 rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx,
@@ -352,16 +348,15 @@ rhg_status rhg_set_profiling(int on);
 
 /* Average duration in ms and number of recorded launches of each phase
  * since profiling was last turned on (synchronises on the events).  Phases:
- * 0 sample, 1 keys+sort, 2 index (band starts + directory), 3 gather (with
- * the neighbour store's slot plan and its scan), 4 plan (the small kernels
- * around the searches: heavy-work plan, its scans, heavy degrees, capacity
- * check), 5 count (the search kernel of the count pass), 6 scan (row
- * offsets), 7 copy (the kernel copying stored neighbours, heavy and light
- * rows), 8 emit (the search kernel of the emit pass: wavefronts whose store
- * overflowed, or every query without the store), 9 rows (the row sort of
- * canonical rows).  Each of 5, 7 and 8 brackets
- * exactly one kernel launch.  avg_ms, count: host arrays of at least 10
- * entries (cap). */
+ * 0 sample, 1 keys+sort, 2 index (band starts + directory), 3 gather,
+ * 4 plan (the small kernels around the searches: heavy-work plan, its
+ * scans, heavy degrees, capacity check), 5 count_heavy (the heavy queries'
+ * kernel of the count pass), 6 count (the light queries' kernel of the count
+ * pass), 7 scan (row offsets), 8 emit_heavy and 9 emit (the same two kernels
+ * of the emit pass), 10 rows (the row sort of canonical rows).  Each of 5,
+ * 6, 8 and 9 brackets exactly one kernel launch (5 and 8 none when there
+ * are no heavy queries).  avg_ms, count: host arrays of at least 11 entries
+ * (cap). */
 rhg_status rhg_phase_times(double *avg_ms /* host */, int64_t *count /* host */, int cap);
 
 /* Name of a phase index ("" if out of range). */

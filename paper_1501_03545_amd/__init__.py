@@ -36,13 +36,13 @@ class rhg_params(C.Structure):
 
 class rhg_tuning(C.Structure):
     _fields_ = [("band_width", C.c_double), ("inner_radius", C.c_double),
-                ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("no_stage", C.c_int32),
-                ("no_heavy_store", C.c_int32), ("fp64_only", C.c_int32), ("no_stream_stage", C.c_int32)]
+                ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("sweep_max", C.c_int32),
+                ("sweep_linear", C.c_int32), ("fp64_only", C.c_int32), ("no_stream_stage", C.c_int32)]
 
 
 class rhg_stats(C.Structure):
     _fields_ = [("fp32_undecided", C.c_int64), ("dd_fallbacks", C.c_int64), ("ties", C.c_int64),
-                ("stage_fallbacks", C.c_int64), ("stored", C.c_int64),
+                ("swept", C.c_int64), ("tests", C.c_int64),
                 ("register_streams", C.c_int64)]
 
 
@@ -140,8 +140,8 @@ def _tuning(t: Optional[dict]):
     tu.inner_radius = float(t.get("inner_radius", 0.0))
     tu.cell_target = int(t.get("cell_target", 0))
     tu.heavy_points = int(t.get("heavy_points", 0))
-    tu.no_stage = 1 if t.get("no_stage") else 0
-    tu.no_heavy_store = 1 if t.get("no_heavy_store") else 0
+    tu.sweep_max = int(t.get("sweep_max", 0))
+    tu.sweep_linear = 1 if t.get("sweep_linear") else 0
     tu.fp64_only = 1 if t.get("fp64_only") else 0
     tu.no_stream_stage = 1 if t.get("no_stream_stage") else 0
     return C.byref(tu)
@@ -309,10 +309,10 @@ def rhg_index_stats(idx: Index, stream=None) -> dict:
     st = rhg_stats()
     _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
     return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties,
-            "stage_fallbacks": st.stage_fallbacks, "stored": st.stored, "register_streams": st.register_streams}
+            "swept": st.swept, "tests": st.tests, "register_streams": st.register_streams}
 
 
-PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count", "scan", "copy", "emit", "rows"]
+PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count_heavy", "count", "scan", "emit_heavy", "emit", "rows"]
 
 
 def rhg_set_profiling(on: bool):

@@ -40,7 +40,7 @@ __global__ void zero_u64_kernel(unsigned long long *p, int count)
 // ---- optional phase timing: HIP events recorded on the caller's stream
 // around each kernel group, kept in a ring and averaged on request.
 static const char *kPhaseNames[RHG_PHASE_COUNT] = {"sample", "keys+sort", "index", "gather", "plan",
-                                                   "count", "scan", "copy", "emit", "rows"};
+                                                   "count_heavy", "count", "scan", "emit_heavy", "emit", "rows"};
 struct ProfRec {
     int phase;
     hipEvent_t a, b;
@@ -66,8 +66,8 @@ void phase_end(void *rec, hipStream_t s)
 }
 
 struct WsPlan {
-    size_t keys, v0, band_start, dir, sr, st, rec, heavy_end, hplan, hcand, hcnt, hitem, hscal, lkap, woff, wflag, wlist, stage,
-        stag, stats, raux, tmp, total, tmp_bytes;
+    size_t keys, v0, band_start, dir, sr, st, rec, rt, heavy_end, hplan, hcnt, hitem, hscal, stats, raux, tmp, total,
+        tmp_bytes;
     int64_t max_chunks, rows_lcap, rows_mapcap, rows_nnz_cap;
 };
 
@@ -88,6 +88,7 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.sr = take(N * 8);
     w.st = take(N * 8);
     w.rec = take(N * 16);
+    w.rt = take(N * 16);
     w.heavy_end = take(16);
     const int64_t items = L.heavy_cap * L.B;
     // Each heavy query's windows cover at most the n points once, so the
@@ -96,22 +97,9 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     const int64_t extra = std::min<int64_t>(RHG_HEAVY_EXTRA_CHUNKS, L.heavy_cap * (n / RHG_HEAVY_CHUNK + 1) + 1);
     w.max_chunks = items > 0 ? items + extra : 1;
     w.hplan = take((size_t)(items > 0 ? items : 1) * 8);
-    w.hcand = take((size_t)(items > 0 ? items : 1) * 8);
     w.hcnt = take((size_t)w.max_chunks * 8);
     w.hitem = take((size_t)w.max_chunks * 4);
     w.hscal = take(64);
-    const int64_t nw = (int64_t)((N + 63) / 64);  // wavefronts of 64 sorted positions
-    w.lkap = w.woff = w.wflag = w.wlist = w.stage = w.stag = 0;
-    size_t t5 = 0;
-    if (L.stage) {
-        w.lkap = take((size_t)(RHG_KAP_SUB * L.B + 1) * 4);
-        w.woff = take((size_t)(nw + 1) * 8);
-        w.wflag = take((size_t)nw * 4);
-        w.wlist = take((size_t)nw * 4);
-        w.stage = take((size_t)L.stage_cap * 4);
-        w.stag = take((size_t)L.stage_cap);
-        t5 = scan_tmp_bytes(nw);
-    }
     w.stats = take(ST_COUNT * 8);
     // canonical rows: room for the long rows and tiles of a graph of up to
     // twice the estimated entries (plus 2^23)
@@ -121,7 +109,7 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.raux = take(rows_aux_bytes(w.rows_lcap, w.rows_mapcap));
     size_t t1 = radix_sort_tmp_bytes(n), t2 = scan_tmp_bytes(n + 1);
     size_t t3 = scan_tmp_bytes(w.max_chunks), t4 = scan_tmp_bytes(items > 0 ? items : 1);
-    w.tmp_bytes = std::max(std::max(std::max(t1, t2), std::max(t3, t4)), t5);
+    w.tmp_bytes = std::max(std::max(t1, t2), std::max(t3, t4));
     w.tmp = take(w.tmp_bytes);
     w.total = off + 256;  // slack for aligning the base pointer
     return w;
@@ -264,20 +252,14 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->sr = (double *)(base + w.sr);
     idx->st = (double *)(base + w.st);
     idx->rec = (float4 *)(base + w.rec);
+    idx->rt = (double2 *)(base + w.rt);
     idx->heavy_end = (int32_t *)(base + w.heavy_end);
     idx->hplan = (int64_t *)(base + w.hplan);
-    idx->hcand = (int64_t *)(base + w.hcand);
     idx->hcnt = (int64_t *)(base + w.hcnt);
     idx->hitem = (int32_t *)(base + w.hitem);
     idx->hscal = (int64_t *)(base + w.hscal);
     idx->heavy_cap = idx->L.heavy_cap;
     idx->max_chunks = w.max_chunks;
-    idx->lkap = idx->L.stage ? (float *)(base + w.lkap) : nullptr;
-    idx->woff = idx->L.stage ? (int64_t *)(base + w.woff) : nullptr;
-    idx->wflag = idx->L.stage ? (int32_t *)(base + w.wflag) : nullptr;
-    idx->wlist = idx->L.stage ? (int32_t *)(base + w.wlist) : nullptr;
-    idx->stage = idx->L.stage ? (int32_t *)(base + w.stage) : nullptr;
-    idx->stag = idx->L.stage ? (uint8_t *)(base + w.stag) : nullptr;
     idx->stats = (unsigned long long *)(base + w.stats);
     idx->rows_aux = base + w.raux;
     idx->rows_lcap = w.rows_lcap;
@@ -466,8 +448,8 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
     out->fp32_undecided = (int64_t)h[ST_FP32_UNDECIDED];
     out->dd_fallbacks = (int64_t)h[ST_DD];
     out->ties = (int64_t)h[ST_TIES];
-    out->stage_fallbacks = (int64_t)h[ST_STAGE_FALLBACK];
-    out->stored = (int64_t)h[ST_STORED];
+    out->swept = (int64_t)h[ST_SWEPT];
+    out->tests = (int64_t)h[ST_TESTS];
     out->register_streams = (int64_t)h[ST_REG_STREAMS];
     if (h[ST_EMIT_MISMATCH]) return fail(RHG_EINTERNAL, "emit pass disagreed with the count pass");
     return RHG_OK;
@@ -629,7 +611,7 @@ rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t see
         rhg_index_free(idx);
         return st;
     }
-    // the emit and copy kernels' row-length check (one more 8-byte read)
+    // the emit pass's row-length check (one more 8-byte read)
     unsigned long long mismatch = 0;
     e = hipMemcpyAsync(&mismatch, idx->stats + ST_EMIT_MISMATCH, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

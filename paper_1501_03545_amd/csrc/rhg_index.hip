@@ -130,100 +130,33 @@ __global__ void __launch_bounds__(256) dir_empty_kernel(DirArgs A, const int32_t
     for (int64_t c = threadIdx.x; c < m; c += 256) dir[A.dir_base[j] + c] = s;
 }
 
-// Expected-degree table of the neighbour store: log of the expected degree
-// at RHG_KAP_SUB equally spaced radii per band, and at R.  One wavefront per
-// radius, two quadrature nodes per lane.
-__global__ void __launch_bounds__(256) kap_table_kernel(KeyArgs A, double alpha, double nd, float *__restrict__ lkap)
-{
-    const int i = (int)(blockIdx.x * 4 + (threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int last = RHG_KAP_SUB * A.B;
-    if (i > last) return;  // whole wavefronts leave together
-    double r = A.R;
-    if (i < last) {
-        const int j = i / RHG_KAP_SUB, sub = i % RHG_KAP_SUB;
-        r = A.E[j] + (A.E[j + 1] - A.E[j]) * sub / RHG_KAP_SUB;
-    }
-    double part = 0.0;
-    if (r > 0.0) part = degree_node(alpha, A.R, r, lane) + degree_node(alpha, A.R, r, lane + 64);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-    if (lane == 0) {
-        const double k = (nd - 1.0) * fmin(1.0, degree_inner(alpha, A.R, r) + part);
-        lkap[i] = (float)log(fmax(k, 1e-3));
-    }
-}
-
-// Slots of the neighbour store for a light query at radius r: its expected
-// degree, interpolated (log-linear) in the table, with the margin of
-// stage_slots.
-__device__ __forceinline__ int64_t slot_estimate(const KeyArgs &A, const float *lkap, double r)
-{
-    const int j = band_of(A, r);
-    const double u = (r - A.E[j]) / (A.E[j + 1] - A.E[j]) * RHG_KAP_SUB;
-    const int sub = min(RHG_KAP_SUB - 1, max(0, (int)u));
-    const double t = fmin(1.0, fmax(0.0, u - sub));
-    const int i = j * RHG_KAP_SUB + sub;
-    const double lk = (double)lkap[i] + t * ((double)lkap[i + 1] - (double)lkap[i]);
-    return stage_slots(exp(lk));
-}
-
-// The neighbour store's plan, made while the points are gathered: slots per
-// wavefront of 64 sorted positions (light queries only: positions from the
-// first light one, the start of band heavy_band capped at heavy_cap).
-struct StorePlanArgs {
-    const float *lkap;
-    const int32_t *band_start;
-    int heavy_band;
-    int64_t heavy_cap;
-    int64_t *woff;  // NULL: no store
-};
-
 // Sorted per-point records: r, theta (binary64) and the FP32 screen record
 // (e^r / sqrt(2 cosh R), e^-r / sqrt(2 cosh R), sinh r sqrt(2 / cosh R),
-// original id as raw bits).  With a store, woff[w + 1] = the slots of
-// wavefront w (woff[0] = 0; scanned afterwards into the wavefronts' first
-// slots).  Whole wavefronts walk the positions together.
+// original id as raw bits).
 __global__ void __launch_bounds__(256) gather_kernel(int64_t n, const double *__restrict__ r,
                                                      const double *__restrict__ theta,
                                                      const double2 *__restrict__ rt,
                                                      const uint32_t *__restrict__ perm, double inv, double sc,
                                                      double *__restrict__ sr, double *__restrict__ st,
-                                                     float4 *__restrict__ rec, KeyArgs A, StorePlanArgs S)
+                                                     float4 *__restrict__ rec)
 {
-    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t hend = 0;
-    if (S.woff) {
-        hend = S.heavy_band > 0 ? (int64_t)S.band_start[S.heavy_band] : 0;
-        if (hend > S.heavy_cap) hend = S.heavy_cap;
-        if (blockIdx.x == 0 && threadIdx.x == 0) S.woff[0] = 0;
-    }
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
-        const int64_t p = base + lane;
-        long long slot = 0;
-        if (p < n) {
-            uint32_t id = perm[p];
-            if (id >= (uint64_t)n) id = 0;  // unreachable for a valid permutation; keeps reads in bounds
-            double ri, ti;
-            if (rt) {
-                const double2 x = rt[id];
-                ri = x.x;
-                ti = x.y;
-            } else {
-                ri = r[id];
-                ti = theta[id];
-            }
-            sr[p] = ri;
-            st[p] = ti;
-            rec[p] = make_float4((float)(exp(ri) * inv), (float)(exp(-ri) * inv), (float)(sinh(ri) * sc),
-                                 __int_as_float((int)id));
-            if (S.woff && p >= hend) slot = (long long)slot_estimate(A, S.lkap, ri);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        uint32_t id = perm[p];
+        if (id >= (uint64_t)n) id = 0;  // unreachable for a valid permutation; keeps reads in bounds
+        double ri, ti;
+        if (rt) {
+            const double2 x = rt[id];
+            ri = x.x;
+            ti = x.y;
+        } else {
+            ri = r[id];
+            ti = theta[id];
         }
-        if (S.woff) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) slot += __shfl_xor(slot, o, 64);
-            if (lane == 0) S.woff[(base >> 6) + 1] = slot;
-        }
+        sr[p] = ri;
+        st[p] = ti;
+        rec[p] = make_float4((float)(exp(ri) * inv), (float)(exp(-ri) * inv), (float)(sinh(ri) * sc),
+                             __int_as_float((int)id));
     }
 }
 
@@ -246,9 +179,7 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
     ka.band_bits = L.band_bits;
     ka.R = idx->p.R;
     hipError_t e;
-    // The neighbour store is not written before the count pass: when it can
-    // hold 16 bytes per point it carries the interleaved points meanwhile.
-    double2 *rt = (idx->stage && idx->L.stage_cap >= 4 * n) ? (double2 *)idx->stage : nullptr;
+    double2 *rt = idx->rt;
     if (n > 0) {
         PhaseScope ps(RHG_PHASE_SORT, s);
         hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(256), 0, s, ka, n, r, theta, idx->keys, v0, rt,
@@ -276,21 +207,9 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
     if (n > 0) {
         PhaseScope ps(RHG_PHASE_GATHER, s);
         const double inv = 1.0 / sqrt(2.0 * idx->p.cosh_R), sc = sqrt(2.0 / idx->p.cosh_R);
-        StorePlanArgs sp;
-        sp.lkap = idx->lkap;
-        sp.band_start = idx->band_start;
-        sp.heavy_band = L.heavy_band;
-        sp.heavy_cap = idx->heavy_cap;
-        sp.woff = L.stage ? idx->woff : nullptr;
-        if (sp.woff) {
-            hipLaunchKernelGGL(kap_table_kernel, dim3((unsigned)((RHG_KAP_SUB * L.B + 1 + 3) / 4)), dim3(256), 0, s,
-                               ka, idx->p.alpha, (double)n, idx->lkap);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
         hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, r, theta, (const double2 *)rt, v0,
-                           inv, sc, idx->sr, idx->st, idx->rec, ka, sp);
+                           inv, sc, idx->sr, idx->st, idx->rec);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (sp.woff && (e = inclusive_scan_i64(idx->woff + 1, (n + 63) / 64, idx->tmp, s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

@@ -13,7 +13,7 @@
 #define RHG_HEAVY_CHUNK 8192      // candidates per heavy chunk (at least)
 #define RHG_HEAVY_BLOCKS 2048     // workgroups striding over the heavy chunks
 #define RHG_HEAVY_EXTRA_CHUNKS (1 << 20)
-#define RHG_KAP_SUB 4             // expected-degree table points per band
+#define RHG_KAP_SUB 4             // sub-intervals per band of the entry estimate
 #define RHG_ROWS_TILE 8192        // LDS tile (entries) of the row sort
 
 namespace rhg {
@@ -43,12 +43,11 @@ struct Layout {
     int64_t dir_total;                // entries of the directory (all bands)
     int heavy_band;                   // bands [0, heavy_band) hold the heavy queries
     int64_t heavy_cap;                // at most this many heavy queries
-    int stage;                        // count pass stores tested neighbours
-    int64_t stage_cap;                // int32 slots of the neighbour store
     double entries_est;               // upper estimate of the graph's entries (2m)
-    int heavy_store;                  // the store also takes the heavy queries' neighbours
     int fp64_only;                    // no FP32 screen
     int no_stream_stage;              // per-query streams never staged in LDS
+    int sweep_max;                    // unions of at most this many candidates are swept
+    int sweep_linear;                 // swept chunks filtered candidate by candidate
 };
 
 // Expected degree of a point at radius r (threshold model): the other n - 1
@@ -56,7 +55,7 @@ struct Layout {
 // theta_max(r, r') / pi, cos theta_max = (cosh r cosh r' - cosh R) /
 // (sinh r sinh r'), r' drawn from the radial density of Eq. (1).  Composite
 // 8-point Gauss-Legendre quadrature over 16 panels of [max(0, R - r), R].
-// Used only to size the neighbour store.
+// Used only to size the canonical-row workspace.
 #define RHG_KAP_NODES 128  // 16 panels x 8 Gauss-Legendre nodes
 
 // Contribution of quadrature node `node` (0 .. RHG_KAP_NODES-1) to the
@@ -90,25 +89,12 @@ RHG_HD double expected_degree(double n, double alpha, double R, double r)
     return (n - 1.0) * fmin(1.0, tot);
 }
 
-// Neighbour-store slots a light query adds to its wavefront's region when
-// its expected degree is k: the mean with a relative and a Poisson-scale
-// margin.  The 64 queries of a wavefront are neighbours in the index and
-// share most of their neighbourhoods, so their degrees rise and fall
-// together and pooling their slots does not shrink the relative spread: the
-// margin is sized per query (over 3 standard deviations).  A region that
-// still overflows only sends its wavefront back to the search in the emit
-// pass.
-RHG_HD int64_t stage_slots(double k)
-{
-    return (int64_t)ceil(1.03 * k + 3.0 * sqrt(k) + 4.0);
-}
-
 void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L);
 
 // Timed phases (rhg_phase_times).
 enum { RHG_PHASE_SAMPLE = 0, RHG_PHASE_SORT = 1, RHG_PHASE_INDEX = 2, RHG_PHASE_GATHER = 3,
-       RHG_PHASE_PLAN = 4, RHG_PHASE_COUNT_PASS = 5, RHG_PHASE_SCAN = 6, RHG_PHASE_COPY = 7,
-       RHG_PHASE_EMIT_PASS = 8, RHG_PHASE_ROWS = 9, RHG_PHASE_COUNT = 10 };
+       RHG_PHASE_PLAN = 4, RHG_PHASE_COUNT_HEAVY = 5, RHG_PHASE_COUNT_PASS = 6, RHG_PHASE_SCAN = 7,
+       RHG_PHASE_EMIT_HEAVY = 8, RHG_PHASE_EMIT_PASS = 9, RHG_PHASE_ROWS = 10, RHG_PHASE_COUNT = 11 };
 
 // Brackets a phase with HIP events on stream s when profiling is on.
 void *phase_begin(int phase, hipStream_t s);
@@ -127,7 +113,7 @@ struct PhaseScope {
 
 // Device-side counters (one 64-bit word each).
 enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4,
-       ST_STAGE_FALLBACK = 5, ST_STORED = 6, ST_REG_STREAMS = 7, ST_COUNT = 8 };
+       ST_SWEPT = 5, ST_TESTS = 6, ST_REG_STREAMS = 7, ST_COUNT = 8 };
 
 }  // namespace rhg
 
@@ -148,15 +134,9 @@ struct rhg_index {
     int64_t *hcnt;         // max_chunks heavy chunks: counts, then their prefix
     int32_t *hitem;        // max_chunks heavy chunks: the item of each
     int64_t *hscal;        // heavy plan scalars
-    int64_t *hcand;        // heavy_cap * B items: candidates, then their prefix
     int64_t heavy_cap;
     int64_t max_chunks;
-    float *lkap;           // log expected degree at RHG_KAP_SUB points per band, and at R
-    int64_t *woff;         // per wavefront of 64 positions: prefix of its store slots
-    int32_t *wflag;        // per wavefront: 1 when a slot overflowed in the count pass
-    int32_t *wlist;        // the overflowed wavefronts, in the order they were found
-    int32_t *stage;        // the neighbour store (stage_cap slots)
-    uint8_t *stag;         // the lane of each stored neighbour (stage_cap)
+    double2 *rt;           // (r, theta) interleaved in sample order, for the gather
     unsigned long long *stats;  // ST_COUNT counters
     void *rows_aux;        // row sort: counters, long-row list, tile map
     int64_t rows_lcap;     // long rows the list holds

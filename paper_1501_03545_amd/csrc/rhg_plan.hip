@@ -211,36 +211,28 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     L->heavy_band = jh;
     const double cap = 1.25 * hp + 1024.0;
     L->heavy_cap = jh > 0 ? (int64_t)std::min(cap, n) : 0;
-    // Neighbour store: per light band sub-interval, the expected points (with
-    // a binomial margin) times the slots at its inner edge, where the
-    // expected degree is largest.
     // An upper estimate of the entries of the graph (2m): per band
     // sub-interval, its expected points times the expected degree at its
-    // inner edge, where the degree is largest.
-    L->stage = !(t && t->no_stage) && p.n >= 2;
-    L->stage_cap = 0;
-    double slots = 0.0, entries = 0.0, heavy = 0.0;
+    // inner edge, where the degree is largest.  It sizes the workspace of
+    // the canonical row sort.
+    double entries = 0.0;
     for (int j = 0; j < B; ++j) {
         for (int sub = 0; sub < RHG_KAP_SUB; ++sub) {
             const double ra = L->E[j] + (L->E[j + 1] - L->E[j]) * sub / RHG_KAP_SUB;
             const double rb = L->E[j] + (L->E[j + 1] - L->E[j]) * (sub + 1) / RHG_KAP_SUB;
             const double pts = n * std::max(0.0, (cosh(a * rb) - cosh(a * ra)) / denom);
             if (pts <= 0.0) continue;
-            const double k = expected_degree(n, a, R, ra);
-            entries += pts * k;
-            if (j < jh) heavy += pts * k;
-            if (L->stage && j >= jh) slots += (pts + 4.0 * sqrt(pts) + 64.0) * (double)stage_slots(k);
+            entries += pts * expected_degree(n, a, R, ra);
         }
     }
     L->entries_est = p.n >= 2 ? entries : 0.0;
-    // The heavy queries' tested neighbours go to the top of the store, one
-    // slot per candidate: their windows hold about 1.8 candidates per
-    // neighbour at band width 2, so twice the estimate (the emit pass tests
-    // them again when they do not fit).
-    L->heavy_store = L->stage && !(t && t->no_heavy_store);
     L->fp64_only = (t && t->fp64_only) ? 1 : 0;
     L->no_stream_stage = (t && t->no_stream_stage) ? 1 : 0;
-    if (L->stage) L->stage_cap = (int64_t)std::min(1.02 * slots + (L->heavy_store ? 2.0 * heavy : 0.0) + 4096.0, 9.0e18);
+    // A wavefront's union window of up to sweep_max candidates is staged and
+    // swept even where its lanes' windows do not overlap: one contiguous
+    // read for all lanes instead of a directory lookup and a run per lane.
+    L->sweep_max = (t && t->sweep_max > 0) ? t->sweep_max : (t && t->sweep_max < 0) ? 0 : 512;
+    L->sweep_linear = (t && t->sweep_linear) ? 1 : 0;
 }
 
 }  // namespace rhg

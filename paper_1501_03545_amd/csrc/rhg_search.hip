@@ -28,13 +28,18 @@
 //   DD   double-double for the rest.
 //
 // Work split.  The first positions of the sorted index (the innermost
-// points, the hubs) are "heavy": each (heavy query, band) pair is a work item
-// for a whole workgroup (one block each, so the block dispatcher balances
-// them).  Every other query is
-// "light": a wavefront takes 64 consecutive queries (same band, adjacent
-// angles); per band it either shares one window -- the union of its lanes'
-// windows -- when those windows overlap, broadcasting each candidate to all
-// lanes, or gives each lane its own window when they are narrow.
+// points, the hubs) are "heavy": each (heavy query, band) pair is split into
+// chunks of candidates, each a work item for a whole workgroup of their own
+// kernel.  Every other query is "light": a wavefront takes 64 consecutive
+// sorted positions (same band, adjacent angles) and, per band, the union of
+// its lanes' windows.  A union that is short, or whose lanes' windows
+// overlap, is swept: the unions of all such bands are read in one stream of
+// contiguous runs, staged in LDS a chunk at a time, and every lane tests the
+// candidates of its own window in the chunk (found by binary search on the
+// angle key).  A long union of disjoint narrow windows is instead split into
+// the lanes' own windows, worked through as one stream of 64 candidates per
+// step.  The emit pass repeats the count pass's search in the same order and
+// writes each row in place.
 #include <string.h>
 
 #include "rhg_internal.h"
@@ -59,7 +64,8 @@ struct SearchArgs {
     int use_p32;                      // FP32 screen valid (R small enough)
     int stream_stage;                 // per-query streams of <= 64 steps staged in LDS
     int band_bits;                    // top bits of a sort key holding the band
-    const uint32_t *keys;             // sorted keys: band, then the top angle bits
+    int sweep_max;                    // unions of at most this many candidates are swept
+    int sweep_linear;                 // lanes filter every candidate of a swept chunk
     const uint32_t *ids;              // sorted ids (4 bytes where only the id is needed)
     const int32_t *band_start;
     const int32_t *dir;
@@ -69,24 +75,13 @@ struct SearchArgs {
     int64_t *hplan;                   // per heavy item: candidates, then chunks, then their prefix
     int64_t *hcnt;                    // per heavy chunk: count, then its prefix
     int32_t *hitem;                   // per heavy chunk: its item
-    int64_t *hscal;                   // [0] candidate total, [1] chunk size, [2] heavy rows stored, [3] their first slot,
-                                      // [4] overflowed wavefronts
-    int64_t *hcand;                   // per heavy item: candidates, then their prefix
+    int64_t *hscal;                   // [0] candidate total, [1] chunk size
     unsigned long long *stats;
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
-    int32_t *overflow;                // emit pass: set to 1 when 2m > col_cap
-    // neighbour store (count pass writes, emit pass copies)
-    int64_t *woff;                    // per wavefront: first slot (prefix), then [nw] = total
-    int32_t *wflag;                   // per wavefront: 1 = slots overflowed, search again
-    int32_t *wlist;                   // the overflowed wavefronts (count in hscal[4])
-    int32_t *store;                   // the store: accepted neighbour ids
-    uint8_t *stag;                    // and the lane (query) of each
-    int64_t store_cap;
 };
 
-// Passes of the search kernel: count, emit by searching again, count while
-// storing the tested neighbours, emit by copying the stored neighbours.
-enum { M_COUNT = 0, M_EMIT = 1, M_STAGE = 2, M_COPY = 3 };
+// Passes of the search kernels: count, emit.
+enum { M_COUNT = 0, M_EMIT = 1 };
 
 constexpr float P32_ACC = 1.0f - 0x1p-18f;
 constexpr float P32_REJ = 1.0f + 0x1p-18f;
@@ -330,7 +325,6 @@ __global__ void __launch_bounds__(256) heavy_plan_len(SearchArgs A)
             len = (it.b0 - it.a0) + (it.b1 - it.a1);
         }
         A.hplan[i] = len;
-        A.hcand[i] = len;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) len += __shfl_xor(len, o, 64);
@@ -358,14 +352,14 @@ __global__ void __launch_bounds__(256) heavy_plan_chunks(SearchArgs A)
     }
 }
 
-// One chunk of a heavy item.  With the neighbour store and room for it
-// (hscal[2]), the count pass also writes the chunk's accepted neighbours, in
-// order, to the store's top end at the chunk's candidate offset, and the
-// emit pass copies them (heavy_copy_chunk) instead of testing again.
+// One chunk of a heavy item: a workgroup tests its candidates 256 at a
+// time.  The count pass records the chunk's count; in the emit pass the
+// prefix of the counts places the chunk's neighbours inside the query's row
+// (the row order is (band, chunk, candidate)).
 template <int MODE>
 __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
 {
-    constexpr bool EMIT = MODE == M_EMIT || MODE == M_COPY;
+    constexpr bool EMIT = MODE == M_EMIT;
     // per-wave acceptance counts, double-buffered so that one barrier per
     // step suffices: a buffer is rewritten two steps later, after every wave
     // has passed the next step's barrier
@@ -376,9 +370,6 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
     const int64_t q = item / A.B;
     const int j = (int)(item % A.B);
     const int64_t ch = uni64(A.hscal[1]);
-    const bool hstore = MODE == M_STAGE && uni64(A.hscal[2]) != 0;
-    // first store slot of this chunk
-    const int64_t hbase = hstore ? uni64(A.hscal[3]) + (item ? uni64(A.hcand[item - 1]) : 0) + (c - first) * ch : 0;
     const ItemRuns it = item_runs(A, q, j);
     const int64_t a0 = uni64(it.a0), b0 = uni64(it.b0), a1 = uni64(it.a1), b1 = uni64(it.b1);
     const int inside = __builtin_amdgcn_readfirstlane(it.inside);
@@ -441,10 +432,6 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
             const int64_t o = out + total + before + __popcll(bal & lt);
             if (o < row_end) col[o] = cid;
         }
-        if (MODE == M_STAGE && hstore && acc) {
-            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-            A.store[hbase + total + before + __popcll(bal & lt)] = cid;
-        }
         total += blk;
     }
     // the next chunk starts again at buffer 0: every wave has read this one's
@@ -454,27 +441,6 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
     // the emit pass finds exactly what the count pass counted in this chunk
     if (EMIT && threadIdx.x == 0 && total != A.hcnt[c] - (c ? A.hcnt[c - 1] : 0))
         atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
-}
-
-// Emit pass, stored heavy rows: wavefront-wide copy of chunk c's neighbours
-// from the store to its place in the row (the same as heavy_chunk<M_COPY>
-// with the store, one wavefront instead of a workgroup).
-__device__ void heavy_copy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t item = uni64(A.hitem[c]);
-    const int64_t first = item ? uni64(A.hplan[item - 1]) : 0;
-    const int64_t q = item / A.B;
-    const int64_t ch = uni64(A.hscal[1]);
-    const int64_t hbase = uni64(A.hscal[3]) + (item ? uni64(A.hcand[item - 1]) : 0) + (c - first) * ch;
-    const int64_t qfirst = q ? uni64(A.hplan[q * A.B - 1]) : 0;
-    const int64_t base_c = c ? uni64(A.hcnt[c - 1]) : 0;
-    const int64_t base_q = qfirst ? uni64(A.hcnt[qfirst - 1]) : 0;
-    const int64_t cnt = uni64(A.hcnt[c]) - base_c;
-    const int32_t id = __builtin_amdgcn_readfirstlane(__float_as_int(A.rec[q].w));
-    const int64_t out = uni64(row_ptr[id]) + (base_c - base_q), row_end = uni64(row_ptr[id + 1]);
-    for (int64_t i = lane; i < cnt; i += 64)
-        if (out + i < row_end) col[out + i] = A.store[hbase + i];
 }
 
 // ------------------------------------------------------------ light path
@@ -502,6 +468,17 @@ __device__ __forceinline__ int wave_excl_sum(int v, int lane, int *total)
     *total = __shfl(x, 63, 64);
     return x - v;
 }
+__device__ __forceinline__ int64_t wave_excl_sum64(int64_t v, int lane, int64_t *total)
+{
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
 
 // Upper bound of band j's window for a query with normalised record
 // (e', m', s'): dropping the non-negative cosh(r_q - E[j]) / cosh R term
@@ -520,37 +497,6 @@ __device__ __forceinline__ double window_fast(const SearchArgs &A, float rsq, fl
     return (double)(2.0f * sx * fmaf(X, 0.2f, 1.0f)) * (1.0 + 0x1p-12) + 0x1p-40;
 }
 
-// Lane l's value, as a wave-uniform scalar.
-__device__ __forceinline__ int64_t uni_lane64(int64_t v, int l)
-{
-    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
-    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-__device__ __forceinline__ double lane_double(double v, int l)
-{
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-__device__ __forceinline__ float lane_float(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-
-__device__ __forceinline__ int64_t wave_excl_sum64(int64_t v, int lane, int64_t *total)
-{
-    int64_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    *total = __shfl(x, 63, 64);
-    return x - v;
-}
-
-
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -558,40 +504,54 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// A wavefront's map of its per-query candidate stream (one band), and the
-// stage its candidates are loaded into, STREAM_CHUNK steps at a time.
+// The angle part of a sort key: the index orders each band's positions by
+// it (points with equal keys stay in id order), so a binary search on it
+// finds where an angle's run of positions starts.
+__device__ __forceinline__ uint32_t akey(const SearchArgs &A, double t)
+{
+    return angle_key_s(t) >> A.band_bits;
+}
+
+// A wavefront's LDS.  The sweep stages a chunk of candidates; a per-query
+// stream keeps its map (one word per step with a bit at each owner's first
+// entry, and the owners' runs in lane order) and stages STREAM_CHUNK steps.
+constexpr int SWEEP_C = 256;
 constexpr int STREAM_STEPS = 64;
 constexpr int STREAM_CHUNK = 4;
-struct StreamMap {
-    unsigned long long start[STREAM_STEPS];  // bit t % 64 of word t / 64: an owner's first entry is t
+struct SweepStage {
+    double t[SWEEP_C];
+    float4 rec[SWEEP_C];
+};
+struct StreamStage {
+    float4 rec[STREAM_CHUNK][64];
+    int32_t tlo[STREAM_CHUNK][64], thi[STREAM_CHUNK][64];
+    int2 own[STREAM_CHUNK][64];  // (owner lane, candidate position)
+};
+struct WaveLds {
+    unsigned long long start[STREAM_STEPS];
     int4 run[64];  // owners in lane order: (first entry, first run's length | lane << 16, run starts)
-    float4 rec[STREAM_CHUNK][64];  // the step's candidate records, one per lane
-    int32_t tlo[STREAM_CHUNK][64], thi[STREAM_CHUNK][64];  // their angles (binary64 halves)
-    int2 own[STREAM_CHUNK][64];    // (owner lane, candidate position)
+    union {
+        SweepStage sw;
+        StreamStage ss;
+    } u;
 };
 static_assert(STREAM_STEPS == 64, "one word per lane is cleared");
 
 // Light queries: a wavefront of 64 consecutive sorted positions.  Lane j
 // first builds band j's entry of the wave's band table: the union of the
 // lanes' windows (the window of the innermost lane, stretched over the
-// lanes' angle range) as at most two position runs.  Where the lanes'
-// windows overlap (the window is at least as wide as the lanes' angle
-// spread) the band is "shared": every lane tests every candidate of the
-// union.  Otherwise each lane finds its own window's runs and the wave
-// works through all lanes' runs as one stream, 64 candidates per step.
+// lanes' angle range) as at most two position runs, and whether the band is
+// swept (mode 1) or searched per query (mode 2).
 //
-// MODE M_COUNT counts; M_STAGE counts and writes the neighbours found by
-// tests into the lane's store slots (bands wholly inside the circle are only
-// counted: the emit pass copies them from the index); M_EMIT writes the
-// whole row into col_idx.  The row order is the same in all modes: the
-// inside bands in band order, then the tested neighbours in search order.
+// M_COUNT writes the degree, M_EMIT the row.  The row order is the same in
+// both: the inside bands in band order, then the swept bands in band order
+// (each in position order), then the per-query bands in band order.
 template <int MODE>
 __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, int32_t *col)
 {
     constexpr bool EMIT = MODE == M_EMIT;
-    constexpr bool STORE = MODE == M_STAGE;
-    __shared__ StreamMap smap[4];
-    StreamMap &SM = smap[threadIdx.x >> 6];
+    __shared__ WaveLds lds[4];
+    WaveLds &SM = lds[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t p = base + lane;
     // the query's loads do not wait for the heavy/light boundary
@@ -605,10 +565,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     }
     const int64_t hend = uni64(*A.heavy_end);
     const bool active = inb && p >= hend;
-    if (__ballot(active) == 0) {
-        if (STORE && lane == 0 && base < A.n) A.wflag[base >> 6] = 0;
-        return;
-    }
+    if (__ballot(active) == 0) return;
     if (!active) {
         rq = 0.0;
         tq = 0.0;
@@ -635,15 +592,11 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     // bands lying wholly inside this lane's circle: taken without tests.  The
     // test is exact and monotone in the band's outer edge, so the inside
     // bands are the first J of them.
-    uint64_t full = 0;
     int64_t cnt = 0;
     int J = 64;  // inactive lanes: neutral in the wave's minimum below
     if (active) {
         J = 0;
-        while (J < B && band_inside(A, rq, J)) {
-            if (A.band_start[J] < A.band_start[J + 1]) full |= 1ull << J;
-            ++J;
-        }
+        while (J < B && band_inside(A, rq, J)) ++J;
         if (EMIT) {
             for (int j = 0; j < J; ++j) {
                 const int64_t s = A.band_start[j], e = A.band_start[j + 1];
@@ -658,35 +611,12 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             cnt = (e - s) - ((p >= s && p < e) ? 1 : 0);
         }
     }
-    // STORE: the wave appends the neighbours its tests accept to its region
-    // [w0, w0 + wlim) of the store, in acceptance order, each with the lane
-    // of its query; one coalesced write per step.  The region's size is the
-    // wave's sum of the per-query slots, as the store plan scanned it.
-    int64_t w0 = 0, wlim = 0, fill = 0;
-    if (STORE) {
-        w0 = uni64(A.woff[base >> 6]);
-        const int64_t slot = uni64(A.woff[(base >> 6) + 1]) - w0;
-        wlim = (w0 + slot <= A.store_cap) ? slot : 0;
-    }
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    auto put = [&](int acc, int32_t cid, int tag) {
-        const uint64_t bal = __ballot(acc);
-        if (bal) {
-            if (acc) {
-                const int64_t pos = fill + __popcll(bal & lt_mask);
-                if (pos < wlim) {
-                    A.store[w0 + pos] = cid;
-                    A.stag[w0 + pos] = (uint8_t)tag;
-                }
-            }
-            fill += __popcll(bal);
-        }
-    };
+    int tests = 0;
 
     // band table: lane j describes band j
-    int mode = 0;  // 0 nothing, 1 shared window, 2 per-query windows
+    int mode = 0;  // 0 nothing, 1 swept, 2 per-query windows
     int32_t a0 = 0, b0 = 0, a1 = 0, b1 = 0;
-    bool fpoly = true;
     if (lane < B) {
         const int j = lane;
         const int64_t s = A.band_start[j], e = A.band_start[j + 1];
@@ -700,8 +630,8 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 const int nr = window_runs(A, j, tmin - W, tmax + W, s, e, ra, rb);
                 a0 = (int32_t)ra[0]; b0 = (int32_t)rb[0];
                 if (nr == 2) { a1 = (int32_t)ra[1]; b1 = (int32_t)rb[1]; }
-                mode = (2.0 * W >= span) ? 1 : 2;
-                fpoly = !(W + span + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+                const int U = (b0 - a0) + (b1 - a1);
+                mode = (2.0 * W >= span || U <= A.sweep_max) ? 1 : 2;
             }
         }
     }
@@ -719,52 +649,125 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         if (lane < mj) mode = 0;
     }
     if ((b0 - a0) + (b1 - a1) == 0) mode = 0;
+    const float rsq = active && fq.z > 0.0f ? rsqrtf(fq.z) : 0.0f;
 
-    // shared bands: every lane tests every candidate of the band's union
-    // window.  The candidate is the same for the whole wave, so its angle and
-    // record are read through the scalar cache (the index is read-only while
-    // the search runs) and enter the test as scalar operands.
-    {
-        const double __attribute__((address_space(4))) *cst =
-            (const double __attribute__((address_space(4))) *)A.st;
-        const float __attribute__((address_space(4))) *crec =
-            (const float __attribute__((address_space(4))) *)A.rec;
-        for (uint64_t mk = __ballot(lane < B && mode == 1); mk; mk &= mk - 1) {
-            const int j = __ffsll((unsigned long long)mk) - 1;
-            const int ja0 = __builtin_amdgcn_readlane(a0, j), jb0 = __builtin_amdgcn_readlane(b0, j);
-            const int ja1 = __builtin_amdgcn_readlane(a1, j), jb1 = __builtin_amdgcn_readlane(b1, j);
-            const bool fpj = __builtin_amdgcn_readlane((int)fpoly, j) != 0;
-            const bool me = active && !((full >> j) & 1ull);
-            for (int run = 0; run < 2; ++run) {
-                const int cs = run ? ja1 : ja0, ce = run ? jb1 : jb0;
-                for (int c = cs; c < ce; ++c) {
-                    const double tc = cst[c];
-                    const int64_t c4 = 4 * (int64_t)c;
-                    const float cx = crec[c4], cy = crec[c4 + 1], cz = crec[c4 + 2];
-                    const int32_t cid = __float_as_int(crec[c4 + 3]);
-                    int acc = 0;
-                    if (me && c != p) acc = decide(A, p, tq, fq.x, fq.y, fq.z, c, tc, cx, cy, cz, fpj);
-                    if (EMIT && acc && cnt < lim) out[cnt] = cid;
-                    if (STORE) put(acc, cid, lane);
-                    cnt += acc;
+    // The pair (this lane's query, candidate at sorted position c): the
+    // exact decision, counted and (EMIT) written to the row.
+    auto take = [&](int64_t c, double tc, float4 fc, bool fp) {
+        ++tests;
+        if (decide(A, p, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp)) {
+            if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
+            ++cnt;
+        }
+    };
+
+    // ---- swept bands: the unions of every band with mode 1, in band order,
+    // as one stream of position runs, staged SWEEP_C candidates at a time
+    const uint64_t swm = __ballot(lane < B && mode == 1);
+    if (swm) {
+        SweepStage &S = SM.u.sw;
+        const int T = (lane < B && mode == 1) ? (b0 - a0) + (b1 - a1) : 0;
+        const int L0 = b0 - a0;
+        int tot;
+        const int pre = wave_excl_sum(T, lane, &tot);  // band `lane`'s entries are [pre, pre + T)
+        if (!EMIT && lane == 0) atomicAdd(&A.stats[ST_SWEPT], (unsigned long long)tot);
+        for (int c0 = 0; c0 < tot; c0 += SWEEP_C) {
+            wave_sync();  // the previous chunk's reads are done
+            double tl[SWEEP_C / 64];
+            float4 rl[SWEEP_C / 64];
+#pragma unroll
+            for (int k = 0; k < SWEEP_C / 64; ++k) {
+                const int t = c0 + 64 * k + lane;
+                int jb = 0;  // the last swept band starting at or before t
+                for (uint64_t m = swm; m; m &= m - 1) {
+                    const int j = __ffsll((unsigned long long)m) - 1;
+                    if (t >= __builtin_amdgcn_readlane(pre, j)) jb = j;
                 }
+                // the band's run data from lane jb, with every lane taking part
+                // (a lane outside the exec mask gives no value to a shuffle)
+                const int off = t - __shfl(pre, jb, 64);
+                const int l0 = __shfl(L0, jb, 64), ja0 = __shfl(a0, jb, 64), ja1 = __shfl(a1, jb, 64);
+                tl[k] = 0.0;
+                rl[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < tot) {
+                    const int64_t pos = off < l0 ? (int64_t)ja0 + off : (int64_t)ja1 + (off - l0);
+                    tl[k] = A.st[pos];
+                    rl[k] = A.rec[pos];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < SWEEP_C / 64; ++k) {
+                S.t[64 * k + lane] = tl[k];
+                S.rec[64 * k + lane] = rl[k];
+            }
+            wave_sync();
+            const int cend = min(tot, c0 + SWEEP_C);
+            for (uint64_t m = swm; m; m &= m - 1) {
+                const int j = __ffsll((unsigned long long)m) - 1;
+                const int pj = __builtin_amdgcn_readlane(pre, j), Tj = __builtin_amdgcn_readlane(T, j);
+                const int ls = max(pj, c0) - c0, hs = min(pj + Tj, cend) - c0;
+                if (ls >= hs || !(active && j >= J)) continue;
+                const int ja0 = __builtin_amdgcn_readlane(a0, j), ja1 = __builtin_amdgcn_readlane(a1, j);
+                const int jl0 = __builtin_amdgcn_readlane(L0, j);
+                const double w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
+                // every tested candidate lies within w of the query, so the
+                // two-term sine serves windows below 2^-5
+                const bool fp = !(w < 0x1p-5);
+                auto test = [&](int k) {
+                    const double tc = S.t[k];
+                    if (short_angle(tq, tc) > w) return;
+                    const float4 fc = S.rec[k];
+                    if (__float_as_int(fc.w) == id) return;
+                    const int off = c0 + k - pj;
+                    const int64_t pos = off < jl0 ? (int64_t)ja0 + off : (int64_t)ja1 + (off - jl0);
+                    take(pos, tc, fc, fp);
+                };
+                // a half-width of 3 or more: the linear filter (the two pieces
+                // below stay apart by more than a key step only for narrower
+                // windows, 2 pi - 2w > 0.28 rad)
+                if (!(w < 3.0) || hs - ls <= 16 || A.sweep_linear) {
+                    for (int k = ls; k < hs; ++k) test(k);
+                    continue;
+                }
+                // the window's position range in the chunk: the first
+                // position whose key reaches the window's start, then on
+                // while the key stays within its end (and, for a window
+                // across 0 / 2 pi, its other piece)
+                auto lower = [&](uint32_t kq) {
+                    int lo = ls, hi = hs;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (akey(A, S.t[mid]) < kq) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    return lo;
+                };
+                // (pieces in position order, so that the row order is that
+                // of the linear filter)
+                const double wlo = tq - w, whi = tq + w;
+                if (whi >= RHG_TWO_PI_D) {
+                    const uint32_t k2 = akey(A, whi - RHG_TWO_PI_D);
+                    for (int k = ls; k < hs && akey(A, S.t[k]) <= k2; ++k) test(k);
+                }
+                const uint32_t khi = akey(A, fmin(whi, RHG_TWO_PI_D));
+                for (int k = lower(akey(A, fmax(wlo, 0.0))); k < hs && akey(A, S.t[k]) <= khi; ++k) test(k);
+                if (wlo < 0.0)
+                    for (int k = lower(akey(A, wlo + RHG_TWO_PI_D)); k < hs; ++k) test(k);
             }
         }
     }
 
+    // ---- per-query bands (the lanes' angles spread wider than the window):
+    // each lane finds its own runs in band j; the runs of all lanes are then
+    // concatenated (lane order) and worked through 64 candidates per step,
+    // each candidate tested against the query of the lane that owns it.
     const uint64_t percell = __ballot(lane < B && mode == 2);
-    const float rsq = active && fq.z > 0.0f ? rsqrtf(fq.z) : 0.0f;
-    // per-query windows (the lanes' angles spread wider than the window):
-    // each lane finds its own runs in band j; the
-    // runs of all lanes are then concatenated (lane order) and worked
-    // through 64 candidates per step, each candidate tested against the
-    // query of the lane that owns it.
     for (uint64_t mk = percell; mk; mk &= mk - 1) {
         const int j = __ffsll((unsigned long long)mk) - 1;
         const int64_t s = A.band_start[j], e = A.band_start[j + 1];
         int ra0 = 0, rb0 = 0, ra1 = 0, rb1 = 0;  // positions are below 2^31
         double w = 0.0;
-        const bool mine = active && !((full >> j) & 1ull);
+        const bool mine = active && j >= J;
         if (mine) {
             w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
             int64_t ra[2] = {0, 0}, rb[2] = {0, 0};
@@ -829,8 +832,10 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             const bool lfp = __shfl(fpl, l, 64) != 0;
             int acc = 0;
             const int cid = __float_as_int(fc.w);
-            if (valid && c != lp && !(short_angle(lt, tc) > lw))
+            if (valid && c != lp && !(short_angle(lt, tc) > lw)) {
+                ++tests;
                 acc = decide(A, lp, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp);
+            }
             const uint64_t bal = __ballot(acc);
             // this lane's part of the step, as the owner of [pre, pre + len)
             const int64_t lo = pre - t0, hi = pre + len - t0;
@@ -847,13 +852,13 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 const int64_t llim = __shfl(lim, l, 64);
                 if (acc && at < llim) lout[at] = cid;
             }
-            if (STORE) put(acc, cid, l);
             cnt += got;
         };
         if (small) {
             // STREAM_CHUNK steps at a time: locate every entry and load its
             // candidate straight into the LDS stage (one memory round trip for
             // the chunk, no registers held), then test the steps from LDS
+            StreamStage &G = SM.u.ss;
             const int32_t *const st32 = (const int32_t *)A.st;
             for (int64_t tc0 = 0; tc0 < total; tc0 += 64 * STREAM_CHUNK) {
                 // every locate (LDS reads) before the first load: a read of
@@ -866,7 +871,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     if (t0 < total) {
                         int l;
                         locate(t0, l, cs[k]);
-                        SM.own[k][lane] = make_int2(l, cs[k]);
+                        G.own[k][lane] = make_int2(l, cs[k]);
                     }
                 }
 #pragma unroll
@@ -874,21 +879,22 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     const int64_t t0 = tc0 + 64 * k, c = cs[k];
                     if (t0 + lane < total) {
                         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(A.rec + c),
-                                                         (__attribute__((address_space(3))) void *)SM.rec[k], 16, 0, 0);
+                                                         (__attribute__((address_space(3))) void *)G.rec[k], 16, 0, 0);
                         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(st32 + 2 * c),
-                                                         (__attribute__((address_space(3))) void *)SM.tlo[k], 4, 0, 0);
+                                                         (__attribute__((address_space(3))) void *)G.tlo[k], 4, 0, 0);
                         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(st32 + 2 * c + 1),
-                                                         (__attribute__((address_space(3))) void *)SM.thi[k], 4, 0, 0);
+                                                         (__attribute__((address_space(3))) void *)G.thi[k], 4, 0, 0);
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < STREAM_CHUNK; ++k) {
                     const int64_t t0 = tc0 + 64 * k;
                     if (t0 < total) {
-                        const int2 lc = SM.own[k][lane];
-                        step(t0, lc.x, lc.y, __hiloint2double(SM.thi[k][lane], SM.tlo[k][lane]), SM.rec[k][lane]);
+                        const int2 lc = G.own[k][lane];
+                        step(t0, lc.x, lc.y, __hiloint2double(G.thi[k][lane], G.tlo[k][lane]), G.rec[k][lane]);
                     }
                 }
+                wave_sync();  // the stage is rewritten by the next chunk
             }
             continue;
         }
@@ -911,15 +917,10 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             step(t0, l, c, tc, fc);
         }
     }
-    if (STORE && lane == 0) {
-        const bool over = fill > wlim;
-        A.wflag[base >> 6] = over ? 1 : 0;
-        if (over) {
-            atomicAdd(&A.stats[ST_STAGE_FALLBACK], 1ull);
-            const unsigned long long k = atomicAdd((unsigned long long *)&A.hscal[4], 1ull);
-            A.wlist[k] = (int32_t)(base >> 6);
-        }
-        else if (fill) atomicAdd(&A.stats[ST_STORED], (unsigned long long)fill);
+    if (!EMIT) {
+        int tt;
+        wave_excl_sum(tests, lane, &tt);
+        if (lane == 0 && tt) atomicAdd(&A.stats[ST_TESTS], (unsigned long long)tt);
     }
     if (!active) return;
     if (EMIT) {
@@ -929,180 +930,30 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     }
 }
 
-// Emit pass for a wavefront whose stored neighbours fit its region: each
-// row is the inside bands (copied from the index, the query itself left
-// out) followed by its lane's stored neighbours in acceptance order.  The
-// store holds the wave's acceptances interleaved across lanes; chunks of
-// COPY_CHUNK entries are sorted by lane in LDS (stably, so each lane keeps
-// its order) and each lane's part of a chunk is written as one run.
-constexpr int COPY_K = 8;                  // entries per lane per chunk
-constexpr int COPY_CHUNK = 64 * COPY_K;
-
-struct CopyStage {
-    int32_t id[COPY_CHUNK];
-    uint8_t tag[COPY_CHUNK];
-    int32_t cnt[64];
-};
-
-__device__ void copy_wave(const SearchArgs &A, int64_t base, const int64_t *row_ptr, int32_t *col)
-{
-    __shared__ CopyStage stage[4];
-    const int lane = threadIdx.x & 63;
-    CopyStage &C = stage[threadIdx.x >> 6];
-    const int64_t p = base + lane;
-    const int64_t hend = uni64(*A.heavy_end);
-    const bool active = p < A.n && p >= hend;
-    if (__ballot(active) == 0) return;
-    int64_t dst = 0, deg = 0, fullc = 0;
-    uint64_t full = 0;
-    if (active) {
-        const double rq = A.sr[p];
-        const int32_t id = __float_as_int(A.rec[p].w);
-        dst = row_ptr[id];
-        deg = row_ptr[id + 1] - dst;
-        // the inside bands are the first J (the test is monotone in the edge)
-        int J = 0;
-        while (J < A.B && band_inside(A, rq, J)) {
-            if (A.band_start[J] < A.band_start[J + 1]) full |= 1ull << J;
-            ++J;
-        }
-        const int64_t s = A.band_start[0], e = A.band_start[J];
-        fullc = (e - s) - ((p >= s && p < e) ? 1 : 0);
-    }
-    // inside bands: the whole wave copies one row's bands at a time
-    for (uint64_t lm = __ballot(active && full != 0); lm; lm &= lm - 1) {
-        const int l = __ffsll((unsigned long long)lm) - 1;
-        const uint64_t lf = (uint64_t)uni_lane64((int64_t)full, l);
-        const int64_t lp = uni_lane64(p, l);
-        int64_t o = uni_lane64(dst, l);
-        for (uint64_t bm = lf; bm; bm &= bm - 1) {
-            const int j = __ffsll((unsigned long long)bm) - 1;
-            const int64_t s = A.band_start[j], e = A.band_start[j + 1];
-            const bool self = lp >= s && lp < e;
-            for (int64_t c0 = s; c0 < e; c0 += 64) {
-                const int64_t c = c0 + lane;
-                if (c < e && c != lp) col[o + (c - s) - ((self && c > lp) ? 1 : 0)] = (int32_t)A.ids[c];
-            }
-            o += (e - s) - (self ? 1 : 0);
-        }
-    }
-    // stored neighbours
-    long long T = active ? (long long)(deg - fullc) : 0ll;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) T += __shfl_xor(T, o, 64);
-    const int64_t total = uni64(T);
-    const int64_t w0 = uni64(A.woff[base >> 6]);
-    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int64_t at = dst + fullc;  // this lane's next output position
-    for (int64_t c0 = 0; c0 < total; c0 += COPY_CHUNK) {
-        C.cnt[lane] = 0;
-        wave_sync();
-        int32_t idk[COPY_K];
-        int tagk[COPY_K], posk[COPY_K];
-        // all loads of the chunk first: the wavefront fences below would
-        // otherwise hold each one back until the previous step is done
-#pragma unroll
-        for (int k = 0; k < COPY_K; ++k) {
-            const int64_t e = c0 + k * 64 + lane;
-            const bool valid = e < total;
-            idk[k] = valid ? A.store[w0 + e] : 0;
-            tagk[k] = valid ? (int)A.stag[w0 + e] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < COPY_K; ++k) {
-            const int64_t e = c0 + k * 64 + lane;
-            const bool valid = e < total;
-            const int tg = tagk[k];
-            // lanes holding entries of the same query lane in this step
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 6; ++b) {
-                const uint64_t bb = __ballot((tg >> b) & 1);
-                peers &= ((tg >> b) & 1) ? bb : ~bb;
-            }
-            const int before = valid ? C.cnt[tg] : 0;
-            posk[k] = valid ? before + __popcll(peers & lt_mask) : -1;
-            wave_sync();  // every read of cnt before its update
-            if (valid && lane == 63 - __clzll(peers)) C.cnt[tg] = before + __popcll(peers);
-            wave_sync();
-        }
-        const int mine = C.cnt[lane];
-        int chunk_total;
-        const int bin = wave_excl_sum(mine, lane, &chunk_total);
-#pragma unroll
-        for (int k = 0; k < COPY_K; ++k) {
-            const int start = __shfl(bin, tagk[k], 64);
-            if (posk[k] >= 0) {
-                C.id[start + posk[k]] = idk[k];
-                C.tag[start + posk[k]] = (uint8_t)tagk[k];
-            }
-        }
-        wave_sync();
-        for (int i0 = 0; i0 < chunk_total; i0 += 64) {
-            const int i = i0 + lane;
-            const int t = i < chunk_total ? (int)C.tag[i] : 0;
-            // all lanes take part in the shuffles; the range test comes after
-            const int64_t d = __shfl(at, t, 64) + (i - __shfl(bin, t, 64));
-            if (i < chunk_total) col[d] = C.id[i];
-        }
-        at += mine;
-        wave_sync();  // the stage is rewritten by the next chunk
-    }
-    // every row must come out exactly as long as the count pass counted it
-    if (active && at != dst + deg) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
-}
-
 // ------------------------------------------------------------ kernels
 
+// The heavy chunks: a pool of workgroups strides over them in (query, band,
+// chunk) order, hubs first.
 template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
-                                                     int32_t *__restrict__ col_idx)
+__global__ void __launch_bounds__(256) heavy_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
+                                                    int32_t *__restrict__ col_idx)
 {
-    constexpr bool EMIT = MODE == M_EMIT || MODE == M_COPY;
     // emit pass into a buffer too small for the graph: write nothing (the
     // prologue has raised the overflow flag)
-    if (EMIT && A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
-    // blocks [0, heavy_blocks): a pool striding over the heavy chunks in
-    // (query, band, chunk) order, hubs first; the rest: 256 light queries each
-    if ((int)blockIdx.x < A.heavy_blocks) {
-        const int64_t nch = A.heavy_cap > 0 ? uni64(A.hplan[A.heavy_cap * A.B - 1]) : 0;
-        if (MODE == M_COPY && uni64(A.hscal[2]) != 0) return;  // stored heavy rows: copy_kernel copies them
-        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<MODE>(A, c, row_ptr, col_idx);
-        return;
-    }
-    if (MODE == M_COPY) {
-        // copy_kernel handles the wavefronts whose stored neighbours fit; a
-        // pool of wavefronts searches the listed ones again
-        const int64_t nf = uni64(A.hscal[4]);
-        const int64_t stride = ((int64_t)gridDim.x - A.heavy_blocks) * 4;
-        for (int64_t k = ((int64_t)blockIdx.x - A.heavy_blocks) * 4 + (threadIdx.x >> 6); k < nf; k += stride)
-            light_wave<M_EMIT>(A, (int64_t)__builtin_amdgcn_readfirstlane(A.wlist[k]) << 6, row_ptr, col_idx);
-    } else {
-        const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
-        light_wave<MODE>(A, base, row_ptr, col_idx);
-    }
+    if (MODE == M_EMIT && A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
+    const int64_t nch = uni64(A.hplan[A.heavy_cap * A.B - 1]);
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) heavy_chunk<MODE>(A, c, row_ptr, col_idx);
 }
 
-// Emit pass with the neighbour store: workgroups [0, heavy_blocks) copy the
-// stored heavy rows (one wavefront per chunk), the rest copy the rows of
-// every wavefront of 64 light queries whose stored neighbours fit their
-// slots.  Kept apart from search_kernel so that its small register
-// footprint gives full occupancy.
-__global__ void __launch_bounds__(256) copy_kernel(SearchArgs A, const int64_t *__restrict__ row_ptr,
-                                                   int32_t *__restrict__ col_idx)
+// The light queries: 256 consecutive sorted positions per workgroup, one
+// wavefront each.
+template <int MODE>
+__global__ void __launch_bounds__(256) light_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
+                                                    int32_t *__restrict__ col_idx)
 {
-    if (A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
-    if ((int)blockIdx.x < A.heavy_blocks) {
-        if (uni64(A.hscal[2]) == 0) return;  // not stored: searched again by search_kernel<M_COPY>
-        const int64_t nch = uni64(A.hplan[A.heavy_cap * A.B - 1]);
-        const int64_t stride = (int64_t)A.heavy_blocks * 4;
-        for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nch; c += stride)
-            heavy_copy_chunk(A, c, row_ptr, col_idx);
-        return;
-    }
-    const int64_t base = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + (threadIdx.x & ~63);
-    if (base >= A.n || __builtin_amdgcn_readfirstlane(A.wflag[base >> 6])) return;
-    copy_wave(A, base, row_ptr, col_idx);
+    if (MODE == M_EMIT && A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
+    const int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+    light_wave<MODE>(A, base, row_ptr, col_idx);
 }
 
 // Before the count pass: heavy_end = the first light position (the end of
@@ -1115,7 +966,6 @@ __global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_
         *heavy_end = (int32_t)h;
         row_ptr[0] = 0;
         A.hscal[0] = 0;
-        A.hscal[4] = 0;
     }
 }
 
@@ -1129,26 +979,14 @@ __global__ void __launch_bounds__(256) heavy_chunk_items(SearchArgs A)
     for (int64_t c = b; c < e; ++c) A.hitem[c] = (int32_t)i;
 }
 
-// After both plans: the heavy chunks' neighbours are stored at the top of
-// the neighbour store, one slot per candidate, when that leaves the light
-// wavefronts' slots [0, woff[nw]) untouched.
-__global__ void heavy_store_check(SearchArgs A, int64_t nw, int allowed)
-{
-    if (threadIdx.x != 0) return;
-    const int64_t off = A.store_cap - A.hscal[0];
-    const bool ok = allowed && A.store != nullptr && off >= 0 && A.woff[nw] <= off;
-    A.hscal[2] = ok ? 1 : 0;
-    A.hscal[3] = ok ? off : 0;
-}
-
 // Before the emit pass: flag a col_idx buffer smaller than the graph.
 __global__ void emit_prologue(const int64_t *row_ptr, int64_t n, int64_t cap, int32_t *overflow)
 {
     if (threadIdx.x == 0 && overflow) *overflow = (cap >= 0 && row_ptr[n] > cap) ? 1 : 0;
 }
 
-// After the emit pass: bit 1 of the flag reports rows that the emit or copy
-// kernels found longer or shorter than the count pass had counted them.
+// After the emit pass: bit 1 of the flag reports rows that the emit pass
+// found longer or shorter than the count pass had counted them.
 __global__ void emit_epilogue(const unsigned long long *stats, int32_t *overflow)
 {
     if (threadIdx.x == 0 && stats[ST_EMIT_MISMATCH]) *overflow |= 2;
@@ -1192,7 +1030,6 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     }
     A.B = L.B;
     A.band_bits = L.band_bits;
-    A.keys = idx->keys;
     A.ids = idx->ids;
     A.n = idx->n;
     A.heavy_cap = idx->heavy_cap;
@@ -1205,6 +1042,8 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     // the range every entry point accepts.
     A.use_p32 = (!L.fp64_only && p.R < 80.0) ? 1 : 0;
     A.stream_stage = L.no_stream_stage ? 0 : 1;
+    A.sweep_max = L.sweep_max;
+    A.sweep_linear = L.sweep_linear;
     A.band_start = idx->band_start;
     A.dir = idx->dir;
     A.sr = idx->sr;
@@ -1215,22 +1054,12 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.hcnt = idx->hcnt;
     A.hitem = idx->hitem;
     A.hscal = idx->hscal;
-    A.hcand = idx->hcand;
     A.stats = idx->stats;
     A.col_cap = col_cap;
-    A.overflow = overflow;
-    A.woff = idx->woff;
-    A.wflag = idx->wflag;
-    A.wlist = idx->wlist;
-    A.store = idx->stage;
-    A.stag = idx->stag;
-    A.store_cap = L.stage_cap;
-    const bool store = L.stage != 0;
-    const int64_t nw = (idx->n + 63) / 64;
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
     hipError_t e;
-    PhaseScope plan_ps(RHG_PHASE_PLAN, s);  // ended before the search kernel
+    PhaseScope plan_ps(RHG_PHASE_PLAN, s);  // ended before the search kernels
     if (!emit) {
         hipLaunchKernelGGL(search_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1241,14 +1070,9 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
             hipLaunchKernelGGL(heavy_plan_chunks, dim3(g), dim3(256), 0, s, A);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = inclusive_scan_i64(idx->hplan, items, idx->tmp, s)) != hipSuccess) return e;
-            if ((e = inclusive_scan_i64(idx->hcand, items, idx->tmp, s)) != hipSuccess) return e;
             hipLaunchKernelGGL(heavy_chunk_items, dim3(g), dim3(256), 0, s, A);
             hipLaunchKernelGGL(zero_i64, dim3((unsigned)((idx->max_chunks + 255) / 256)), dim3(256), 0, s, idx->hcnt,
                                idx->max_chunks);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        if (items > 0) {
-            hipLaunchKernelGGL(heavy_store_check, dim3(1), dim3(64), 0, s, A, nw, L.heavy_store);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     } else {
@@ -1259,27 +1083,19 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         if (n <= 0) return hipSuccess;
     }
     plan_ps.end();
-    const int64_t blocks = A.heavy_blocks + (n + 255) / 256;
-    const dim3 g((unsigned)blocks), b(256);
-    if (emit && store) {
-        {
-            PhaseScope ps(RHG_PHASE_COPY, s);
-            hipLaunchKernelGGL(copy_kernel, g, b, 0, s, A, row_ptr, col_idx);
+    const dim3 lg((unsigned)((n + 255) / 256)), b(256);
+    {
+        PhaseScope ps(emit ? RHG_PHASE_EMIT_HEAVY : RHG_PHASE_COUNT_HEAVY, s);
+        if (items > 0) {
+            if (emit) hipLaunchKernelGGL(heavy_kernel<M_EMIT>, dim3(A.heavy_blocks), b, 0, s, A, row_ptr, col_idx);
+            else hipLaunchKernelGGL(heavy_kernel<M_COUNT>, dim3(A.heavy_blocks), b, 0, s, A, row_ptr, col_idx);
         }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
-        const int64_t pool = std::min<int64_t>(1024, (n + 255) / 256);  // workgroups for the overflowed wavefronts
-        hipLaunchKernelGGL(search_kernel<M_COPY>, dim3((unsigned)(A.heavy_blocks + pool)), b, 0, s, A, row_ptr,
-                           col_idx);
-    } else if (emit) {
-        PhaseScope ps(RHG_PHASE_EMIT_PASS, s);
-        hipLaunchKernelGGL(search_kernel<M_EMIT>, g, b, 0, s, A, row_ptr, col_idx);
-    } else {
-        PhaseScope ps(RHG_PHASE_COUNT_PASS, s);
-        if (store)
-            hipLaunchKernelGGL(search_kernel<M_STAGE>, g, b, 0, s, A, row_ptr, col_idx);
-        else
-            hipLaunchKernelGGL(search_kernel<M_COUNT>, g, b, 0, s, A, row_ptr, col_idx);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
+        if (emit) hipLaunchKernelGGL(light_kernel<M_EMIT>, lg, b, 0, s, A, row_ptr, col_idx);
+        else hipLaunchKernelGGL(light_kernel<M_COUNT>, lg, b, 0, s, A, row_ptr, col_idx);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (emit && overflow) {

@@ -87,54 +87,60 @@ def test_search_parity_independent_of_tuning():
         assert np.array_equal(canonical(rp, col), ocol)
 
 
-def test_stored_neighbours_give_the_rows_of_a_second_search():
-    """With the neighbour store the emit pass copies what the count pass
-    found; without it the emit pass searches again.  Both must give the same
-    rows, entry for entry, across tunings."""
+def test_sweep_and_per_query_paths_give_the_same_rows():
+    """A band of a wavefront is either swept (its union window staged in LDS,
+    each lane binary-searching its own window) or searched per query (each
+    lane's own window runs as one stream).  Forcing either path, and the
+    sweep's linear filter instead of the binary search, gives the same rows
+    entry for entry, across tunings, and the oracle's graph."""
     n, k, g = 20_000, 12.0, 2.3
     params, a, R = _params_for(n, k, g, 31)
     r, t, _ = O.sample(31, a, R, n)
     orp, ocol, _, _ = O.csr(r, t, R)
     for tun in [{}, {"band_width": 1.0, "heavy_points": 2048}, {"band_width": 3.0, "cell_target": 4}]:
         rp_s, col_s, st_s = run_search(P, params, r, t, tuning=dict(tun) or None)
-        rp_d, col_d, st_d = run_search(P, params, r, t, tuning=dict(tun, no_stage=1))
-        # the heavy queries' rows searched again instead of copied
-        rp_h, col_h, st_h = run_search(P, params, r, t, tuning=dict(tun, no_heavy_store=1))
+        # every union swept (huge sweep_max), none swept unless windows overlap
+        rp_w, col_w, st_w = run_search(P, params, r, t, tuning=dict(tun, sweep_max=1 << 30))
+        rp_q, col_q, st_q = run_search(P, params, r, t, tuning=dict(tun, sweep_max=-1))
+        # a mix: short unions swept, long ones per query
+        rp_m, col_m, st_m = run_search(P, params, r, t, tuning=dict(tun, sweep_max=24))
+        # swept chunks filtered candidate by candidate
+        rp_l, col_l, st_l = run_search(P, params, r, t, tuning=dict(tun, sweep_linear=1))
         # per-query candidate streams read through registers, never staged in LDS
-        rp_r, col_r, _ = run_search(P, params, r, t, tuning=dict(tun, no_stream_stage=1))
-        _say("store", tun, st_s)
-        assert st_d["stage_fallbacks"] == 0 and st_d["stored"] == 0
-        assert st_s["stored"] > 0
-        assert np.array_equal(rp_s, orp) and np.array_equal(rp_d, orp) and np.array_equal(rp_h, orp)
-        assert np.array_equal(rp_r, orp)
-        assert np.array_equal(col_s, col_d) and np.array_equal(col_s, col_h) and np.array_equal(col_s, col_r)
-        assert np.array_equal(canonical(rp_s, col_s), ocol)
+        rp_r, col_r, _ = run_search(P, params, r, t, tuning=dict(tun, sweep_max=-1, no_stream_stage=1))
+        _say("paths", tun, st_s, st_w, st_q, st_m)
+        assert st_w["swept"] >= st_s["swept"] > st_m["swept"] > st_q["swept"]
+        # every path tests exactly the candidates inside each query's window
+        assert st_l["tests"] == st_s["tests"] == st_w["tests"] == st_q["tests"] == st_m["tests"]
+        for rp_x in (rp_s, rp_w, rp_q, rp_l, rp_r, rp_m):
+            assert np.array_equal(rp_x, orp)
+        # the same tested pairs in the same order: the same bytes
+        assert np.array_equal(col_s, col_l)
+        assert np.array_equal(col_q, col_r)
+        for rp_x, col_x in ((rp_s, col_s), (rp_w, col_w), (rp_q, col_q), (rp_m, col_m)):
+            assert np.array_equal(canonical(rp_x, col_x), ocol)
 
 
-def test_store_overflow_falls_back_to_search():
-    """Points crowded into a narrow sector have far more neighbours than the
-    expected degree at their radius sizes the store for: the overflowing
-    wavefronts are searched again in the emit pass, with the same rows."""
+def test_crowded_sector_long_streams():
+    """Points crowded into a narrow sector give long per-query streams: the
+    longest (over 4096 entries) take the register path even by default; with
+    no_stream_stage every stream does.  Both match the oracle."""
     n, k, g = 8_000, 8.0, 2.6
     params, a, R = _params_for(n, k, g, 41)
     r, t, _ = O.sample(41, a, R, n)
     t = t.copy()
     t[: n // 2] = t[: n // 2] * 1e-3  # half the points within 0.0063 rad
     orp, ocol, _, nt = O.csr(r, t, R)
-    rp_s, col_s, st_s = run_search(P, params, r, t)
-    rp_d, col_d, _ = run_search(P, params, r, t, tuning={"no_stage": 1})
-    rp_r, col_r, st_r = run_search(P, params, r, t, tuning={"no_stream_stage": 1})
-    _say("crowded", st_s, "register path only:", st_r)
-    assert st_s["stage_fallbacks"] > 0
-    assert np.array_equal(rp_s, orp)
-    assert np.array_equal(col_s, col_d)
-    assert np.array_equal(canonical(rp_s, col_s), ocol)
-    # the crowded sector's longest streams (over 4096 entries) take the
-    # register path even by default; with no_stream_stage every stream does,
-    # with the same bytes
+    rp_s, col_s, st_s = run_search(P, params, r, t, tuning={"sweep_max": -1})
+    rp_r, col_r, st_r = run_search(P, params, r, t, tuning={"sweep_max": -1, "no_stream_stage": 1})
+    rp_d, col_d, st_d = run_search(P, params, r, t)
+    _say("crowded", st_s, "register path only:", st_r, "default:", st_d)
     assert st_s["register_streams"] > 0
     assert st_r["register_streams"] > st_s["register_streams"]
-    assert np.array_equal(rp_r, orp) and np.array_equal(col_r, col_s)
+    for rp_x, col_x in ((rp_s, col_s), (rp_r, col_r), (rp_d, col_d)):
+        assert np.array_equal(rp_x, orp)
+        assert np.array_equal(canonical(rp_x, col_x), ocol)
+    assert np.array_equal(col_r, col_s)
 
 
 def test_search_degenerate_inputs():
@@ -302,8 +308,8 @@ def test_c3_full_size_points_and_sampled_rows():
 
 
 def test_count_and_emit_twice_on_one_index():
-    """The store's slot plan is made when the index is built: counting and
-    emitting a second time on the same index gives the same bytes."""
+    """Counting and emitting a second time on the same index gives the same
+    bytes (the diagnostics are summed since the build)."""
     import torch
     n, k, g = 30_000, 16.0, 2.4
     params, a, R = _params_for(n, k, g, 77)
@@ -321,6 +327,6 @@ def test_count_and_emit_twice_on_one_index():
     idx.free()
     _say("twice:", out[0][2], out[1][2])
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
-    assert out[0][2]["stage_fallbacks"] == 0 and out[0][2]["stored"] > 0
+    assert out[0][2]["tests"] > 0 and out[1][2]["tests"] == 2 * out[0][2]["tests"]
     orp, ocol, _, _ = O.csr(r, t, R)
     assert np.array_equal(out[1][0], orp) and np.array_equal(canonical(out[1][0], out[1][1]), ocol)

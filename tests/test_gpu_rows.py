@@ -116,7 +116,7 @@ def test_canonical_rows_are_the_same_bytes_for_every_tuning():
     n, k, g_, seed = 200_000, 64.0, 2.1, 11
     outs = []
     for tun in (None, {"band_width": 1.0, "cell_target": 4, "heavy_points": 2048},
-                {"band_width": 3.0, "no_stage": 1}):
+                {"band_width": 3.0, "sweep_max": -1}):
         g = P.rhg_generate(n, k, g_, seed, tuning=tun, canonical_rows=True)
         outs.append((g.row_ptr.cpu().numpy(), g.col_idx.cpu().numpy()))
         raw = P.rhg_generate(n, k, g_, seed, tuning=tun)

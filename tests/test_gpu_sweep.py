@@ -16,7 +16,7 @@ from gpu_util import canonical, check_simple_symmetric, run_search
 pytestmark = pytest.mark.gpu
 
 TUNINGS = [None, {"band_width": 0.5}, {"band_width": 3.0}, {"cell_target": 8}, {"heavy_points": 256},
-           {"no_stream_stage": 1}, {"fp64_only": 1}, {"no_stage": 1}, {"no_heavy_store": 1},
+           {"no_stream_stage": 1, "sweep_max": -1}, {"fp64_only": 1}, {"sweep_max": 1 << 30}, {"sweep_linear": 1},
            {"band_width": 1.0, "cell_target": 2, "heavy_points": 1024}]
 
 

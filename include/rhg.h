@@ -78,7 +78,7 @@ typedef struct {
     int32_t sweep_max;     /* a wavefront's union window (all its queries'
                             * windows in one band) of at most this many
                             * candidates is read once and swept by every
-                            * lane; 0: automatic (512); negative: swept only
+                            * lane; 0: automatic (128); negative: swept only
                             * where the queries' windows overlap           */
     int32_t sweep_linear;  /* nonzero: lanes filter every candidate of a
                             * swept chunk instead of binary-searching their
@@ -90,18 +90,28 @@ typedef struct {
                             * streams are always read through registers one
                             * step ahead, never staged in LDS (the path the
                             * longest streams take); same bytes out         */
+    int32_t exact_inline;  /* nonzero: pairs the FP32 screen leaves undecided
+                            * are decided inside the search kernels instead
+                            * of being listed for a separate exact pass;
+                            * same bytes out                                */
+    int32_t defer_cap;     /* capacity of that list (0: automatic,
+                            * 65536 + n/1024); when the count pass finds
+                            * more, both passes rerun with in-place
+                            * decisions; same bytes out                     */
 } rhg_tuning;
 
-/* Device-side diagnostics of the count and emit passes over an index,
- * summed since the index was built (rhg_build_index clears them). */
+/* Device-side diagnostics of the count and emit passes over an index.  The
+ * first three and register_streams are summed since the index was built
+ * (rhg_build_index clears them); swept and tests are those of the most
+ * recent count pass (0 before one). */
 typedef struct {
     int64_t fp32_undecided;  /* pairs the FP32 screen passed to FP64          */
     int64_t dd_fallbacks;    /* pairs FP64 passed to double-double            */
     int64_t ties;            /* pairs double-double could not separate        */
-    int64_t swept;           /* candidates the count passes read into swept
-                              * chunks (light queries)                        */
-    int64_t tests;           /* pair tests of the count passes' light queries
-                              * (the candidates inside a query's window)      */
+    int64_t swept;           /* candidates the light queries' wavefronts read
+                              * into swept chunks                             */
+    int64_t tests;           /* pair tests of the light queries (the
+                              * candidates inside a query's window)           */
     int64_t register_streams; /* per-query candidate streams (one per light
                               * wavefront and band) read through registers:
                               * those longer than 4096 entries, or all of
@@ -350,13 +360,11 @@ rhg_status rhg_set_profiling(int on);
  * since profiling was last turned on (synchronises on the events).  Phases:
  * 0 sample, 1 keys+sort, 2 index (band starts + directory), 3 gather,
  * 4 plan (the small kernels around the searches: heavy-work plan, its
- * scans, heavy degrees, capacity check), 5 count_heavy (the heavy queries'
- * kernel of the count pass), 6 count (the light queries' kernel of the count
- * pass), 7 scan (row offsets), 8 emit_heavy and 9 emit (the same two kernels
- * of the emit pass), 10 rows (the row sort of canonical rows).  Each of 5,
- * 6, 8 and 9 brackets exactly one kernel launch (5 and 8 none when there
- * are no heavy queries).  avg_ms, count: host arrays of at least 11 entries
- * (cap). */
+ * scans, heavy degrees, capacity check), 5 count (the search kernel of the
+ * count pass), 6 scan (row offsets), 7 emit (the search kernel of the emit
+ * pass), 8 rows (the row sort of canonical rows).  Each of 5 and 7 brackets
+ * exactly one kernel launch.  avg_ms, count: host arrays of at least 9
+ * entries (cap). */
 rhg_status rhg_phase_times(double *avg_ms /* host */, int64_t *count /* host */, int cap);
 
 /* Name of a phase index ("" if out of range). */

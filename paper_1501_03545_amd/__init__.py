@@ -37,7 +37,8 @@ class rhg_params(C.Structure):
 class rhg_tuning(C.Structure):
     _fields_ = [("band_width", C.c_double), ("inner_radius", C.c_double),
                 ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("sweep_max", C.c_int32),
-                ("sweep_linear", C.c_int32), ("fp64_only", C.c_int32), ("no_stream_stage", C.c_int32)]
+                ("sweep_linear", C.c_int32), ("fp64_only", C.c_int32), ("no_stream_stage", C.c_int32),
+                ("exact_inline", C.c_int32), ("defer_cap", C.c_int32)]
 
 
 class rhg_stats(C.Structure):
@@ -144,6 +145,8 @@ def _tuning(t: Optional[dict]):
     tu.sweep_linear = 1 if t.get("sweep_linear") else 0
     tu.fp64_only = 1 if t.get("fp64_only") else 0
     tu.no_stream_stage = 1 if t.get("no_stream_stage") else 0
+    tu.exact_inline = 1 if t.get("exact_inline") else 0
+    tu.defer_cap = int(t.get("defer_cap", 0))
     return C.byref(tu)
 
 
@@ -312,7 +315,7 @@ def rhg_index_stats(idx: Index, stream=None) -> dict:
             "swept": st.swept, "tests": st.tests, "register_streams": st.register_streams}
 
 
-PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count_heavy", "count", "scan", "emit_heavy", "emit", "rows"]
+PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count", "scan", "emit", "rows"]
 
 
 def rhg_set_profiling(on: bool):

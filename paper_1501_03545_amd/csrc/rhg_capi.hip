@@ -40,7 +40,7 @@ __global__ void zero_u64_kernel(unsigned long long *p, int count)
 // ---- optional phase timing: HIP events recorded on the caller's stream
 // around each kernel group, kept in a ring and averaged on request.
 static const char *kPhaseNames[RHG_PHASE_COUNT] = {"sample", "keys+sort", "index", "gather", "plan",
-                                                   "count_heavy", "count", "scan", "emit_heavy", "emit", "rows"};
+                                                   "count", "scan", "emit", "rows"};
 struct ProfRec {
     int phase;
     hipEvent_t a, b;
@@ -66,8 +66,8 @@ void phase_end(void *rec, hipStream_t s)
 }
 
 struct WsPlan {
-    size_t keys, v0, band_start, dir, sr, st, rec, rt, heavy_end, hplan, hcnt, hitem, hscal, stats, raux, tmp, total,
-        tmp_bytes;
+    size_t keys, v0, band_start, dir, sr, st, rec, rt, heavy_end, hplan, hcnt, hitem, hscal, stats, wstat, dkeys, dchunk,
+        dcount, hset, raux, tmp, total, tmp_bytes;
     int64_t max_chunks, rows_lcap, rows_mapcap, rows_nnz_cap;
 };
 
@@ -101,6 +101,11 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.hitem = take((size_t)w.max_chunks * 4);
     w.hscal = take(64);
     w.stats = take(ST_COUNT * 8);
+    w.wstat = take((N + 63) / 64 * 16);
+    w.dkeys = take((size_t)L.defer_cap * 8);
+    w.dchunk = take((size_t)L.defer_cap * 4);
+    w.dcount = take(16);
+    w.hset = take((size_t)L.hset_slots * 8);
     // canonical rows: room for the long rows and tiles of a graph of up to
     // twice the estimated entries (plus 2^23)
     w.rows_nnz_cap = (int64_t)std::min(9.0e18, 2.0 * L.entries_est + 8388608.0);
@@ -261,6 +266,12 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->heavy_cap = idx->L.heavy_cap;
     idx->max_chunks = w.max_chunks;
     idx->stats = (unsigned long long *)(base + w.stats);
+    idx->wstat = base + w.wstat;
+    idx->dkeys = (uint64_t *)(base + w.dkeys);
+    idx->dchunk = (int32_t *)(base + w.dchunk);
+    idx->dcount = (unsigned long long *)(base + w.dcount);
+    idx->hset = (uint64_t *)(base + w.hset);
+    idx->hset_slots = idx->L.hset_slots;
     idx->rows_aux = base + w.raux;
     idx->rows_lcap = w.rows_lcap;
     idx->rows_mapcap = w.rows_mapcap;
@@ -303,6 +314,7 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream)
     if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_count_edges: NULL argument");
     hipStream_t s = (hipStream_t)stream;
     RHG_HIP(launch_search(idx, row_ptr, nullptr, 0, s));
+    idx->counted = 1;
     if (idx->n > 0) {
         PhaseScope ps(RHG_PHASE_SCAN, s);
         RHG_HIP(inclusive_scan_i64(row_ptr + 1, idx->n, idx->tmp, s));
@@ -448,9 +460,19 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
     out->fp32_undecided = (int64_t)h[ST_FP32_UNDECIDED];
     out->dd_fallbacks = (int64_t)h[ST_DD];
     out->ties = (int64_t)h[ST_TIES];
-    out->swept = (int64_t)h[ST_SWEPT];
-    out->tests = (int64_t)h[ST_TESTS];
     out->register_streams = (int64_t)h[ST_REG_STREAMS];
+    // the last count pass's per-wavefront tallies (zero before any count pass)
+    out->swept = out->tests = 0;
+    if (idx->counted && idx->n > 0) {
+        const size_t nw = (size_t)(idx->n + 63) / 64;
+        std::vector<long long> w(2 * nw);
+        RHG_HIP(hipMemcpyAsync(w.data(), idx->wstat, nw * 16, hipMemcpyDeviceToHost, s));
+        RHG_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < nw; ++i) {
+            out->tests += w[2 * i];
+            out->swept += w[2 * i + 1];
+        }
+    }
     if (h[ST_EMIT_MISMATCH]) return fail(RHG_EINTERNAL, "emit pass disagreed with the count pass");
     return RHG_OK;
 }

@@ -48,6 +48,9 @@ struct Layout {
     int no_stream_stage;              // per-query streams never staged in LDS
     int sweep_max;                    // unions of at most this many candidates are swept
     int sweep_linear;                 // swept chunks filtered candidate by candidate
+    int exact_inline;                 // undecided pairs decided inside the search kernels
+    int64_t defer_cap;                // capacity of the undecided-pair list
+    int64_t hset_slots;               // slots of the resolved-edge set (a power of two >= 2 defer_cap)
 };
 
 // Expected degree of a point at radius r (threshold model): the other n - 1
@@ -93,8 +96,8 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L);
 
 // Timed phases (rhg_phase_times).
 enum { RHG_PHASE_SAMPLE = 0, RHG_PHASE_SORT = 1, RHG_PHASE_INDEX = 2, RHG_PHASE_GATHER = 3,
-       RHG_PHASE_PLAN = 4, RHG_PHASE_COUNT_HEAVY = 5, RHG_PHASE_COUNT_PASS = 6, RHG_PHASE_SCAN = 7,
-       RHG_PHASE_EMIT_HEAVY = 8, RHG_PHASE_EMIT_PASS = 9, RHG_PHASE_ROWS = 10, RHG_PHASE_COUNT = 11 };
+       RHG_PHASE_PLAN = 4, RHG_PHASE_COUNT_PASS = 5, RHG_PHASE_SCAN = 6, RHG_PHASE_EMIT_PASS = 7,
+       RHG_PHASE_ROWS = 8, RHG_PHASE_COUNT = 9 };
 
 // Brackets a phase with HIP events on stream s when profiling is on.
 void *phase_begin(int phase, hipStream_t s);
@@ -113,7 +116,7 @@ struct PhaseScope {
 
 // Device-side counters (one 64-bit word each).
 enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4,
-       ST_SWEPT = 5, ST_TESTS = 6, ST_REG_STREAMS = 7, ST_COUNT = 8 };
+       ST_REG_STREAMS = 5, ST_COUNT = 6 };
 
 }  // namespace rhg
 
@@ -138,6 +141,13 @@ struct rhg_index {
     int64_t max_chunks;
     double2 *rt;           // (r, theta) interleaved in sample order, for the gather
     unsigned long long *stats;  // ST_COUNT counters
+    void *wstat;           // per light wavefront of the last count pass: (tests, candidates swept)
+    int counted;           // a count pass has run on this index
+    uint64_t *dkeys;       // undecided-pair list (defer_cap): packed sorted positions
+    int32_t *dchunk;       // its heavy chunk, or -1
+    unsigned long long *dcount;  // [0] pairs listed, [1] overflow flag
+    uint64_t *hset;        // resolved edges (hset_slots)
+    int64_t hset_slots;
     void *rows_aux;        // row sort: counters, long-row list, tile map
     int64_t rows_lcap;     // long rows the list holds
     int64_t rows_mapcap;   // tiles the map holds

@@ -231,8 +231,16 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // A wavefront's union window of up to sweep_max candidates is staged and
     // swept even where its lanes' windows do not overlap: one contiguous
     // read for all lanes instead of a directory lookup and a run per lane.
-    L->sweep_max = (t && t->sweep_max > 0) ? t->sweep_max : (t && t->sweep_max < 0) ? 0 : 512;
+    L->sweep_max = (t && t->sweep_max > 0) ? t->sweep_max : (t && t->sweep_max < 0) ? 0 : 128;
     L->sweep_linear = (t && t->sweep_linear) ? 1 : 0;
+    // Pairs the FP32 screen leaves undecided are listed for an exact pass
+    // after the search (about 1.5e-4 of the edges at n = 1e8); a longer list
+    // sends both passes to the kernels that decide them in place.
+    L->exact_inline = (t && t->exact_inline) ? 1 : 0;
+    L->defer_cap = (t && t->defer_cap > 0) ? (int64_t)t->defer_cap : 65536 + (int64_t)(n / 1024.0);
+    int64_t hs = 1;
+    while (hs < 2 * L->defer_cap) hs <<= 1;
+    L->hset_slots = hs;
 }
 
 }  // namespace rhg

@@ -29,8 +29,7 @@
 //
 // Work split.  The first positions of the sorted index (the innermost
 // points, the hubs) are "heavy": each (heavy query, band) pair is split into
-// chunks of candidates, each a work item for a whole workgroup of their own
-// kernel.  Every other query is "light": a wavefront takes 64 consecutive
+// chunks of candidates, each a work item for a whole workgroup.  Every other query is "light": a wavefront takes 64 consecutive
 // sorted positions (same band, adjacent angles) and, per band, the union of
 // its lanes' windows.  A union that is short, or whose lanes' windows
 // overlap, is swept: the unions of all such bands are read in one stream of
@@ -41,6 +40,8 @@
 // step.  The emit pass repeats the count pass's search in the same order and
 // writes each row in place.
 #include <string.h>
+
+#include <algorithm>
 
 #include "rhg_internal.h"
 
@@ -66,6 +67,7 @@ struct SearchArgs {
     int band_bits;                    // top bits of a sort key holding the band
     int sweep_max;                    // unions of at most this many candidates are swept
     int sweep_linear;                 // lanes filter every candidate of a swept chunk
+    const uint32_t *keys;             // sorted keys: band, then the top angle bits
     const uint32_t *ids;              // sorted ids (4 bytes where only the id is needed)
     const int32_t *band_start;
     const int32_t *dir;
@@ -77,6 +79,17 @@ struct SearchArgs {
     int32_t *hitem;                   // per heavy chunk: its item
     int64_t *hscal;                   // [0] candidate total, [1] chunk size
     unsigned long long *stats;
+    longlong2 *wstat;                 // count pass, per light wavefront: (tests, candidates swept)
+    // pairs the FP32 screen leaves undecided: the count pass lists them
+    // (sorted positions q, c; the heavy chunk or -1), a resolving kernel
+    // decides them exactly, adds the edges to the degrees and to a hash set,
+    // and the emit pass looks them up
+    uint64_t *dkeys;
+    int32_t *dchunk;
+    unsigned long long *dcount;       // [0] pairs listed, [1] the list overflowed
+    int64_t dcap;                     // list capacity
+    uint64_t *hset;                   // open-addressing set of listed edges (0 = empty slot)
+    int64_t hmask;                    // its size - 1 (a power of two, at least twice dcap)
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
 };
 
@@ -172,18 +185,50 @@ __device__ __forceinline__ int p32(double tq, float eq, float mq, float sq, doub
     return L < P32_ACC ? 1 : (L > P32_REJ ? 0 : 2);
 }
 
+// A listed pair as a set key: never 0, the empty slot.
+__device__ __forceinline__ uint64_t pair_key(int64_t q, int64_t c)
+{
+    return (1ull << 63) | ((uint64_t)(uint32_t)q << 32) | (uint32_t)c;
+}
+__device__ __forceinline__ uint64_t slot_hash(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
 // The pair (query at sorted position q, candidate c): the FP32 screen, then
-// the exact test, which reads the query's radius from the index.
+// the exact test.  EXACT decides it here (binary64, then double-double; the
+// calls need a stack and spill the caller's registers, so the fast kernels
+// keep them out): the count pass instead lists the pair and counts it later
+// if it is an edge, and the emit pass finds the resolved edges in the set.
+// `chunk` is the heavy chunk the pair belongs to (-1 for a light query).
+template <int MODE, bool EXACT>
 __device__ __forceinline__ int decide(const SearchArgs &A, int64_t q, double tq, float eq, float mq, float sq,
-                                      int64_t c, double tc, float ec, float mc, float sc, bool full_poly)
+                                      int64_t c, double tc, float ec, float mc, float sc, bool full_poly,
+                                      int64_t chunk)
 {
     int v = 2;
     if (A.use_p32) v = p32(tq, eq, mq, sq, tc, ec, mc, sc, full_poly);
-    if (v == 2) {
-        if (A.use_p32) atomicAdd(&A.stats[ST_FP32_UNDECIDED], 1ull);
-        v = edge_p64(A.sr[q], tq, A.sr[c], tc, A.C, A.C_lo, A.stats);
+    if (v != 2) return v;
+    if (EXACT) {
+        if (A.use_p32 && MODE == M_COUNT) atomicAdd(&A.stats[ST_FP32_UNDECIDED], 1ull);
+        return edge_p64(A.sr[q], tq, A.sr[c], tc, A.C, A.C_lo, A.stats);
     }
-    return v;
+    const uint64_t key = pair_key(q, c);
+    if (MODE == M_COUNT) {
+        const unsigned long long k = atomicAdd(&A.dcount[0], 1ull);
+        if ((int64_t)k < A.dcap) {
+            A.dkeys[k] = key;
+            A.dchunk[k] = (int32_t)chunk;
+        }
+        return 0;
+    }
+    for (uint64_t h = slot_hash(key) & (uint64_t)A.hmask;; h = (h + 1) & (uint64_t)A.hmask) {
+        const uint64_t x = A.hset[h];
+        if (x == key) return 1;
+        if (x == 0) return 0;
+    }
 }
 
 // ------------------------------------------------------------ windows
@@ -356,7 +401,7 @@ __global__ void __launch_bounds__(256) heavy_plan_chunks(SearchArgs A)
 // time.  The count pass records the chunk's count; in the emit pass the
 // prefix of the counts places the chunk's neighbours inside the query's row
 // (the row order is (band, chunk, candidate)).
-template <int MODE>
+template <int MODE, bool EXACT>
 __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
 {
     constexpr bool EMIT = MODE == M_EMIT;
@@ -415,7 +460,7 @@ __device__ void heavy_chunk(const SearchArgs &A, int64_t c, const int64_t *row_p
         int acc = 0;
         const int32_t cid = __float_as_int(fc.w);
         if (v < v1 && pos != q)
-            acc = inside ? 1 : decide(A, q, tq, fq.x, fq.y, fq.z, pos, tc, fc.x, fc.y, fc.z, full_poly);
+            acc = inside ? 1 : decide<MODE, EXACT>(A, q, tq, fq.x, fq.y, fq.z, pos, tc, fc.x, fc.y, fc.z, full_poly, c);
         const uint64_t bal = __ballot(acc);
         const int buf = (int)(((vb - v0) >> 8) & 1);
         if (lane == 0) wave_cnt[buf][wave] = __popcll(bal);
@@ -468,6 +513,13 @@ __device__ __forceinline__ int wave_excl_sum(int v, int lane, int *total)
     *total = __shfl(x, 63, 64);
     return x - v;
 }
+// Lane l's value, as a wave-uniform scalar.
+__device__ __forceinline__ int64_t uni_lane64(int64_t v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
 __device__ __forceinline__ int64_t wave_excl_sum64(int64_t v, int lane, int64_t *total)
 {
     int64_t x = v;
@@ -504,23 +556,33 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The angle part of a sort key: the index orders each band's positions by
-// it (points with equal keys stay in id order), so a binary search on it
-// finds where an angle's run of positions starts.
-__device__ __forceinline__ uint32_t akey(const SearchArgs &A, double t)
+// The sort key of angle t in band j, as the index computed it (the index
+// orders each band's positions by it; points with equal keys stay in id
+// order), so a binary search on the staged keys finds where an angle's run
+// of positions starts.
+__device__ __forceinline__ uint32_t band_key(const SearchArgs &A, int j, double t)
 {
-    return angle_key_s(t) >> A.band_bits;
+    const uint32_t ak = angle_key_s(t);
+    return A.band_bits ? (((uint32_t)j << (32 - A.band_bits)) | (ak >> A.band_bits)) : ak;
 }
 
 // A wavefront's LDS.  The sweep stages a chunk of candidates; a per-query
 // stream keeps its map (one word per step with a bit at each owner's first
 // entry, and the owners' runs in lane order) and stages STREAM_CHUNK steps.
-constexpr int SWEEP_C = 256;
+constexpr int SWEEP_C = 128;
+constexpr int ROWBUF = 16;  // emit pass: row entries each lane gathers in LDS before writing them
 constexpr int STREAM_STEPS = 64;
 constexpr int STREAM_CHUNK = 4;
 struct SweepStage {
     double t[SWEEP_C];
     float4 rec[SWEEP_C];
+    uint32_t key[SWEEP_C];
+    int32_t row[ROWBUF][64];  // entry i of lane l's buffered row run at row[i][l]
+};
+// A run of a row written as whole 16-byte stores where the target allows
+// dword-aligned ones (the compiler splits them otherwise).
+struct __attribute__((aligned(4))) int4a {
+    int32_t x, y, z, w;
 };
 struct StreamStage {
     float4 rec[STREAM_CHUNK][64];
@@ -546,7 +608,7 @@ static_assert(STREAM_STEPS == 64, "one word per lane is cleared");
 // M_COUNT writes the degree, M_EMIT the row.  The row order is the same in
 // both: the inside bands in band order, then the swept bands in band order
 // (each in position order), then the per-query bands in band order.
-template <int MODE>
+template <int MODE, bool EXACT>
 __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, int32_t *col)
 {
     constexpr bool EMIT = MODE == M_EMIT;
@@ -565,7 +627,10 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     }
     const int64_t hend = uni64(*A.heavy_end);
     const bool active = inb && p >= hend;
-    if (__ballot(active) == 0) return;
+    if (__ballot(active) == 0) {
+        if (!EMIT && lane == 0 && base < A.n) A.wstat[base >> 6] = make_longlong2(0, 0);
+        return;
+    }
     if (!active) {
         rq = 0.0;
         tq = 0.0;
@@ -612,7 +677,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         }
     }
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int tests = 0;
+    int tests = 0, swept = 0;
 
     // band table: lane j describes band j
     int mode = 0;  // 0 nothing, 1 swept, 2 per-query windows
@@ -651,12 +716,29 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     if ((b0 - a0) + (b1 - a1) == 0) mode = 0;
     const float rsq = active && fq.z > 0.0f ? rsqrtf(fq.z) : 0.0f;
 
+    // EMIT: the swept bands' entries of this lane's row gather in LDS,
+    // ROWBUF at a time, and leave as whole runs; row entries [fl, fl + nb)
+    // are buffered.
+    int64_t fl = cnt;
+    int nb = 0;
+
     // The pair (this lane's query, candidate at sorted position c): the
-    // exact decision, counted and (EMIT) written to the row.
-    auto take = [&](int64_t c, double tc, float4 fc, bool fp) {
+    // exact decision, counted and (EMIT) put into the row.
+    auto take = [&](int64_t c, double tc, float4 fc, bool fp, SweepStage &S) {
         ++tests;
-        if (decide(A, p, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp)) {
-            if (EMIT && cnt < lim) out[cnt] = __float_as_int(fc.w);
+        if (decide<MODE, EXACT>(A, p, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp, -1)) {
+            if (EMIT && cnt < lim) {
+                S.row[nb][lane] = __float_as_int(fc.w);
+                if (++nb == ROWBUF) {
+                    // a full buffer: fl + ROWBUF <= lim
+#pragma unroll
+                    for (int i = 0; i < ROWBUF; i += 4)
+                        *(int4a *)(out + fl + i) = int4a{S.row[i][lane], S.row[i + 1][lane], S.row[i + 2][lane],
+                                                          S.row[i + 3][lane]};
+                    fl += ROWBUF;
+                    nb = 0;
+                }
+            }
             ++cnt;
         }
     };
@@ -670,11 +752,12 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         const int L0 = b0 - a0;
         int tot;
         const int pre = wave_excl_sum(T, lane, &tot);  // band `lane`'s entries are [pre, pre + T)
-        if (!EMIT && lane == 0) atomicAdd(&A.stats[ST_SWEPT], (unsigned long long)tot);
+        swept = tot;
         for (int c0 = 0; c0 < tot; c0 += SWEEP_C) {
             wave_sync();  // the previous chunk's reads are done
             double tl[SWEEP_C / 64];
             float4 rl[SWEEP_C / 64];
+            uint32_t kl[SWEEP_C / 64];
 #pragma unroll
             for (int k = 0; k < SWEEP_C / 64; ++k) {
                 const int t = c0 + 64 * k + lane;
@@ -689,16 +772,19 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 const int l0 = __shfl(L0, jb, 64), ja0 = __shfl(a0, jb, 64), ja1 = __shfl(a1, jb, 64);
                 tl[k] = 0.0;
                 rl[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                kl[k] = 0u;
                 if (t < tot) {
                     const int64_t pos = off < l0 ? (int64_t)ja0 + off : (int64_t)ja1 + (off - l0);
                     tl[k] = A.st[pos];
                     rl[k] = A.rec[pos];
+                    kl[k] = A.keys[pos];
                 }
             }
 #pragma unroll
             for (int k = 0; k < SWEEP_C / 64; ++k) {
                 S.t[64 * k + lane] = tl[k];
                 S.rec[64 * k + lane] = rl[k];
+                S.key[64 * k + lane] = kl[k];
             }
             wave_sync();
             const int cend = min(tot, c0 + SWEEP_C);
@@ -709,6 +795,18 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 if (ls >= hs || !(active && j >= J)) continue;
                 const int ja0 = __builtin_amdgcn_readlane(a0, j), ja1 = __builtin_amdgcn_readlane(a1, j);
                 const int jl0 = __builtin_amdgcn_readlane(L0, j);
+                // a segment of a few candidates: each is tested as it is,
+                // with no window to compute first
+                if (hs - ls <= 4) {
+                    for (int k = ls; k < hs; ++k) {
+                        const float4 fc = S.rec[k];
+                        if (__float_as_int(fc.w) == id) continue;
+                        const int off = c0 + k - pj;
+                        const int64_t pos = off < jl0 ? (int64_t)ja0 + off : (int64_t)ja1 + (off - jl0);
+                        take(pos, S.t[k], fc, true, S);
+                    }
+                    continue;
+                }
                 const double w = (fq.z > 0.0f) ? window_fast(A, rsq, fq.x, fq.y, fq.z, j) : 4.0;
                 // every tested candidate lies within w of the query, so the
                 // two-term sine serves windows below 2^-5
@@ -720,12 +818,12 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     if (__float_as_int(fc.w) == id) return;
                     const int off = c0 + k - pj;
                     const int64_t pos = off < jl0 ? (int64_t)ja0 + off : (int64_t)ja1 + (off - jl0);
-                    take(pos, tc, fc, fp);
+                    take(pos, tc, fc, fp, S);
                 };
                 // a half-width of 3 or more: the linear filter (the two pieces
                 // below stay apart by more than a key step only for narrower
                 // windows, 2 pi - 2w > 0.28 rad)
-                if (!(w < 3.0) || hs - ls <= 16 || A.sweep_linear) {
+                if (!(w < 3.0) || hs - ls <= 8 || A.sweep_linear) {
                     for (int k = ls; k < hs; ++k) test(k);
                     continue;
                 }
@@ -737,7 +835,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                     int lo = ls, hi = hs;
                     while (lo < hi) {
                         const int mid = (lo + hi) >> 1;
-                        if (akey(A, S.t[mid]) < kq) lo = mid + 1;
+                        if (S.key[mid] < kq) lo = mid + 1;
                         else hi = mid;
                     }
                     return lo;
@@ -746,15 +844,28 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 // of the linear filter)
                 const double wlo = tq - w, whi = tq + w;
                 if (whi >= RHG_TWO_PI_D) {
-                    const uint32_t k2 = akey(A, whi - RHG_TWO_PI_D);
-                    for (int k = ls; k < hs && akey(A, S.t[k]) <= k2; ++k) test(k);
+                    const uint32_t k2 = band_key(A, j, whi - RHG_TWO_PI_D);
+                    for (int k = ls; k < hs && S.key[k] <= k2; ++k) test(k);
                 }
-                const uint32_t khi = akey(A, fmin(whi, RHG_TWO_PI_D));
-                for (int k = lower(akey(A, fmax(wlo, 0.0))); k < hs && akey(A, S.t[k]) <= khi; ++k) test(k);
+                const uint32_t khi = band_key(A, j, fmin(whi, RHG_TWO_PI_D));
+                for (int k = lower(band_key(A, j, fmax(wlo, 0.0))); k < hs && S.key[k] <= khi; ++k) test(k);
                 if (wlo < 0.0)
-                    for (int k = lower(akey(A, wlo + RHG_TWO_PI_D)); k < hs; ++k) test(k);
+                    for (int k = lower(band_key(A, j, wlo + RHG_TWO_PI_D)); k < hs; ++k) test(k);
             }
         }
+    }
+
+    if (EMIT && swm) {
+        // the rest of every lane's buffered run, one lane's run per store
+        SweepStage &S = SM.u.sw;
+        wave_sync();
+        for (uint64_t m = __ballot(nb > 0); m; m &= m - 1) {
+            const int l = __ffsll((unsigned long long)m) - 1;
+            const int ln = __builtin_amdgcn_readlane(nb, l);
+            int32_t *const dst = (int32_t *)uni_lane64((int64_t)(out + fl), l);
+            if (lane < ln) dst[lane] = S.row[lane][l];
+        }
+        wave_sync();  // the stage is reused by the per-query bands
     }
 
     // ---- per-query bands (the lanes' angles spread wider than the window):
@@ -834,7 +945,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             const int cid = __float_as_int(fc.w);
             if (valid && c != lp && !(short_angle(lt, tc) > lw)) {
                 ++tests;
-                acc = decide(A, lp, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp);
+                acc = decide<MODE, EXACT>(A, lp, lt, le, lmq, ls, c, tc, fc.x, fc.y, fc.z, lfp, -1);
             }
             const uint64_t bal = __ballot(acc);
             // this lane's part of the step, as the owner of [pre, pre + len)
@@ -920,7 +1031,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     if (!EMIT) {
         int tt;
         wave_excl_sum(tests, lane, &tt);
-        if (lane == 0 && tt) atomicAdd(&A.stats[ST_TESTS], (unsigned long long)tt);
+        if (lane == 0) A.wstat[base >> 6] = make_longlong2(tt, swept);
     }
     if (!active) return;
     if (EMIT) {
@@ -932,28 +1043,59 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
 
 // ------------------------------------------------------------ kernels
 
-// The heavy chunks: a pool of workgroups strides over them in (query, band,
-// chunk) order, hubs first.
-template <int MODE>
-__global__ void __launch_bounds__(256) heavy_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
-                                                    int32_t *__restrict__ col_idx)
+// The search: workgroups [0, heavy_blocks) are a pool striding over the
+// heavy chunks in (query, band, chunk) order, hubs first; the rest take 256
+// consecutive light positions each, one wavefront per 64.  The heavy pool
+// has the lowest workgroup ids, so it starts first and the light
+// wavefronts fill the chip around it.  The fast kernel (EXACT false) lists
+// the pairs its FP32 screen leaves undecided; when that list overflowed in
+// the count pass (dcount[1]) the EXACT kernels redo both passes, and each
+// kind leaves as soon as it sees it is not the one to run.  The EXACT
+// kernel strides over the light positions with a grid of any size.
+template <int MODE, bool EXACT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr, int32_t *__restrict__ col_idx, int gate)
 {
     // emit pass into a buffer too small for the graph: write nothing (the
     // prologue has raised the overflow flag)
     if (MODE == M_EMIT && A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
-    const int64_t nch = uni64(A.hplan[A.heavy_cap * A.B - 1]);
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) heavy_chunk<MODE>(A, c, row_ptr, col_idx);
+    if (gate && (__builtin_amdgcn_readfirstlane((int)A.dcount[1]) != 0) != EXACT) return;
+    if ((int)blockIdx.x < A.heavy_blocks) {
+        const int64_t nch = uni64(A.hplan[A.heavy_cap * A.B - 1]);
+        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<MODE, EXACT>(A, c, row_ptr, col_idx);
+        return;
+    }
+    const int64_t lb = (A.n + 255) / 256, nb = (int64_t)gridDim.x - A.heavy_blocks;
+    for (int64_t b = (int64_t)blockIdx.x - A.heavy_blocks; b < lb; b += nb) {
+        light_wave<MODE, EXACT>(A, b * 256 + (threadIdx.x & ~63), row_ptr, col_idx);
+        if (!EXACT) break;
+    }
 }
 
-// The light queries: 256 consecutive sorted positions per workgroup, one
-// wavefront each.
-template <int MODE>
-__global__ void __launch_bounds__(256) light_kernel(SearchArgs A, int64_t *__restrict__ row_ptr,
-                                                    int32_t *__restrict__ col_idx)
+// After the fast count pass: decide the listed pairs exactly, count the
+// edges among them (the light query's degree, or the heavy chunk's count)
+// and enter them in the set the emit pass reads.  Flags an overflowed list.
+__global__ void __launch_bounds__(256) resolve_kernel(SearchArgs A, int64_t *__restrict__ row_ptr)
 {
-    if (MODE == M_EMIT && A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
-    const int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
-    light_wave<MODE>(A, base, row_ptr, col_idx);
+    const unsigned long long cnt = A.dcount[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if ((int64_t)cnt > A.dcap) A.dcount[1] = 1;
+        if (A.use_p32 && cnt) atomicAdd(&A.stats[ST_FP32_UNDECIDED], cnt);
+    }
+    if ((int64_t)cnt > A.dcap) return;
+    const int64_t m = (int64_t)cnt, stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += stride) {
+        const uint64_t key = A.dkeys[i];
+        const int64_t q = (int64_t)((key >> 32) & 0x7fffffffull), c = (int64_t)(key & 0xffffffffull);
+        if (!edge_p64(A.sr[q], A.st[q], A.sr[c], A.st[c], A.C, A.C_lo, A.stats)) continue;
+        for (uint64_t h = slot_hash(key) & (uint64_t)A.hmask;; h = (h + 1) & (uint64_t)A.hmask) {
+            const unsigned long long prev = atomicCAS((unsigned long long *)&A.hset[h], 0ull, (unsigned long long)key);
+            if (prev == 0ull || prev == key) break;
+        }
+        const int32_t ch = A.dchunk[i];
+        if (ch >= 0) atomicAdd((unsigned long long *)&A.hcnt[ch], 1ull);
+        else atomicAdd((unsigned long long *)&row_ptr[__float_as_int(A.rec[q].w) + 1], 1ull);
+    }
 }
 
 // Before the count pass: heavy_end = the first light position (the end of
@@ -966,6 +1108,8 @@ __global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_
         *heavy_end = (int32_t)h;
         row_ptr[0] = 0;
         A.hscal[0] = 0;
+        A.dcount[0] = 0;
+        A.dcount[1] = 0;
     }
 }
 
@@ -1030,6 +1174,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     }
     A.B = L.B;
     A.band_bits = L.band_bits;
+    A.keys = idx->keys;
     A.ids = idx->ids;
     A.n = idx->n;
     A.heavy_cap = idx->heavy_cap;
@@ -1055,6 +1200,13 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.hitem = idx->hitem;
     A.hscal = idx->hscal;
     A.stats = idx->stats;
+    A.wstat = (longlong2 *)idx->wstat;
+    A.dkeys = idx->dkeys;
+    A.dchunk = idx->dchunk;
+    A.dcount = idx->dcount;
+    A.dcap = L.defer_cap;
+    A.hset = idx->hset;
+    A.hmask = idx->hset_slots - 1;
     A.col_cap = col_cap;
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
@@ -1083,21 +1235,38 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         if (n <= 0) return hipSuccess;
     }
     plan_ps.end();
-    const dim3 lg((unsigned)((n + 255) / 256)), b(256);
+    const dim3 g((unsigned)(A.heavy_blocks + (n + 255) / 256)), b(256);
+    // the EXACT kernels, when they only stand by for an overflowed list,
+    // run on a smaller grid (their light part strides)
+    const dim3 gx((unsigned)(A.heavy_blocks + std::min<int64_t>((n + 255) / 256, 4096)));
+    // with no FP32 screen (or on request) every undecided pair is decided
+    // in place: the EXACT kernels alone
+    const bool exact_only = !A.use_p32 || L.exact_inline;
     {
-        PhaseScope ps(emit ? RHG_PHASE_EMIT_HEAVY : RHG_PHASE_COUNT_HEAVY, s);
-        if (items > 0) {
-            if (emit) hipLaunchKernelGGL(heavy_kernel<M_EMIT>, dim3(A.heavy_blocks), b, 0, s, A, row_ptr, col_idx);
-            else hipLaunchKernelGGL(heavy_kernel<M_COUNT>, dim3(A.heavy_blocks), b, 0, s, A, row_ptr, col_idx);
+        PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
+        if (exact_only) {
+            if (emit) hipLaunchKernelGGL((search_kernel<M_EMIT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
+            else hipLaunchKernelGGL((search_kernel<M_COUNT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
+        } else if (emit) {
+            hipLaunchKernelGGL((search_kernel<M_EMIT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
+        } else {
+            if (A.hmask >= 0)
+                hipLaunchKernelGGL(zero_i64, dim3((unsigned)((A.hmask + 256) / 256)), dim3(256), 0, s, (int64_t *)A.hset,
+                                   A.hmask + 1);
+            hipLaunchKernelGGL((search_kernel<M_COUNT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
         }
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    {
-        PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
-        if (emit) hipLaunchKernelGGL(light_kernel<M_EMIT>, lg, b, 0, s, A, row_ptr, col_idx);
-        else hipLaunchKernelGGL(light_kernel<M_COUNT>, lg, b, 0, s, A, row_ptr, col_idx);
+    if (!exact_only) {
+        PhaseScope ps(RHG_PHASE_PLAN, s);
+        if (!emit) {
+            hipLaunchKernelGGL(resolve_kernel, dim3(256), dim3(256), 0, s, A, row_ptr);
+            hipLaunchKernelGGL((search_kernel<M_COUNT, true>), gx, b, 0, s, A, row_ptr, col_idx, 1);
+        } else {
+            hipLaunchKernelGGL((search_kernel<M_EMIT, true>), gx, b, 0, s, A, row_ptr, col_idx, 1);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (emit && overflow) {
         hipLaunchKernelGGL(emit_epilogue, dim3(1), dim3(64), 0, s, (const unsigned long long *)idx->stats, overflow);
         if ((e = hipGetLastError()) != hipSuccess) return e;

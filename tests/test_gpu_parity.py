@@ -110,8 +110,8 @@ def test_sweep_and_per_query_paths_give_the_same_rows():
         rp_r, col_r, _ = run_search(P, params, r, t, tuning=dict(tun, sweep_max=-1, no_stream_stage=1))
         _say("paths", tun, st_s, st_w, st_q, st_m)
         assert st_w["swept"] >= st_s["swept"] > st_m["swept"] > st_q["swept"]
-        # every path tests exactly the candidates inside each query's window
-        assert st_l["tests"] == st_s["tests"] == st_w["tests"] == st_q["tests"] == st_m["tests"]
+        # the linear filter and the binary search test the same candidates
+        assert st_l["tests"] == st_s["tests"]
         for rp_x in (rp_s, rp_w, rp_q, rp_l, rp_r, rp_m):
             assert np.array_equal(rp_x, orp)
         # the same tested pairs in the same order: the same bytes
@@ -309,7 +309,7 @@ def test_c3_full_size_points_and_sampled_rows():
 
 def test_count_and_emit_twice_on_one_index():
     """Counting and emitting a second time on the same index gives the same
-    bytes (the diagnostics are summed since the build)."""
+    bytes and the same per-pass test count."""
     import torch
     n, k, g = 30_000, 16.0, 2.4
     params, a, R = _params_for(n, k, g, 77)
@@ -327,6 +327,6 @@ def test_count_and_emit_twice_on_one_index():
     idx.free()
     _say("twice:", out[0][2], out[1][2])
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
-    assert out[0][2]["tests"] > 0 and out[1][2]["tests"] == 2 * out[0][2]["tests"]
+    assert out[0][2]["tests"] > 0 and out[1][2]["tests"] == out[0][2]["tests"]
     orp, ocol, _, _ = O.csr(r, t, R)
     assert np.array_equal(out[1][0], orp) and np.array_equal(canonical(out[1][0], out[1][1]), ocol)

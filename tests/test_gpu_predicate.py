@@ -7,7 +7,9 @@ windows (band inner edges), the angular cell directory and the 0 / 2 pi
 seam could each lose a pair (see tests/adversarial.py), at the radii of the
 n = 1e4 (R = 16.7) and n = 1e8 (R = 36.9) configurations, under tunings
 that send the pairs through the heavy (workgroup) and the light (wavefront)
-search paths, and through the plain binary64 path."""
+search paths, and through the plain binary64 path; the undecided pairs are
+listed and resolved after the count pass by default, decided in place with
+exact_inline, and in place again when their list overflows."""
 import numpy as np
 import pytest
 
@@ -20,6 +22,10 @@ TUNINGS = {
     "light": {"heavy_points": 64},
     "light_narrow_bands": {"heavy_points": 64, "band_width": 0.5},
     "fp64_only": {"heavy_points": 64, "fp64_only": 1},
+    # undecided pairs decided inside the search kernels, and a list too
+    # short for them (both passes rerun with in-place decisions)
+    "exact_inline": {"exact_inline": 1},
+    "list_overflow": {"heavy_points": 64, "defer_cap": 8},
 }
 
 

@@ -389,6 +389,24 @@ rhg_status rhg_generate_async(const rhg_params *p /* host */, const rhg_tuning *
                               int64_t *row_ptr, int32_t *col_idx, int64_t col_capacity,
                               int32_t *overflow, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rhg_generate_async with the index workspace taken from the library's own
+ * device array of RHG_NOALLOC_SCRATCH_BYTES bytes, one per GPU, held from
+ * the library's first use of that GPU until the process ends.  The caller
+ * still passes the points, the CSR and the overflow flag exactly as for
+ * rhg_generate_async (same meaning, same results, bit for bit); the stream
+ * must belong to the current device.  Allocates no device memory.  Every
+ * call on one GPU uses the same array, so calls whose stream work overlaps
+ * on a GPU race and must be ordered by the caller.
+ * Errors: those of rhg_generate_async; RHG_ECAPACITY when
+ * rhg_index_workspace_bytes(p, t) exceeds RHG_NOALLOC_SCRATCH_BYTES (about
+ * n = 7e5 points); RHG_EDEVICE when the array's address cannot be read. */
+#define RHG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+rhg_status rhg_generate_async_noalloc(const rhg_params *p /* host */, const rhg_tuning *t /* host, may be NULL */,
+                                      double *r, double *theta, int64_t *row_ptr, int32_t *col_idx,
+                                      int64_t col_capacity, int32_t *overflow, void *stream);
+
 typedef struct rhg_batch rhg_batch;  /* opaque, host-side handle */
 
 /* Captures rhg_generate_async for `count` graphs into one HIP graph (one

@@ -99,6 +99,7 @@ def load():
         "rhg_index_free": (None, [vp]),
         "rhg_generate": (i32, [i64, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
         "rhg_generate_async": (i32, [P(rhg_params), P(rhg_tuning), vp, vp, vp, C.c_size_t, vp, vp, i64, vp, vp]),
+        "rhg_generate_async_noalloc": (i32, [P(rhg_params), P(rhg_tuning), vp, vp, vp, vp, i64, vp, vp]),
         "rhg_batch_create": (i32, [i32, P(rhg_params), P(rhg_tuning), P(vp), P(vp), P(vp), P(C.c_size_t), P(vp),
                                    P(vp), P(i64), vp, i32, P(vp)]),
         "rhg_batch_launch": (i32, [vp, vp]),
@@ -381,6 +382,16 @@ def rhg_generate_async(p: rhg_params, r, theta, workspace, row_ptr, col_idx, ove
                                      _ptr(overflow), _stream(stream)))
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20  # RHG_NOALLOC_SCRATCH_BYTES
+
+
+def rhg_generate_async_noalloc(p: rhg_params, r, theta, row_ptr, col_idx, overflow, tuning=None, stream=None):
+    """rhg_generate_async with the library's own per-GPU workspace (no
+    device allocation; calls on one GPU must not overlap)."""
+    _check(load().rhg_generate_async_noalloc(C.byref(p), _tuning(tuning), _ptr(r), _ptr(theta), _ptr(row_ptr),
+                                             _ptr(col_idx), col_idx.numel(), _ptr(overflow), _stream(stream)))
+
+
 def expected_col_capacity(p: rhg_params, slack: float = 1.3) -> int:
     """int32 slots to reserve for col_idx before counting: 2m in expectation
     (the target degree times n), with slack for the spread of the degree."""
@@ -479,6 +490,7 @@ __all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_worksp
            "rhg_sort_rows_workspace_bytes", "rhg_long_range", "rhg_long_range_workspace_bytes",
            "long_range_count", "rhg_graph_stats", "rhg_graph_stats_workspace_bytes", "rhg_index_stats",
            "rhg_generate",
-           "rhg_set_profiling", "rhg_phase_times", "rhg_generate_async", "GraphBuffers", "Batch",
+           "rhg_set_profiling", "rhg_phase_times", "rhg_generate_async", "rhg_generate_async_noalloc",
+           "GraphBuffers", "Batch",
            "expected_col_capacity", "RhgError", "Graph", "Index", "load", "version",
            "LIB_PATH", "PHASES"]

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -499,6 +500,46 @@ rhg_status rhg_generate_async(const rhg_params *p, const rhg_tuning *t, double *
     }
     rhg_index_free(idx);  // the launches hold their arguments by value
     return RHG_OK;
+}
+
+// The index workspace of rhg_generate_async_noalloc: one array per GPU
+// (each device holds its own copy at its own address), held until the
+// process ends.  Host code takes its address from hipGetSymbolAddress, once
+// per device, and passes that pointer on; the array's name is no device
+// address in host code.
+static __device__ __align__(256) unsigned char g_noalloc_scratch[RHG_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[256];
+
+rhg_status rhg_generate_async_noalloc(const rhg_params *p, const rhg_tuning *t, double *r, double *theta,
+                                      int64_t *row_ptr, int32_t *col_idx, int64_t col_capacity, int32_t *overflow,
+                                      void *stream)
+{
+    g_last_error.clear();
+    rhg_status st = check_params(p, "rhg_generate_async_noalloc");
+    if (st != RHG_OK) return st;
+    const size_t need = rhg_index_workspace_bytes(p, t);
+    if (need > RHG_NOALLOC_SCRATCH_BYTES)
+        return fail(RHG_ECAPACITY, "rhg_generate_async_noalloc: the index needs " + std::to_string(need) +
+                                       " bytes of workspace, the library's array holds " +
+                                       std::to_string((unsigned long long)RHG_NOALLOC_SCRATCH_BYTES));
+    int dev = 0;
+    RHG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 256) return fail(RHG_EDEVICE, "rhg_generate_async_noalloc: device index out of range");
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_noalloc_scratch));
+            if (e != hipSuccess || !ptr) return check_hip(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                          "rhg_generate_async_noalloc (hipGetSymbolAddress)");
+            g_noalloc_ptr[dev] = ptr;
+        }
+        ws = g_noalloc_ptr[dev];
+    }
+    return rhg_generate_async(p, t, r, theta, ws, RHG_NOALLOC_SCRATCH_BYTES, row_ptr, col_idx, col_capacity, overflow,
+                              stream);
 }
 
 struct rhg_batch {

@@ -7,10 +7,14 @@ timed region; the emit call's 8-byte read of 2m is inside it.
 
 Prints one JSON line (see the keys below).  `value` is undirected edges per
 second of the whole job.  `roofline` is the dominant kernel's achieved
-bandwidth (its algorithmic bytes per launch over its average launch time,
-both measured with HIP events on the library's stream during the timed
-steps).  `cpu_baseline` times the CPU oracle on a bounded sample of the same
-workload and scales it to the full job.
+bandwidth: the method's bytes of that pass (its share of the floor
+56n + 8m + 8) per launch over its average launch time, both measured with HIP
+events on the library's stream during the timed steps, with the HBM traffic
+rocprofv3 counted for the same kernel.  `step_roofline` puts the whole step
+against the same floor (floor fraction), against the counted traffic
+(achieved fraction and amplification) and against a measured device copy.
+`cpu_baseline` times the CPU oracle's pair loop on bounded samples of the
+same workload and extrapolates to the full job.
 """
 from __future__ import annotations
 
@@ -26,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 HBM-traffic summaries per workload (profiles/), see the design doc
+TRAFFIC_FILES = {"large": "traffic_n1e8_avgdeg20_gamma2.2.json"}
 METRIC = "undirected edges/sec at n=1e8 on 1 MI355X (% HBM roofline); p50/p99 request latency"
 
 
@@ -41,19 +47,17 @@ def _source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(phase: str, n: int, m: int, stored: int) -> int:
-    """Least bytes a phase has to move per launch (its inputs read once, its
-    outputs written once); `stored` is the number of neighbours the count
-    pass kept for the copy kernel."""
+def algorithmic_bytes(phase: str, n: int, m: int) -> int:
+    """The method's own bytes per launch of a phase: its share of the floor
+    B_alg = 56n + 8m + 8 of one generation (write the points, read them to
+    index, read them once to search, write the row offsets, write col_idx).
+    Everything else a phase moves (sort passes, sorted copies, the index's
+    records) is the design's traffic, reported under `traffic`."""
     table = {
-        "sample": 16 * n,                     # write r, theta
-        "keys+sort": 16 * n + 8 * n,          # read r, theta; write sorted (key, id)
-        "index": 4 * n,                       # read sorted keys (band starts, cell directory)
-        "gather": 4 * n + 16 * n + 32 * n,    # read ids, gather r, theta; write sorted r, theta, record
-        "count": 16 * n + 8 * n + 4 * stored,  # read sorted r, theta; write row offsets, stored neighbours
-        "scan": 16 * n,                       # read + write row offsets
-        "copy": 8 * stored + 8 * n,           # read + write stored neighbours; read row offsets
-        "emit": 8 * (m * 2 - stored) // 2,    # write the rest of the rows (heavy, inside bands, fallbacks)
+        "sample": 16 * n,                 # write r, theta
+        "keys+sort": 16 * n,              # read r, theta to index them
+        "count": 16 * n + 8 * (n + 1),    # read the points once to search; row offsets
+        "emit": 8 * m,                    # col_idx: 4 bytes x 2m entries
     }
     return int(table.get(phase, 0))
 
@@ -289,27 +293,52 @@ def copy_calibration(nbytes=4 << 30, reps=5):
     return {"bytes_each_way": nbytes, "ms": ms, "GB_s": 2 * nbytes / (ms / 1000.0) / 1e9}
 
 
-def cpu_baseline(cfg, params, m_edges, sample_pts):
-    """Oracle pair-test rate on all pairs among the first `sample_pts`
-    points of the same graph, scaled to the oracle's full job
-    (n samples + 2 n (n-1) ordered pair tests: degrees, then CSR fill)."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, params, m_edges, all_pts=40_000, one_pts=10_000, reps=3):
+    """The oracle's pair loop (every pair i < j tested once, the points
+    already in memory), timed around the loop alone, median of `reps`: on
+    all host threads over the first `all_pts` points of the graph, on one
+    thread over the first `one_pts`, and the n = 1e4 graph in full.  `value`
+    is the whole job's edges/s extrapolated from the all-core rate
+    (n (n - 1) / 2 pairs)."""
+    import statistics
     import oracle as O
     O.build(force=False)
+    threads = O.threads()
     n = cfg["n"]
-    t0 = time.perf_counter()
-    r, t, _ = O.sample(cfg["seed"], params.alpha, params.R, sample_pts)
-    t1 = time.perf_counter()
-    O.degrees(r, t, params.R)
-    t2 = time.perf_counter()
-    per_pt = (t1 - t0) / sample_pts
-    rate = sample_pts * (sample_pts - 1) / (t2 - t1)  # ordered pair tests per second
-    full_s = n * per_pt + 2.0 * n * (n - 1) / rate
-    return {"value": m_edges / full_s, "unit": "undirected edges/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": "all %d ordered pair tests among the first %d points of the same graph "
-                      "(+ sampling them), %.1f s wall; scaled to the full job of %d samples and "
-                      "2n(n-1) pair tests = %.3g s" % (sample_pts * (sample_pts - 1), sample_pts,
-                                                      t2 - t0, n, full_s)}
+    r, t, _ = O.sample(cfg["seed"], params.alpha, params.R, all_pts, nthreads=threads)
+
+    def rate(rr, tt, R, nt):
+        secs = [O.pair_scan(rr, tt, R, nthreads=nt, timing=True)[-1] for _ in range(reps)]
+        med = statistics.median(secs)
+        k = rr.shape[0]
+        return k * (k - 1) / 2 / med, med
+
+    all_rate, all_s = rate(r, t, params.R, threads)
+    one_rate, one_s = rate(r[:one_pts], t[:one_pts], params.R, 1)
+    a1, R1 = O.solve_R(10_000, 6.0, 3.0)
+    r1, t1, _ = O.sample(1, a1, R1, 10_000, nthreads=threads)
+    c1_rate, c1_s = rate(r1, t1, R1, threads)
+    O.threads()  # (the next oracle call sets its own thread count)
+    full_s = n * (n - 1) / 2 / all_rate
+    return {"value": m_edges / full_s, "unit": "undirected edges/s", "cores": threads, "kind": "oracle",
+            "sample": "pair loop only (points preloaded), median of %d: all %d threads over the first %d points "
+                      "of the same graph, %.3g pairs/s (%.2f s); one thread over the first %d points, %.3g pairs/s; "
+                      "whole job extrapolated as n(n-1)/2 = %.3g pairs / the all-thread rate = %.3g s"
+                      % (reps, threads, all_pts, all_rate, all_s, one_pts, one_rate, n * (n - 1) / 2, full_s),
+            "pairs_per_s_all_threads": all_rate, "pairs_per_s_one_thread": one_rate,
+            "c1_full": {"workload": "rhg n=10000 avg_degree=6 gamma=3 seed=1", "pair_loop_s": c1_s,
+                        "pairs_per_s": c1_rate},
+            "host": {"nproc": os.cpu_count(), "omp_threads": threads, "cpu_model": _cpu_model()}}
 
 
 def main():
@@ -318,12 +347,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="large", choices=["small", "medium", "large"])
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=40_000, help="points of the all-thread oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=512, help="graphs in the batch workload (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the serving run (0: skip)")
-    ap.add_argument("--calibrate", action="store_true", help="also time a 4 GiB device copy (HBM reference)")
     ap.add_argument("--band-width", type=float, default=0.0)
     ap.add_argument("--cell-target", type=int, default=0)
     args = ap.parse_args()
@@ -344,16 +372,33 @@ def main():
     m = res["nnz"] // 2
     sec = res["ms_per_step"] / 1000.0
     phases = res["phases"]
-    stored = int(res["stats"].get("stored", 0))
-    dom = max(phases, key=lambda k: phases[k][0])
+    # the dominant kernel: the longer of the two search kernels (each phase
+    # brackets exactly that one launch on the library's stream)
+    dom = max((k for k in ("count", "emit") if phases.get(k, (0, 0))[1]), key=lambda k: phases[k][0])
     dom_ms = phases[dom][0]
-    achieved = algorithmic_bytes(dom, n, m, stored) / (dom_ms / 1000.0) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (dom, args.config))
-    if os.path.exists(tfile):
+    alg = algorithmic_bytes(dom, n, m)
+    achieved = alg / (dom_ms / 1000.0) / 1e9
+    floor_bytes = 56 * n + 8 * m + 8
+    _log("copy calibration")
+    copy = copy_calibration()
+    # HBM traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+    # workload, taken on these very kernel sources (else null)
+    traffic, step_bytes, prof_src = None, None, None
+    tfile = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(args.config, ""))
+    if os.path.isfile(tfile):
         t = json.load(open(tfile))
-        if t.get("source_sha") == _source_sha():
-            traffic = t.get("bytes_per_launch")
+        prof_src = t.get("source_sha")
+        if prof_src == _source_sha():
+            traffic = t.get("bytes_per_launch", {}).get(dom)
+            step_bytes = t.get("step_bytes")
+    step_gbs = step_bytes / sec / 1e9 if step_bytes else None
+    step = {"floor_bytes": floor_bytes, "floor_frac": floor_bytes / sec / 1e9 / HBM_PEAK_GBS,
+            "achieved_bytes": step_bytes, "achieved_GB_s": step_gbs,
+            "achieved_frac": step_gbs / HBM_PEAK_GBS if step_gbs else None,
+            "amplification": step_bytes / floor_bytes if step_bytes else None,
+            "copy_GB_s": copy["GB_s"], "copy_frac": step_gbs / copy["GB_s"] if step_gbs else None,
+            "traffic_source": os.path.relpath(tfile, ROOT) if traffic is not None else
+            ("stale profile (sources changed since %s)" % prof_src if prof_src else None)}
     out = {
         "metric": METRIC,
         "value": m / sec,
@@ -371,20 +416,21 @@ def main():
             n, cfg["avg_degree"], cfg["gamma"], cfg["seed"], args.config),
             "n": n, "avg_degree": cfg["avg_degree"], "gamma": cfg["gamma"], "R": res["params"].R,
             "undirected_edges": m, "parallelism": "1 gpu"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": algorithmic_bytes(dom, n, m, stored), "avg_launch_ms": dom_ms},
+        "roofline": {"bound": "hbm", "kernel": "search_kernel (%s pass)" % dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes": alg, "avg_launch_ms": dom_ms,
+                     "traffic_frac": traffic / (dom_ms / 1000.0) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                     "amplification": traffic / alg if traffic else None},
+        "step_roofline": step,
         "phases_ms": {k: round(v[0] * v[1] / args.steps, 4) for k, v in phases.items() if v[1]},
         "canonical_rows": {"ms": res["rows_ms"], "form": "rhg_sort_rows on the emitted CSR (ascending rows), "
                            "timed apart from the step and not in value"},
         "long_range": dict(res["lr"], form="rhg_long_range: ceil(0.005 m) random extra edges merged into the "
                            "emitted CSR (RHG-LR), timed apart from the step and not in value"),
         "validation": res["validation"],
-        "pipeline_floor_frac": (56 * n + 8 * m) / sec / 1e9 / HBM_PEAK_GBS,
         "search_stats": res["stats"],
+        "copy_calibration": copy,
     }
-    if args.calibrate:
-        out["copy_calibration"] = copy_calibration()
     _log("validation statistics with triangles (n=1e7)")
     out["validation_triangles"] = run_validation_triangles()
     if args.batch > 0:
@@ -401,7 +447,7 @@ def main():
         _log("serve done: p50 %.2f ms p99 %.2f ms" % (out["serve"]["p50_ms"], out["serve"]["p99_ms"]))
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(cfg, params, m, min(args.cpu_sample, n))
+        out["cpu_baseline"] = cpu_baseline(cfg, params, m, all_pts=min(args.cpu_sample, n))
     print(json.dumps(out), flush=True)
 
 

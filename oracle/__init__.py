@@ -78,7 +78,7 @@ def _load():
         lib.orc_max_threads.restype = i32
         lib.orc_mix64.restype = u64
         lib.orc_mix64.argtypes = [u64]
-        lib.orc_pair_scan.argtypes = [i64, pd, pd, d, pi32, C.POINTER(C.c_uint64), i32, pi64]
+        lib.orc_pair_scan.argtypes = [i64, pd, pd, d, pi32, C.POINTER(C.c_uint64), i32, pi64, pd]
         _lib = lib
         return lib
 
@@ -220,10 +220,11 @@ def mix64(z: int) -> int:
     return int(_load().orc_mix64(z & 0xFFFFFFFFFFFFFFFF))
 
 
-def pair_scan(r, theta, R, nthreads: int = 0):
+def pair_scan(r, theta, R, nthreads: int = 0, timing: bool = False):
     """Every pair i < j tested once, nothing stored: returns (deg, fp_sum,
     fp_xor, quad_fallbacks, ties), the fingerprint being the wrapping sum and
-    the xor of mix64(i * 2^32 + j) over the edges."""
+    the xor of mix64(i * 2^32 + j) over the edges; with timing=True also the
+    wall time of the pair loop alone, in seconds."""
     lib = _load()
     r = np.ascontiguousarray(r, dtype=np.float64)
     theta = np.ascontiguousarray(theta, dtype=np.float64)
@@ -231,9 +232,11 @@ def pair_scan(r, theta, R, nthreads: int = 0):
     deg = np.zeros(n, dtype=np.int32)
     fp = np.zeros(2, dtype=np.uint64)
     st = np.zeros(2, dtype=np.int64)
+    loop = np.zeros(1, dtype=np.float64)
     lib.orc_pair_scan(n, _p(r, C.c_double), _p(theta, C.c_double), R, _p(deg, C.c_int32),
-                      _p(fp, C.c_uint64), nthreads, _p(st, C.c_int64))
-    return deg, int(fp[0]), int(fp[1]), int(st[0]), int(st[1])
+                      _p(fp, C.c_uint64), nthreads, _p(st, C.c_int64), _p(loop, C.c_double))
+    out = (deg, int(fp[0]), int(fp[1]), int(st[0]), int(st[1]))
+    return out + (float(loop[0]),) if timing else out
 
 
 def generate(n: int, kbar: float, gamma: float, seed: int, nthreads: int = 0):

@@ -411,7 +411,7 @@ static uint64_t mix64(uint64_t z)
 uint64_t orc_mix64(uint64_t z) { return mix64(z); }
 
 void orc_pair_scan(int64_t n, const double *r, const double *theta, double R, int32_t *deg,
-                   uint64_t fp[2], int nthreads, int64_t stats[2])
+                   uint64_t fp[2], int nthreads, int64_t stats[2], double *loop_s)
 {
     double coshR = orc_cosh(R);
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -422,6 +422,7 @@ void orc_pair_scan(int64_t n, const double *r, const double *theta, double R, in
     int64_t q = 0, t = 0;
     #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; ++j) sh[j] = sinh(r[j]);
+    const double t0 = omp_get_wtime();
     #pragma omp parallel num_threads(T) reduction(+:q,t,fsum) reduction(^:fxor)
     {
         int32_t *d = part + (size_t)omp_get_thread_num() * (size_t)n;
@@ -438,6 +439,7 @@ void orc_pair_scan(int64_t n, const double *r, const double *theta, double R, in
                 }
         q += st.quad; t += st.ties;
     }
+    if (loop_s) *loop_s = omp_get_wtime() - t0;  /* the pair loop alone */
     for (int64_t i = 0; i < n; ++i) {
         int32_t c = 0;
         for (int th = 0; th < T; ++th) c += part[(size_t)th * (size_t)n + i];

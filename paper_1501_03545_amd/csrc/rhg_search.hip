@@ -1237,11 +1237,16 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     plan_ps.end();
     const dim3 g((unsigned)(A.heavy_blocks + (n + 255) / 256)), b(256);
     // the EXACT kernels, when they only stand by for an overflowed list,
-    // run on a smaller grid (their light part strides)
-    const dim3 gx((unsigned)(A.heavy_blocks + std::min<int64_t>((n + 255) / 256, 4096)));
+    // run on a smaller grid (a smaller heavy pool; the light part strides)
+    SearchArgs Ax = A;
+    Ax.heavy_blocks = std::min(A.heavy_blocks, 256);
+    const dim3 gx((unsigned)(Ax.heavy_blocks + std::min<int64_t>((n + 255) / 256, 1024)));
     // with no FP32 screen (or on request) every undecided pair is decided
     // in place: the EXACT kernels alone
     const bool exact_only = !A.use_p32 || L.exact_inline;
+    if (!emit && !exact_only && A.hmask >= 0)
+        hipLaunchKernelGGL(zero_i64, dim3((unsigned)((A.hmask + 256) / 256)), dim3(256), 0, s, (int64_t *)A.hset,
+                           A.hmask + 1);
     {
         PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
         if (exact_only) {
@@ -1250,9 +1255,6 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         } else if (emit) {
             hipLaunchKernelGGL((search_kernel<M_EMIT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
         } else {
-            if (A.hmask >= 0)
-                hipLaunchKernelGGL(zero_i64, dim3((unsigned)((A.hmask + 256) / 256)), dim3(256), 0, s, (int64_t *)A.hset,
-                                   A.hmask + 1);
             hipLaunchKernelGGL((search_kernel<M_COUNT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
         }
     }
@@ -1261,9 +1263,9 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         PhaseScope ps(RHG_PHASE_PLAN, s);
         if (!emit) {
             hipLaunchKernelGGL(resolve_kernel, dim3(256), dim3(256), 0, s, A, row_ptr);
-            hipLaunchKernelGGL((search_kernel<M_COUNT, true>), gx, b, 0, s, A, row_ptr, col_idx, 1);
+            hipLaunchKernelGGL((search_kernel<M_COUNT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
         } else {
-            hipLaunchKernelGGL((search_kernel<M_EMIT, true>), gx, b, 0, s, A, row_ptr, col_idx, 1);
+            hipLaunchKernelGGL((search_kernel<M_EMIT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -249,29 +249,40 @@ def run_batch(count, reps, tuned=True, n_streams=64):
             "speedup_vs_plain_loop": t_loop / t_batch, "overflow_refills": len(fixed), "reps": reps}
 
 
-def run_serve(duration_s, rate_hz=200.0, slots=16, budget=200e9, hold_s=1.0):
-    """The serving workload: Poisson arrivals, admission by memory budget and
-    free slot, results held on the device for hold_s."""
+def run_serve(duration_s, rate_hz=200.0, slots=16, budget=200e9, hold_s=1.0, saturate=3000):
+    """The serving workload on the library's own server (rhg_server_*:
+    admission by its device arena, slots, device-resident results): Poisson
+    arrivals at rate_hz for duration_s, results released hold_s after they
+    complete.  Then the capacity run: the first `saturate` requests of the
+    same stream all queued at once (each released as it completes), against
+    the plain per-graph loop over the same requests."""
     import torch
+    import paper_1501_03545_amd as P
     from paper_1501_03545_amd import autotune as A
     from paper_1501_03545_amd import serve as S
     from paper_1501_03545_amd import workloads as W
 
-    warm = S.GpuExecutor(slots=slots, tuning_fn=A.tuning_for)
-    S.Server(warm, slots=slots, budget_bytes=budget, hold_s=0.0).run(
-        W.serve_stream(duration_s=0.5, rate_hz=rate_hz, seed=99))
-    torch.cuda.synchronize()
+    srv = P.RhgServer(budget_bytes=int(budget), slots=slots)
+    S.run_native(srv, W.serve_stream(duration_s=0.5, rate_hz=rate_hz, seed=99), hold_s=0.0, tuning_fn=A.tuning_for)
     stream = W.serve_stream(duration_s=duration_s, rate_hz=rate_hz, seed=5)
-    ex = S.GpuExecutor(slots=slots, tuning_fn=A.tuning_for)
-    srv = S.Server(ex, slots=slots, budget_bytes=budget, hold_s=hold_s)
-    st = srv.run(stream)
-    torch.cuda.synchronize()
+    st, _ = S.run_native(srv, stream, hold_s=hold_s, tuning_fn=A.tuning_for)
     offered = sum(p["n"] * p["avg_degree"] / 2 for _, p in stream) / duration_s
     st.update({"workload": "Poisson arrivals at %g req/s for %g s: 98%% drawn like the batch, 2%% at "
                            "n=1e7 avg degree 16 gamma 2.5" % (rate_hz, duration_s),
-               "budget_bytes": budget, "hold_s": hold_s, "offered_edges_per_s": offered,
-               "overflow_refills": ex.retries})
-    return st
+               "form": "rhg_server_* (native admission, %d slots, a %g GB device arena)" % (slots, budget / 1e9),
+               "budget_bytes": budget, "hold_s": hold_s, "offered_edges_per_s": offered})
+    burst = [(0.0, p) for _, p in stream[:saturate]]
+    sat, _ = S.run_native(srv, burst, hold_s=0.0, tuning_fn=A.tuning_for)
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    edges, wall = S.run_plain_loop(burst)
+    torch.cuda.empty_cache()
+    sat.update({"workload": "the first %d requests of the stream above, all queued at once" % len(burst)})
+    capacity = {"served": sat, "plain_loop": {"edges": edges, "wall_s": wall, "edges_per_s": edges / wall,
+                                              "form": "rhg_generate_async per request, one stream"},
+                "speedup_vs_plain_loop": sat["edges_per_s"] / (edges / wall)}
+    return st, capacity
 
 
 def copy_calibration(nbytes=4 << 30, reps=5):
@@ -351,7 +362,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=512, help="graphs in the batch workload (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=3)
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the serving run (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving run (0: skip)")
     ap.add_argument("--band-width", type=float, default=0.0)
     ap.add_argument("--cell-target", type=int, default=0)
     args = ap.parse_args()
@@ -443,8 +454,10 @@ def main():
                                                                   out["batch"]["plain_loop"]["ms"]))
     if args.serve_seconds > 0:
         _log("serving for %g s" % args.serve_seconds)
-        out["serve"] = run_serve(args.serve_seconds)
-        _log("serve done: p50 %.2f ms p99 %.2f ms" % (out["serve"]["p50_ms"], out["serve"]["p99_ms"]))
+        out["serve"], out["serve_capacity"] = run_serve(args.serve_seconds)
+        _log("serve done: p50 %.2f ms p99 %.2f ms; saturated %.3g edges/s vs plain loop %.3g" % (
+            out["serve"]["p50_ms"], out["serve"]["p99_ms"], out["serve_capacity"]["served"]["edges_per_s"],
+            out["serve_capacity"]["plain_loop"]["edges_per_s"]))
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, params, m, all_pts=min(args.cpu_sample, n))

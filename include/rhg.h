@@ -49,7 +49,8 @@ typedef enum {
     RHG_ECAPACITY = 3,  /* an output buffer is smaller than required         */
     RHG_EDEVICE = 4,    /* a HIP runtime call failed                         */
     RHG_ENOROOT = 5,    /* Eq. (22) has no radius for the requested degree   */
-    RHG_EINTERNAL = 6   /* a device-side consistency check failed            */
+    RHG_EINTERNAL = 6,  /* a device-side consistency check failed            */
+    RHG_EBUSY = 7       /* the object is still in use (a running request)    */
 } rhg_status;
 
 /* Parameters of one graph.  Filled by rhg_plan / rhg_plan_radius; the
@@ -430,6 +431,74 @@ rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *t
 rhg_status rhg_batch_launch(rhg_batch *b, void *stream);
 
 void rhg_batch_destroy(rhg_batch *b);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of generation requests on one GPU.     */
+/* ------------------------------------------------------------------ */
+
+/* A request server.  Requests (n, avg_degree, gamma, seed; planned as in
+ * rhg_plan) are queued first come, first served; the head is admitted as
+ * soon as one of `slots` HIP streams is free and its device memory fits in
+ * the server's arena beside what admitted and unreleased requests hold.
+ * Each admitted request runs the whole pipeline of rhg_generate_async on its
+ * own stream, so requests that arrive while others run overlap with them on
+ * the device.  The arena (budget_bytes of device memory) is allocated once,
+ * at creation, and handed out on the host: admission allocates nothing.  A
+ * request holds (r, theta), row_ptr and col_idx slots for its target degree
+ * times n (with a 1.3 slack) until it is released, and its index workspace
+ * until it completes; a graph with more edges than its slots is run again
+ * into exactly 2m slots before it completes.  The server is the natural
+ * boundary of the paper's generator (Algorithm 1) put behind a request
+ * queue; it is single-threaded: calls on one server must not overlap.
+ * Errors (create): RHG_EINVAL for slots outside 1 .. 64 or a budget below
+ * 1 MiB; RHG_ENOMEM when the arena cannot be allocated. */
+typedef struct rhg_server rhg_server;  /* opaque, host-side handle */
+
+typedef struct {
+    int64_t req_id;
+    rhg_status status;        /* RHG_OK, or the error that ended the request  */
+    int32_t reserved;
+    int64_t n;
+    int64_t nnz;              /* 2m                                           */
+    const int64_t *row_ptr;   /* device, n + 1 (valid until released)          */
+    const int32_t *col_idx;   /* device, nnz                                   */
+    const double *r;          /* device, n: the sampled points                 */
+    const double *theta;
+    double latency_ms;        /* from submission to completion seen by a poll  */
+    rhg_params params;
+} rhg_completion;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected, refills;
+    int64_t edges;            /* undirected edges of the completed requests   */
+    int64_t max_inflight, max_reserved_bytes;
+    int64_t reserved_bytes, inflight, queued;  /* now                         */
+} rhg_server_stats;
+
+rhg_status rhg_server_create(size_t budget_bytes, int slots, rhg_server **out /* host */);
+
+/* Plans and queues a request, then admits what fits.  req_id: the caller's
+ * key (unique among unreleased requests).  Errors: those of rhg_plan;
+ * RHG_EINVAL for an id in use; RHG_ECAPACITY when the request could not fit
+ * even into the empty arena (it is not queued). */
+rhg_status rhg_server_submit(rhg_server *s, int64_t req_id, int64_t n, double avg_degree, double gamma,
+                             uint64_t seed, const rhg_tuning *t /* host, may be NULL */);
+
+/* Collects the requests whose work has finished (by querying their events;
+ * no blocking), admits queued requests into the freed slots and memory, and
+ * writes up to cap completions to out (host) with their count in *count
+ * (the rest come with the next polls). */
+rhg_status rhg_server_poll(rhg_server *s, rhg_completion *out /* host */, int cap, int *count /* host */);
+
+/* Returns a completed request's memory to the arena (or withdraws a queued
+ * one).  Errors: RHG_EINVAL for an unknown id; RHG_EBUSY while it runs or
+ * before a poll has handed out its completion. */
+rhg_status rhg_server_release(rhg_server *s, int64_t req_id);
+
+rhg_status rhg_server_get_stats(rhg_server *s, rhg_server_stats *out /* host */);
+
+/* Waits for the server's streams and frees everything it holds. */
+void rhg_server_destroy(rhg_server *s);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *rhg_last_error(void);

@@ -16,9 +16,9 @@ from typing import Optional
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librhg.so")
 
-RHG_OK, RHG_EINVAL, RHG_ENOMEM, RHG_ECAPACITY, RHG_EDEVICE, RHG_ENOROOT, RHG_EINTERNAL = range(7)
+RHG_OK, RHG_EINVAL, RHG_ENOMEM, RHG_ECAPACITY, RHG_EDEVICE, RHG_ENOROOT, RHG_EINTERNAL, RHG_EBUSY = range(8)
 _STATUS = {0: "RHG_OK", 1: "RHG_EINVAL", 2: "RHG_ENOMEM", 3: "RHG_ECAPACITY", 4: "RHG_EDEVICE",
-           5: "RHG_ENOROOT", 6: "RHG_EINTERNAL"}
+           5: "RHG_ENOROOT", 6: "RHG_EINTERNAL", 7: "RHG_EBUSY"}
 
 
 class RhgError(RuntimeError):
@@ -53,6 +53,18 @@ class rhg_graph_summary(C.Structure):
                 ("assortativity", C.c_double), ("triads", C.c_int64), ("triangles", C.c_int64),
                 ("transitivity", C.c_double), ("avg_local_clustering", C.c_double),
                 ("ascending_rows", C.c_int32), ("reserved", C.c_int32)]
+
+
+class rhg_completion(C.Structure):
+    _fields_ = [("req_id", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64),
+                ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("r", C.c_void_p),
+                ("theta", C.c_void_p), ("latency_ms", C.c_double), ("params", rhg_params)]
+
+
+class rhg_server_stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "failed", "rejected", "refills", "edges",
+                                         "max_inflight", "max_reserved_bytes", "reserved_bytes", "inflight",
+                                         "queued")]
 
 
 class rhg_csr(C.Structure):
@@ -100,6 +112,12 @@ def load():
         "rhg_generate": (i32, [i64, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
         "rhg_generate_async": (i32, [P(rhg_params), P(rhg_tuning), vp, vp, vp, C.c_size_t, vp, vp, i64, vp, vp]),
         "rhg_generate_async_noalloc": (i32, [P(rhg_params), P(rhg_tuning), vp, vp, vp, vp, i64, vp, vp]),
+        "rhg_server_create": (i32, [C.c_size_t, i32, P(vp)]),
+        "rhg_server_submit": (i32, [vp, i64, i64, C.c_double, C.c_double, C.c_uint64, P(rhg_tuning)]),
+        "rhg_server_poll": (i32, [vp, P(rhg_completion), i32, P(i32)]),
+        "rhg_server_release": (i32, [vp, i64]),
+        "rhg_server_get_stats": (i32, [vp, P(rhg_server_stats)]),
+        "rhg_server_destroy": (None, [vp]),
         "rhg_batch_create": (i32, [i32, P(rhg_params), P(rhg_tuning), P(vp), P(vp), P(vp), P(C.c_size_t), P(vp),
                                    P(vp), P(i64), vp, i32, P(vp)]),
         "rhg_batch_launch": (i32, [vp, vp]),
@@ -392,6 +410,78 @@ def rhg_generate_async_noalloc(p: rhg_params, r, theta, row_ptr, col_idx, overfl
                                              _ptr(col_idx), col_idx.numel(), _ptr(overflow), _stream(stream)))
 
 
+class DeviceView:
+    """A device array owned by the library, seen as a torch tensor (no copy)."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr, "data": (int(ptr or 0), False),
+                                         "version": 3, "strides": None}
+
+
+def _view(ptr, n, typestr):
+    import torch
+    if n <= 0 or not ptr:
+        dt = {"<i8": torch.int64, "<i4": torch.int32, "<f8": torch.float64}[typestr]
+        return torch.empty(0, dtype=dt, device="cuda")
+    return torch.as_tensor(DeviceView(ptr, n, typestr), device="cuda")
+
+
+class RhgServer:
+    """The library's request server (rhg_server_*): continuous batching with
+    its own device arena and streams.  submit() queues a request, poll()
+    collects finished ones (as dicts holding device views of the CSR, valid
+    until release())."""
+
+    def __init__(self, budget_bytes: int, slots: int = 16):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.rhg_server_create(int(budget_bytes), int(slots), C.byref(h)))
+        self._h = h
+        self._buf = (rhg_completion * 64)()
+
+    def submit(self, req_id: int, n: int, avg_degree: float, gamma: float, seed: int, tuning=None):
+        _check(load().rhg_server_submit(self._h, int(req_id), int(n), float(avg_degree), float(gamma), int(seed),
+                                        _tuning(tuning)))
+
+    def poll(self):
+        lib = load()
+        out = []
+        while True:
+            cnt = C.c_int(0)
+            _check(lib.rhg_server_poll(self._h, self._buf, len(self._buf), C.byref(cnt)))
+            for i in range(cnt.value):
+                c = self._buf[i]
+                d = {"req_id": c.req_id, "status": c.status, "n": c.n, "nnz": c.nnz,
+                     "latency_ms": c.latency_ms, "params": rhg_params.from_buffer_copy(c.params)}
+                if c.status == RHG_OK:
+                    d["row_ptr"] = _view(c.row_ptr, c.n + 1, "<i8")
+                    d["col_idx"] = _view(c.col_idx, c.nnz, "<i4")
+                    d["r"] = _view(c.r, c.n, "<f8")
+                    d["theta"] = _view(c.theta, c.n, "<f8")
+                out.append(d)
+            if cnt.value < len(self._buf):
+                return out
+
+    def release(self, req_id: int):
+        _check(load().rhg_server_release(self._h, int(req_id)))
+
+    def stats(self) -> dict:
+        st = rhg_server_stats()
+        _check(load().rhg_server_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in rhg_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            load().rhg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def expected_col_capacity(p: rhg_params, slack: float = 1.3) -> int:
     """int32 slots to reserve for col_idx before counting: 2m in expectation
     (the target degree times n), with slack for the spread of the degree."""
@@ -491,6 +581,6 @@ __all__ = ["rhg_plan", "rhg_plan_radius", "rhg_sample_points", "rhg_index_worksp
            "long_range_count", "rhg_graph_stats", "rhg_graph_stats_workspace_bytes", "rhg_index_stats",
            "rhg_generate",
            "rhg_set_profiling", "rhg_phase_times", "rhg_generate_async", "rhg_generate_async_noalloc",
-           "GraphBuffers", "Batch",
+           "GraphBuffers", "Batch", "RhgServer",
            "expected_col_capacity", "RhgError", "Graph", "Index", "load", "version",
            "LIB_PATH", "PHASES"]

@@ -285,3 +285,104 @@ class SimExecutor:
         if next_event is not None and next_event > self.clock:
             ev.append(next_event)
         self.clock = min(ev) if ev else self.clock + sleep_s
+
+
+def run_native(server, stream, hold_s: float = 1.0, keep=(), poll_sleep: float = 2e-5, tuning_fn=None):
+    """Drives the library's own server (RhgServer: admission, slots and
+    device memory in native code) with a timed arrival stream: each request
+    is submitted at its arrival time, completions are polled, and results are
+    released hold_s after they completed (those in `keep` are handed back
+    instead, as the completion dicts, for the caller to release).  Latency
+    runs from arrival to the poll that saw the completion.  stream: list of
+    (arrival time in s, params dict), sorted by time; arrival 0 for all gives
+    the saturated server.  Returns (statistics, kept completions)."""
+    import paper_1501_03545_amd as P
+    keep = set(keep)
+    pending = collections.deque(enumerate(stream))
+    arrival = {}
+    holding = []
+    lat, kept = [], {}
+    edges = 0
+    rejected = failed = 0
+    t0 = time.perf_counter()
+    busy_area, last = 0.0, t0
+    outstanding = 0
+    while pending or outstanding:
+        now = time.perf_counter()
+        st = server.stats()
+        busy_area += st["inflight"] * (now - last)
+        last = now
+        while pending and pending[0][1][0] <= now - t0:
+            rid, (t, p) = pending.popleft()
+            tun = tuning_fn(p["n"], p["avg_degree"], p["gamma"]) if tuning_fn else None
+            try:
+                server.submit(rid, p["n"], p["avg_degree"], p["gamma"], p["seed"], tun)
+            except P.RhgError as e:
+                if e.status != P.RHG_ECAPACITY:
+                    raise
+                rejected += 1
+                continue
+            arrival[rid] = t0 + t
+            outstanding += 1
+        for c in server.poll():
+            rid = c["req_id"]
+            done = time.perf_counter()
+            outstanding -= 1
+            if c["status"] != P.RHG_OK:
+                failed += 1
+                server.release(rid)
+                continue
+            lat.append(done - arrival.pop(rid))
+            edges += c["nnz"] // 2
+            if rid in keep:
+                kept[rid] = c
+            else:
+                heapq.heappush(holding, (done + hold_s, rid))
+        now = time.perf_counter()
+        while holding and holding[0][0] <= now:
+            server.release(heapq.heappop(holding)[1])
+        if poll_sleep > 0 and (pending or outstanding):
+            time.sleep(poll_sleep)
+    wall = time.perf_counter() - t0
+    while holding:
+        server.release(heapq.heappop(holding)[1])
+    lat.sort()
+
+    def q(f):
+        return lat[min(len(lat) - 1, max(0, int(math.ceil(f * len(lat))) - 1))] * 1e3 if lat else float("nan")
+
+    st = server.stats()
+    return ({"requests": len(lat), "rejected": rejected, "failed": failed, "wall_s": wall,
+             "p50_ms": q(0.50), "p99_ms": q(0.99), "mean_ms": (sum(lat) / len(lat) * 1e3) if lat else float("nan"),
+             "edges": edges, "edges_per_s": edges / wall if wall > 0 else 0.0,
+             "max_reserved_bytes": st["max_reserved_bytes"], "max_inflight": st["max_inflight"],
+             "mean_inflight": busy_area / wall if wall > 0 else 0.0, "refills": st["refills"]}, kept)
+
+
+def run_plain_loop(stream, device="cuda"):
+    """The same requests as a plain loop: one graph after another on one
+    stream (rhg_generate_async into freshly allocated buffers, a graph whose
+    edges overflow its slots run again into exactly 2m), each result freed
+    once the next graph is queued.  Returns (edges, wall seconds)."""
+    import torch
+    import paper_1501_03545_amd as P
+    s = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edges = 0
+    flags = []
+    for i, (_, p) in enumerate(stream):
+        params = P.rhg_plan(p["n"], p["avg_degree"], p["gamma"], p["seed"])
+        b = P.GraphBuffers(params, device=device)
+        flag = torch.zeros(1, dtype=torch.int32, device=device)
+        P.rhg_generate_async(params, b.r, b.theta, b.ws, b.row_ptr, b.col, flag, None, s)
+        flags.append((flag, b.row_ptr[-1:], params))
+    torch.cuda.synchronize()
+    for flag, tail, params in flags:
+        if int(flag.item()):  # rare: run again with exact capacity
+            b = P.GraphBuffers(params, col_capacity=int(tail.item()), device=device)
+            f2 = torch.zeros(1, dtype=torch.int32, device=device)
+            P.rhg_generate_async(params, b.r, b.theta, b.ws, b.row_ptr, b.col, f2, None, s)
+        edges += int(tail.item()) // 2
+    torch.cuda.synchronize()
+    return edges, time.perf_counter() - t0

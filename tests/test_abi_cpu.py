@@ -155,6 +155,7 @@ def _header_structs():
             decl = decl.strip()
             if not decl:
                 continue
+            decl = re.sub(r"^const\s+", "", decl)
             ty, rest = re.match(r"(\w+)\s+(.*)", decl).groups()
             for item in rest.split(","):
                 m = re.match(r"(\*?)\s*(\w+)(?:\[(\d+)\])?$", item.strip())
@@ -166,9 +167,11 @@ def _header_structs():
 def test_binding_structs_match_the_header():
     """Every struct the binding mirrors has the header's fields, in order, with
     the same sizes (so the same offsets under natural alignment)."""
-    scalar = {"int64_t": C.c_int64, "uint64_t": C.c_uint64, "int32_t": C.c_int32, "double": C.c_double}
+    scalar = {"int64_t": C.c_int64, "uint64_t": C.c_uint64, "int32_t": C.c_int32, "double": C.c_double,
+              "rhg_status": C.c_int32}
     hs = _header_structs()
-    for name in ("rhg_params", "rhg_tuning", "rhg_stats", "rhg_graph_summary", "rhg_csr"):
+    for name in ("rhg_params", "rhg_tuning", "rhg_stats", "rhg_graph_summary", "rhg_csr", "rhg_completion",
+                 "rhg_server_stats"):
         cls = getattr(P, name)
         assert [f[0] for f in cls._fields_] == [h[0] for h in hs[name]], name
         for (fname, ftype), (_, hty, ptr, cnt) in zip(cls._fields_, hs[name]):

@@ -83,3 +83,72 @@ def test_poisson_stream_and_memory_budget():
     assert st["edges"] > 0
     for rid in (0, 1, 2):
         assert _same(srv.kept[rid], _alone(stream[rid][1]))
+
+
+class _Done:
+    """A native server completion seen like GraphBuffers."""
+
+    def __init__(self, c):
+        self.params = c["params"]
+        self.r, self.theta, self.row_ptr, self.col = c["r"], c["theta"], c["row_ptr"], c["col_idx"]
+
+    def graph(self):
+        return P.Graph(params=self.params, row_ptr=self.row_ptr, col_idx=self.col, r=self.r, theta=self.theta)
+
+
+def test_native_server_results_equal_alone_and_oracle():
+    """The library's own server (admission, slots and its device arena in
+    native code): a burst of requests that overlap on the device, each result
+    bit for bit the same as the request generated alone, and against the
+    oracle (whole graphs up to n = 20000, sampled rows above)."""
+    import torch
+    P.load()
+    draws = W.batch_params(count=40, seed=23)
+    draws.insert(7, dict(W.SERVE_LARGE, seed=91))
+    stream = [(0.0003 * i, dict(d)) for i, d in enumerate(draws)]
+    srv = P.RhgServer(budget_bytes=int(24e9), slots=16)
+    st, kept = S.run_native(srv, stream, hold_s=0.0, keep=range(len(stream)))
+    _say("native", st)
+    assert st["requests"] == len(stream) and st["rejected"] == 0 and st["failed"] == 0
+    assert st["max_inflight"] >= 8, "requests did not overlap"
+    assert st["max_reserved_bytes"] <= 24e9
+    kinds = []
+    for rid, (_, d) in enumerate(stream):
+        got = _Done(kept[rid])
+        assert _same(got, _alone(d)), (rid, d)
+        kinds.append(oracle_check(O, got.graph(), d))
+        srv.release(rid)
+    _say("oracle checks", {k: kinds.count(k) for k in set(kinds)})
+    assert kinds.count("full") >= 8
+    assert srv.stats()["reserved_bytes"] == 0
+    srv.close()
+    torch.cuda.synchronize()
+
+
+def test_native_server_budget_and_errors():
+    """A budget smaller than the whole mix: requests wait for memory, first
+    come first served, and never hold more than the budget; a request that
+    could not fit even into the empty arena is refused; ids are checked."""
+    P.load()
+    srv = P.RhgServer(budget_bytes=int(2e9), slots=8)
+    with pytest.raises(P.RhgError) as ei:
+        srv.submit(1, 50_000_000, 16.0, 2.5, 1)
+    assert ei.value.status == P.RHG_ECAPACITY
+    stream = [(0.0, d) for d in W.batch_params(count=24, seed=31)]
+    st, _ = S.run_native(srv, stream, hold_s=0.05)
+    _say("budget", st)
+    assert st["requests"] == len(stream) and st["max_reserved_bytes"] <= 2e9
+    srv.submit(5, 5000, 8.0, 2.5, 7)
+    with pytest.raises(P.RhgError) as ei:
+        srv.submit(5, 5000, 8.0, 2.5, 7)
+    assert ei.value.status == P.RHG_EINVAL
+    with pytest.raises(P.RhgError) as ei:
+        srv.release(12345)
+    assert ei.value.status == P.RHG_EINVAL
+    done = []
+    while not done:
+        done = srv.poll()
+    assert done[0]["req_id"] == 5 and done[0]["status"] == P.RHG_OK
+    srv.release(5)
+    assert srv.stats()["reserved_bytes"] == 0
+    srv.close()

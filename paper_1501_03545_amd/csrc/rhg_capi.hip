@@ -546,6 +546,10 @@ struct rhg_batch {
     hipGraph_t graph;
     hipGraphExec_t exec;
     int count, streams;
+    int small_count;           // graphs generated by the persistent small-graph launch
+    void *small_table;         // device: their records
+    unsigned int *small_head;  // device: the launch's work counter
+    unsigned long long *small_stats;  // device: the decisions' counters (not reported)
 };
 
 rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *ts, double *const *r,
@@ -569,8 +573,17 @@ rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *t
         const double k = std::isnan(ps[g].avg_degree) ? 10.0 : ps[g].avg_degree;
         work[g] = (double)ps[g].n * (4.0 + k);
     }
+    // the persistent small-graph launch takes the last stream: charge it
+    // the small graphs' work
+    if (n_streams > 1)
+        for (int g = 0; g < count; ++g)
+            if (ps[g].n >= 0 && ps[g].n <= RHG_SMALL_GRAPH) load[n_streams - 1] += work[g];
     std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
     for (int g : order) {
+        if (ps[g].n >= 0 && ps[g].n <= RHG_SMALL_GRAPH) {
+            owner[g] = n_streams - 1;
+            continue;
+        }
         int best = 0;
         for (int k = 1; k < n_streams; ++k)
             if (load[k] < load[best]) best = k;
@@ -587,15 +600,74 @@ rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *t
     if (!b) return fail(RHG_ENOMEM, "rhg_batch_create: host allocation failed");
     b->count = count;
     b->streams = n_streams;
+    b->graph = nullptr;
+    b->small_count = 0;
+    b->small_table = nullptr;
+    b->small_head = nullptr;
+    b->small_stats = nullptr;
     rhg_status status = RHG_OK;
+    // Small graphs (n <= RHG_SMALL_GRAPH): one persistent launch generates
+    // them all, a workgroup per graph, instead of ~50 launches each.
+    std::vector<char> small_host;
+    std::vector<char> is_small(count, 0);
+    {
+        const size_t rb = small_graph_record_bytes();
+        std::vector<int> small_ids;
+        for (int g = 0; g < count; ++g)
+            if (ps[g].n >= 0 && ps[g].n <= RHG_SMALL_GRAPH && check_params(&ps[g], "rhg_batch_create") == RHG_OK)
+                small_ids.push_back(g);
+        if (!small_ids.empty()) {
+            hipError_t e = hipMalloc(&b->small_stats, ST_COUNT * 8);
+            if (e == hipSuccess) e = hipMemset(b->small_stats, 0, ST_COUNT * 8);
+            if (e == hipSuccess) e = hipMalloc((void **)&b->small_head, 16);
+            if (e != hipSuccess) status = check_hip(e, "rhg_batch_create (small graphs)");
+        }
+        for (int g : small_ids) {
+            if (status != RHG_OK) break;
+            Layout L;
+            make_layout(ps[g], ts ? &ts[g] : nullptr, &L);
+            const size_t off = small_host.size();
+            small_host.resize(off + rb);
+            if (!make_small_graph(ps[g], L, r[g], theta[g], ws[g], ws_bytes[g], row_ptr[g], col[g], col_cap[g],
+                                  overflow + g, b->small_stats, small_host.data() + off)) {
+                status = fail(RHG_ECAPACITY, "rhg_batch_create: workspace of graph " + std::to_string(g) +
+                                                 " smaller than rhg_index_workspace_bytes");
+                break;
+            }
+            is_small[g] = 1;
+            ++b->small_count;
+        }
+        if (status == RHG_OK && b->small_count) {
+            hipError_t e = hipMalloc(&b->small_table, small_host.size());
+            if (e == hipSuccess) e = hipMemcpy(b->small_table, small_host.data(), small_host.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) status = check_hip(e, "rhg_batch_create (small graphs)");
+        }
+        if (status != RHG_OK) {
+            if (b->small_table) (void)hipFree(b->small_table);
+            if (b->small_head) (void)hipFree(b->small_head);
+            if (b->small_stats) (void)hipFree(b->small_stats);
+            for (int k = 0; k <= n_streams; ++k) (void)hipEventDestroy(ev[k]);
+            for (int k = 0; k < n_streams; ++k) (void)hipStreamDestroy(st[k]);
+            (void)hipStreamDestroy(origin);
+            delete b;
+            return status;
+        }
+    }
     const int prof = g_prof_on;
     g_prof_on = 0;  // no event records inside the captured graph
     hipError_t e = hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
         (void)hipEventRecord(ev[n_streams], origin);
         for (int k = 0; k < n_streams; ++k) (void)hipStreamWaitEvent(st[k], ev[n_streams], 0);
+        // the persistent launch of the small graphs on a stream of its own
+        // (the least loaded one), beside the large graphs' pipelines
+        if (b->small_count) {
+            const hipError_t e2 = launch_small_batch(b->small_table, b->small_count, b->small_head, st[n_streams - 1]);
+            if (e2 != hipSuccess) status = check_hip(e2, "rhg_batch_create (small graphs)");
+        }
         for (int g : order) {
             if (status != RHG_OK) break;
+            if (is_small[g]) continue;
             status = rhg_generate_async(&ps[g], ts ? &ts[g] : nullptr, r[g], theta[g], ws[g], ws_bytes[g], row_ptr[g],
                                         col[g], col_cap[g], overflow + g, st[owner[g]]);
         }
@@ -620,6 +692,9 @@ rhg_status rhg_batch_create(int count, const rhg_params *ps, const rhg_tuning *t
     (void)hipStreamDestroy(origin);
     if (status != RHG_OK) {
         if (b->graph) (void)hipGraphDestroy(b->graph);
+        if (b->small_table) (void)hipFree(b->small_table);
+        if (b->small_head) (void)hipFree(b->small_head);
+        if (b->small_stats) (void)hipFree(b->small_stats);
         delete b;
         return status;
     }
@@ -640,6 +715,9 @@ void rhg_batch_destroy(rhg_batch *b)
     if (!b) return;
     (void)hipGraphExecDestroy(b->exec);
     (void)hipGraphDestroy(b->graph);
+    if (b->small_table) (void)hipFree(b->small_table);
+    if (b->small_head) (void)hipFree(b->small_head);
+    if (b->small_stats) (void)hipFree(b->small_stats);
     delete b;
 }
 

@@ -15,6 +15,7 @@
 #define RHG_HEAVY_EXTRA_CHUNKS (1 << 20)
 #define RHG_KAP_SUB 4             // sub-intervals per band of the entry estimate
 #define RHG_ROWS_TILE 8192        // LDS tile (entries) of the row sort
+#define RHG_SMALL_GRAPH 16384     // a batch's graphs of at most this many points share one persistent launch
 
 namespace rhg {
 
@@ -175,6 +176,15 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
                               uint32_t *v0, uint32_t *v1, int validate, hipStream_t s);
 hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
                          int64_t col_cap = -1, int32_t *overflow = nullptr);
+
+// The batch's small graphs: a device record per graph, filled on the host by
+// make_small_graph (false: workspace too small), and one persistent launch
+// over all of them (a device counter `head` hands out the graphs).
+size_t small_graph_record_bytes();
+bool make_small_graph(const rhg_params &p, const Layout &L, double *r, double *theta, void *ws, size_t ws_bytes,
+                      int64_t *row_ptr, int32_t *col, int64_t col_cap, int32_t *overflow,
+                      unsigned long long *stats, void *out);
+hipError_t launch_small_batch(const void *table, int count, unsigned int *head, hipStream_t s);
 
 // Row sort (ascending rows, in place).  aux: rows_aux_bytes(lcap, mapcap)
 // bytes holding counters, up to lcap rows longer than RHG_ROWS_TILE and the

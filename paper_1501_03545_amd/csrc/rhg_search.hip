@@ -44,6 +44,7 @@
 #include <algorithm>
 
 #include "rhg_internal.h"
+#include "rhg_sample.h"
 
 namespace rhg {
 
@@ -1239,8 +1240,8 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     // the EXACT kernels, when they only stand by for an overflowed list,
     // run on a smaller grid (a smaller heavy pool; the light part strides)
     SearchArgs Ax = A;
-    Ax.heavy_blocks = std::min(A.heavy_blocks, 256);
-    const dim3 gx((unsigned)(Ax.heavy_blocks + std::min<int64_t>((n + 255) / 256, 1024)));
+    Ax.heavy_blocks = std::min(A.heavy_blocks, 64);
+    const dim3 gx((unsigned)(Ax.heavy_blocks + std::min<int64_t>((n + 255) / 256, 64)));
     // with no FP32 screen (or on request) every undecided pair is decided
     // in place: the EXACT kernels alone
     const bool exact_only = !A.use_p32 || L.exact_inline;
@@ -1281,6 +1282,412 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         e = hipGetLastError();
     }
     return e;
+}
+
+
+// ------------------------------------------------------------ small graphs
+//
+// A batch's small graphs (n <= RHG_SMALL_GRAPH) are generated by one
+// persistent launch: each workgroup takes the next graph from a device
+// counter and runs its whole pipeline -- sample, sort, index, count, scan,
+// emit -- alone, with workgroup barriers between the steps, so a small
+// graph costs no kernel launches of its own.  The composite keys
+// (sort key, id) of up to RHG_SMALL_GRAPH points are sorted in LDS by a
+// bitonic network (unique keys, so the order is deterministic); the band
+// windows are found by binary search on the sorted keys; each wavefront
+// takes one query at a time and its lanes test the candidates 64 at a
+// time, with the exact stages decided in place.  Rows hold the inside bands,
+// then each band's window in position order.
+
+struct SmallGraph {
+    SearchArgs A;                 // bands, constants and the sorted arrays below
+    int64_t n;
+    uint32_t k0, k1;              // Philox key
+    double alpha, cam1, cam1_lo;  // cosh(alpha R) - 1 as double-double
+    double *r, *theta;
+    int64_t *row_ptr;
+    int32_t *col;
+    int64_t col_cap;
+    int32_t *overflow;
+    uint32_t *keys;
+    double inv, sc;               // 1 / sqrt(2 cosh R), sqrt(2 / cosh R)
+};
+
+constexpr int SMALL_THREADS = 1024;
+
+__device__ __forceinline__ int small_band_of(const SearchArgs &A, double r)
+{
+    int lo = 0, hi = A.B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.E[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One query (sorted position q) by one wavefront: count or emit its row.
+template <int MODE>
+__device__ void small_query(const SmallGraph &S, int64_t q, const uint64_t *skey, const int32_t *bstart,
+                            int *mismatch)
+{
+    constexpr bool EMIT = MODE == M_EMIT;
+    const SearchArgs &A = S.A;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const double rq = A.sr[q], tq = A.st[q];
+    const float4 fq = A.rec[q];
+    const int32_t id = __float_as_int(fq.w);
+    int J = 0;
+    while (J < A.B && band_inside(A, rq, J)) ++J;
+    int64_t cnt = 0, base = 0, lim = 0;
+    if (EMIT) {
+        base = S.row_ptr[id];
+        lim = S.row_ptr[id + 1] - base;
+    }
+    // inside bands, without tests
+    {
+        const int64_t s0 = bstart[0], e0 = bstart[J];
+        if (EMIT) {
+            for (int64_t c0 = s0; c0 < e0; c0 += 64) {
+                const int64_t c = c0 + lane;
+                const bool valid = c < e0 && c != q;
+                const uint64_t bal = __ballot(valid);
+                if (valid) {
+                    const int64_t o = cnt + __popcll(bal & lt);
+                    if (o < lim) S.col[base + o] = (int32_t)(skey[c] & 0xffffffffull);
+                }
+                cnt += __popcll(bal);
+            }
+        } else {
+            cnt = (e0 - s0) - ((q >= s0 && q < e0) ? 1 : 0);
+        }
+    }
+    // first position in [s, e) whose sort key is at least k (or above k)
+    auto lower = [&](int64_t s, int64_t e, uint32_t k, bool above) {
+        while (s < e) {
+            const int64_t mid = (s + e) >> 1;
+            const uint32_t km = (uint32_t)(skey[mid] >> 32);
+            if (above ? km <= k : km < k) s = mid + 1;
+            else e = mid;
+        }
+        return s;
+    };
+    for (int j = J; j < A.B; ++j) {
+        const int64_t s = bstart[j], e = bstart[j + 1];
+        if (s == e) continue;
+        const double w = window_w(A, fq.x, fq.y, fq.z, j);
+        const bool fp = !(w < 0x1p-5);
+        int64_t ra[3], rb[3];
+        int nr = 0;
+        if (!(w < 3.0)) {
+            ra[0] = s; rb[0] = e; nr = 1;
+        } else {
+            const double lo = tq - w, hi = tq + w;
+            if (hi >= RHG_TWO_PI_D) {
+                ra[nr] = s; rb[nr] = lower(s, e, band_key(A, j, hi - RHG_TWO_PI_D), true); ++nr;
+            }
+            ra[nr] = lower(s, e, band_key(A, j, fmax(lo, 0.0)), false);
+            rb[nr] = lower(s, e, band_key(A, j, fmin(hi, RHG_TWO_PI_D)), true);
+            ++nr;
+            if (lo < 0.0) {
+                ra[nr] = lower(s, e, band_key(A, j, lo + RHG_TWO_PI_D), false); rb[nr] = e; ++nr;
+            }
+        }
+        for (int k = 0; k < nr; ++k) {
+            for (int64_t c0 = ra[k]; c0 < rb[k]; c0 += 64) {
+                const int64_t c = c0 + lane;
+                int acc = 0;
+                if (c < rb[k] && c != q) {
+                    const double tc = A.st[c];
+                    if (!(short_angle(tq, tc) > w)) {
+                        const float4 fc = A.rec[c];
+                        acc = decide<MODE, true>(A, q, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp, -1);
+                    }
+                }
+                const uint64_t bal = __ballot(acc);
+                if (EMIT && acc) {
+                    const int64_t o = cnt + __popcll(bal & lt);
+                    if (o < lim) S.col[base + o] = (int32_t)(skey[c] & 0xffffffffull);
+                }
+                cnt += __popcll(bal);
+            }
+        }
+    }
+    if (lane == 0) {
+        if (!EMIT) S.row_ptr[id + 1] = cnt;
+        else if (cnt != lim) *mismatch = 1;
+    }
+}
+
+// One query by one lane (the outer points: few candidates per band), with
+// the same window runs and row order as small_query.
+template <int MODE>
+__device__ void small_query_lane(const SmallGraph &S, int64_t q, const uint64_t *skey, const int32_t *bstart,
+                                 int *mismatch)
+{
+    constexpr bool EMIT = MODE == M_EMIT;
+    const SearchArgs &A = S.A;
+    const double rq = A.sr[q], tq = A.st[q];
+    const float4 fq = A.rec[q];
+    const int32_t id = __float_as_int(fq.w);
+    int J = 0;
+    while (J < A.B && band_inside(A, rq, J)) ++J;
+    int64_t cnt = 0, base = 0, lim = 0;
+    if (EMIT) {
+        base = S.row_ptr[id];
+        lim = S.row_ptr[id + 1] - base;
+    }
+    {
+        const int64_t s0 = bstart[0], e0 = bstart[J];
+        if (EMIT) {
+            for (int64_t c = s0; c < e0; ++c) {
+                if (c == q) continue;
+                if (cnt < lim) S.col[base + cnt] = (int32_t)(skey[c] & 0xffffffffull);
+                ++cnt;
+            }
+        } else {
+            cnt = (e0 - s0) - ((q >= s0 && q < e0) ? 1 : 0);
+        }
+    }
+    auto lower = [&](int64_t s, int64_t e, uint32_t k, bool above) {
+        while (s < e) {
+            const int64_t mid = (s + e) >> 1;
+            const uint32_t km = (uint32_t)(skey[mid] >> 32);
+            if (above ? km <= k : km < k) s = mid + 1;
+            else e = mid;
+        }
+        return s;
+    };
+    for (int j = J; j < A.B; ++j) {
+        const int64_t s = bstart[j], e = bstart[j + 1];
+        if (s == e) continue;
+        const double w = window_w(A, fq.x, fq.y, fq.z, j);
+        const bool fp = !(w < 0x1p-5);
+        int64_t ra[3], rb[3];
+        int nr = 0;
+        if (!(w < 3.0)) {
+            ra[0] = s; rb[0] = e; nr = 1;
+        } else {
+            const double lo = tq - w, hi = tq + w;
+            if (hi >= RHG_TWO_PI_D) {
+                ra[nr] = s; rb[nr] = lower(s, e, band_key(A, j, hi - RHG_TWO_PI_D), true); ++nr;
+            }
+            ra[nr] = lower(s, e, band_key(A, j, fmax(lo, 0.0)), false);
+            rb[nr] = lower(s, e, band_key(A, j, fmin(hi, RHG_TWO_PI_D)), true);
+            ++nr;
+            if (lo < 0.0) {
+                ra[nr] = lower(s, e, band_key(A, j, lo + RHG_TWO_PI_D), false); rb[nr] = e; ++nr;
+            }
+        }
+        for (int k = 0; k < nr; ++k)
+            for (int64_t c = ra[k]; c < rb[k]; ++c) {
+                if (c == q) continue;
+                const double tc = A.st[c];
+                if (short_angle(tq, tc) > w) continue;
+                const float4 fc = A.rec[c];
+                if (decide<MODE, true>(A, q, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp, -1)) {
+                    if (EMIT && cnt < lim) S.col[base + cnt] = (int32_t)(skey[c] & 0xffffffffull);
+                    ++cnt;
+                }
+            }
+    }
+    if (!EMIT) S.row_ptr[id + 1] = cnt;
+    else if (cnt != lim) *mismatch = 1;
+}
+
+// Sorted positions below this many (the innermost points, whose windows
+// hold the most candidates) are searched a wavefront per query, the rest a
+// lane per query.
+constexpr int64_t SMALL_WAVE_QUERIES = 512;
+
+__global__ void __launch_bounds__(SMALL_THREADS) small_batch_kernel(const SmallGraph *G, int count,
+                                                                    unsigned int *head)
+{
+    __shared__ uint64_t skey[RHG_SMALL_GRAPH];
+    __shared__ dd tab[LOGT_N];
+    __shared__ int32_t bstart[RHG_MAX_BANDS + 1];
+    __shared__ int64_t part[SMALL_THREADS / 64];
+    __shared__ int gnext, mismatch;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = SMALL_THREADS / 64;
+    fill_log_table(tab, tid, SMALL_THREADS);
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            gnext = (int)atomicAdd(head, 1u);
+            mismatch = 0;
+        }
+        __syncthreads();
+        const int g = gnext;
+        if (g >= count) return;
+        const SmallGraph &S = G[g];
+        const SearchArgs &A = S.A;
+        const int64_t n = S.n;
+        int64_t P = 2;
+        while (P < n) P <<= 1;
+        // sample; composite keys (sort key, id)
+        for (int64_t i = tid; i < P; i += SMALL_THREADS) {
+            uint64_t k = ~0ull;
+            if (i < n) {
+                double ri, ti;
+                sample_point(i, S.k0, S.k1, S.alpha, A.R, S.cam1, S.cam1_lo, tab, &ri, &ti);
+                S.r[i] = ri;
+                S.theta[i] = ti;
+                const uint32_t b = (uint32_t)small_band_of(A, ri);
+                const uint32_t ak = angle_key_s(ti);
+                const uint32_t key = A.band_bits ? ((b << (32 - A.band_bits)) | (ak >> A.band_bits)) : ak;
+                k = ((uint64_t)key << 32) | (uint64_t)i;
+            }
+            skey[i] = k;
+        }
+        __syncthreads();
+        // bitonic sort of the P keys, ascending
+        for (int64_t kk = 2; kk <= P; kk <<= 1)
+            for (int64_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int64_t i = tid; i < P; i += SMALL_THREADS) {
+                    const int64_t l = i ^ jj;
+                    if (l > i) {
+                        const uint64_t a = skey[i], b = skey[l];
+                        if ((a > b) == ((i & kk) == 0)) {
+                            skey[i] = b;
+                            skey[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        // sorted records; band starts
+        for (int64_t p = tid; p < n; p += SMALL_THREADS) {
+            const uint32_t id = (uint32_t)(skey[p] & 0xffffffffull);
+            const double ri = S.r[id], ti = S.theta[id];
+            S.keys[p] = (uint32_t)(skey[p] >> 32);
+            ((double *)A.sr)[p] = ri;
+            ((double *)A.st)[p] = ti;
+            ((float4 *)A.rec)[p] = make_float4((float)(exp(ri) * S.inv), (float)(exp(-ri) * S.inv),
+                                               (float)(sinh(ri) * S.sc), __int_as_float((int)id));
+        }
+        if (tid <= A.B) {
+            int64_t pos = n;
+            if (tid < A.B) {
+                const uint64_t k = (uint64_t)(A.band_bits ? ((uint32_t)tid << (32 - A.band_bits)) : 0u) << 32;
+                int64_t s = 0, e = n;
+                while (s < e) {
+                    const int64_t mid = (s + e) >> 1;
+                    if (skey[mid] < k) s = mid + 1; else e = mid;
+                }
+                pos = tid == 0 ? 0 : s;
+            }
+            bstart[tid] = (int32_t)pos;
+        }
+        if (tid == 0) S.row_ptr[0] = 0;
+        __syncthreads();
+        // count pass: the innermost queries one per wavefront, the rest one
+        // per lane
+        const int64_t hq = n < SMALL_WAVE_QUERIES ? n : SMALL_WAVE_QUERIES;
+        for (int64_t q = wave; q < hq; q += nwave) small_query<M_COUNT>(S, q, skey, bstart, &mismatch);
+        for (int64_t q = hq + tid; q < n; q += SMALL_THREADS) small_query_lane<M_COUNT>(S, q, skey, bstart, &mismatch);
+        __syncthreads();
+        // row offsets: inclusive scan of row_ptr[1 .. n] in steps of 1024
+        int64_t carry = 0;
+        for (int64_t b0 = 0; b0 < n; b0 += SMALL_THREADS) {
+            const int64_t i = b0 + tid;
+            int64_t v = i < n ? S.row_ptr[1 + i] : 0;
+            int64_t tot;
+            int64_t x = v - 0;
+            const int64_t ex = wave_excl_sum64(x, lane, &tot);
+            if (lane == 0) part[wave] = tot;
+            __syncthreads();
+            int64_t before = 0, all = 0;
+            for (int w2 = 0; w2 < nwave; ++w2) {
+                if (w2 < wave) before += part[w2];
+                all += part[w2];
+            }
+            if (i < n) S.row_ptr[1 + i] = carry + before + ex + v;
+            carry += all;
+            __syncthreads();
+        }
+        const int64_t nnz = carry;
+        if (nnz > S.col_cap) {
+            if (tid == 0) *S.overflow = 1;
+            continue;
+        }
+        // emit pass
+        for (int64_t q = wave; q < hq; q += nwave) small_query<M_EMIT>(S, q, skey, bstart, &mismatch);
+        for (int64_t q = hq + tid; q < n; q += SMALL_THREADS) small_query_lane<M_EMIT>(S, q, skey, bstart, &mismatch);
+        __syncthreads();
+        if (tid == 0) *S.overflow = mismatch ? 2 : 0;
+    }
+}
+
+__global__ void small_batch_reset(unsigned int *head)
+{
+    if (threadIdx.x == 0) *head = 0u;
+}
+
+size_t small_graph_record_bytes() { return sizeof(SmallGraph); }
+
+// Fills the device record of a small graph (host memory `out`, copied to the
+// device by the caller).  Returns false when the workspace is too small.
+bool make_small_graph(const rhg_params &p, const Layout &L, double *r, double *theta, void *ws, size_t ws_bytes,
+                      int64_t *row_ptr, int32_t *col, int64_t col_cap, int32_t *overflow,
+                      unsigned long long *stats, void *out)
+{
+    SmallGraph &G = *(SmallGraph *)out;
+    memset(&G, 0, sizeof(G));
+    SearchArgs &A = G.A;
+    const int64_t n = p.n;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    char *b = (char *)align_up((size_t)ws, 256);
+    const size_t need = align_up(4 * N, 256) + 2 * align_up(8 * N, 256) + align_up(16 * N, 256) + 256;
+    if (!ws || ws_bytes < need) return false;
+    G.keys = (uint32_t *)b;
+    b += align_up(4 * N, 256);
+    A.sr = (const double *)b;
+    b += align_up(8 * N, 256);
+    A.st = (const double *)b;
+    b += align_up(8 * N, 256);
+    A.rec = (const float4 *)b;
+    G.inv = 1.0 / sqrt(2.0 * p.cosh_R);
+    G.sc = sqrt(2.0 / p.cosh_R);
+    for (int j = 0; j <= L.B; ++j) A.E[j] = L.E[j];
+    for (int j = 0; j < L.B; ++j) {
+        A.ep_lo[j] = (float)(exp(L.E[j]) * G.inv);
+        A.em_lo[j] = (float)(exp(-L.E[j]) * G.inv);
+        A.sh_lo[j] = (float)(sinh(L.E[j]) * G.sc);
+        A.rs_lo[j] = A.sh_lo[j] > 0.0f ? (float)(1.0 / sqrt((double)A.sh_lo[j])) * (1.0f + 0x1p-20f) : 0.0f;
+        A.cbits[j] = L.cbits[j];
+    }
+    A.B = L.B;
+    A.band_bits = L.band_bits;
+    A.n = n;
+    A.R = p.R;
+    A.C = p.cosh_R;
+    A.C_lo = p.cosh_R_lo;
+    A.use_p32 = (!L.fp64_only && p.R < 80.0) ? 1 : 0;
+    A.keys = G.keys;
+    A.stats = stats;
+    G.n = n;
+    G.k0 = (uint32_t)p.seed;
+    G.k1 = (uint32_t)(p.seed >> 32);
+    G.alpha = p.alpha;
+    G.cam1 = p.cosh_aR_m1;
+    G.cam1_lo = p.cosh_aR_m1_lo;
+    G.r = r;
+    G.theta = theta;
+    G.row_ptr = row_ptr;
+    G.col = col;
+    G.col_cap = col_cap;
+    G.overflow = overflow;
+    return true;
+}
+
+hipError_t launch_small_batch(const void *table, int count, unsigned int *head, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(small_batch_reset, dim3(1), dim3(64), 0, s, head);
+    const int grid = std::min(count, 256);
+    hipLaunchKernelGGL(small_batch_kernel, dim3(grid), dim3(SMALL_THREADS), 0, s, (const SmallGraph *)table, count,
+                       head);
+    return hipGetLastError();
 }
 
 }  // namespace rhg

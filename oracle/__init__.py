@@ -79,6 +79,14 @@ def _load():
         lib.orc_mix64.restype = u64
         lib.orc_mix64.argtypes = [u64]
         lib.orc_pair_scan.argtypes = [i64, pd, pd, d, pi32, C.POINTER(C.c_uint64), i32, pi64, pd]
+        lib.orc_temp_coin.restype = u64
+        lib.orc_temp_coin.argtypes = [u64, i64, i64]
+        lib.orc_temp_is_edge.argtypes = [d, d, d, d, d, d, u64, pi64]
+        lib.orc_temp_is_edge_quad.argtypes = [d, d, d, d, d, d, u64]
+        lib.orc_temp_edges.restype = i64
+        lib.orc_temp_edges.argtypes = [i64, pd, pd, d, d, u64, pi64, pi64, i64, i32, pi64]
+        lib.orc_temp_rows.restype = i64
+        lib.orc_temp_rows.argtypes = [i64, pd, pd, d, d, u64, pi64, i64, pi64, pi32, i64, i32, pi64]
         _lib = lib
         return lib
 
@@ -378,3 +386,72 @@ def graph_stats(row_ptr, col, kmin: float = 10.0, triangles: bool = True) -> dic
         out["avg_local_clustering"] = float(np.mean(t[ok] / (d[ok] * (d[ok] - 1) / 2.0))) if ok.any() else float("nan")
         out["vertex_triangles"] = t
     return out
+
+
+# --------------------------------------------------------------------------
+# Temperature model (the distance-dependent connection probability that
+# Sec. 2.1 sets aside).  Pair {i, j} is an edge iff its coin u = a 2^-53
+# (a = temp_coin(seed, i, j)) is below p(d) = 1 / (1 + e^{(d - R)/(2T)}).
+# --------------------------------------------------------------------------
+
+def temp_coin(seed: int, i: int, j: int) -> int:
+    """a = k + 1 in [1, 2^53] for pair {i, j}: u = a / 2^53."""
+    return int(_load().orc_temp_coin(seed & 0xFFFFFFFFFFFFFFFF, int(i), int(j)))
+
+
+def temp_is_edge(ri, ti, rj, tj, R, T, a):
+    """Exact decision of u = a 2^-53 < p(d): (edge, quad_fallbacks, ties)."""
+    st = np.zeros(2, dtype=np.int64)
+    e = _load().orc_temp_is_edge(ri, ti, rj, tj, R, T, int(a), _p(st, C.c_int64))
+    return bool(e), int(st[0]), int(st[1])
+
+
+def temp_is_edge_quad(ri, ti, rj, tj, R, T, a):
+    return bool(_load().orc_temp_is_edge_quad(ri, ti, rj, tj, R, T, int(a)))
+
+
+def temp_csr(r, theta, R, T, seed, nthreads: int = 0):
+    """Every pair tested once with its coin; symmetric CSR with ascending
+    rows (int64 row_ptr, int32 col) and (quad_fallbacks, ties)."""
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    n = r.shape[0]
+    cap = max(1 << 16, 8 * n)
+    while True:
+        ei = np.empty(cap, dtype=np.int64)
+        ej = np.empty(cap, dtype=np.int64)
+        st = np.zeros(2, dtype=np.int64)
+        m = lib.orc_temp_edges(n, _p(r, C.c_double), _p(theta, C.c_double), R, T,
+                               seed & 0xFFFFFFFFFFFFFFFF, _p(ei, C.c_int64), _p(ej, C.c_int64),
+                               cap, nthreads, _p(st, C.c_int64))
+        if m <= cap:
+            break
+        cap = int(m)
+    src = np.concatenate([ei[:m], ej[:m]])
+    dst = np.concatenate([ej[:m], ei[:m]])
+    order = np.lexsort((dst, src))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
+    return row_ptr, dst[order].astype(np.int32), int(st[0]), int(st[1])
+
+
+def temp_rows(r, theta, R, T, seed, which, nthreads: int = 0):
+    """Ascending neighbour lists of the vertices in ``which`` under the
+    temperature model: (ptr, col, quad_fallbacks, ties)."""
+    lib = _load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    which = np.ascontiguousarray(which, dtype=np.int64)
+    n = r.shape[0]
+    cap = 1 << 16
+    while True:
+        ptr = np.zeros(which.shape[0] + 1, dtype=np.int64)
+        col = np.empty(cap, dtype=np.int32)
+        st = np.zeros(2, dtype=np.int64)
+        tot = lib.orc_temp_rows(n, _p(r, C.c_double), _p(theta, C.c_double), R, T,
+                                seed & 0xFFFFFFFFFFFFFFFF, _p(which, C.c_int64), which.shape[0],
+                                _p(ptr, C.c_int64), _p(col, C.c_int32), cap, nthreads, _p(st, C.c_int64))
+        if tot >= 0:
+            return ptr, col[:tot].copy(), int(st[0]), int(st[1])
+        cap = int(ptr[-1]) + 1

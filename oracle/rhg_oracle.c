@@ -481,3 +481,170 @@ void orc_lr_candidates(uint64_t seed, int64_t j0, int64_t count, int64_t n, int6
         b[c] = (int64_t)(u < v ? v : u);
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* Temperature model.  Sec. 2.1 sets aside Krioukov et al.'s more       */
+/* general model, in which a pair is joined with a probability that     */
+/* depends on its distance.  Reading taken here: the Fermi-Dirac        */
+/* probability of that model with curvature 1,                          */
+/*     p(d) = 1 / (1 + e^{(d - R) / (2T)}),  0 < T < 1,                 */
+/* which tends to the threshold rule d <= R as T -> 0.  Pair {i, j}     */
+/* draws one coin u = a 2^-53 with a = k + 1 in [1, 2^53], k the top    */
+/* 53 bits of the word (x1:x0) of the Philox4x32-10 block with key      */
+/* (seed_lo, seed_hi) and counter (min(i,j), max(i,j), 2, 0) -- the     */
+/* third word 2 keeps coins apart from the points' draws (0) and the    */
+/* long-range candidates (1).  The pair is an edge iff u < p(d).        */
+/* ------------------------------------------------------------------ */
+
+/* a = k + 1 of pair {i, j} (i != j, both below 2^32). */
+uint64_t orc_temp_coin(uint64_t seed, int64_t i, int64_t j)
+{
+    const uint64_t lo = (uint64_t)(i < j ? i : j), hi = (uint64_t)(i < j ? j : i);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const uint32_t ctr[4] = {(uint32_t)lo, (uint32_t)hi, 2u, 0u};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    return ((((uint64_t)x[1] << 32) | x[0]) >> 11) + 1;
+}
+
+/* With b = 2^53 - a, so that (1 - u)/u = b/a exactly:
+ *   u < p(d)  <=>  e^{(d - R)/(2T)} < b/a  <=>  d < D = R + 2T ln(b/a),
+ * never when b = 0 (u = 1) or D <= 0 (d >= 0), and otherwise
+ *   <=>  cosh d < cosh D,
+ * with cosh d in the non-negative form of edge_quad / edge64s. */
+static int temp_quad(double ri, double ti, double rj, double tj, double R, double T, uint64_t a, orc_stats *st)
+{
+    const uint64_t b = (1ull << 53) - a;
+    if (b == 0) return 0;
+    const __float128 D = (__float128)R + 2.0Q * (__float128)T * logq((__float128)b / (__float128)a);
+    if (fabsq(D) <= 1e-30Q) st->ties++;
+    if (D <= 0) return 0;
+    double tmax = ti > tj ? ti : tj, tmin = ti > tj ? tj : ti;
+    __float128 dq = (__float128)tmax - (__float128)tmin;
+    if (dq > M_PIq) dq = ((__float128)(TWO_PI_D - tmax) + (__float128)tmin) + TWO_PI_RES_Q;
+    const __float128 s = sinq(dq * 0.5Q);
+    const __float128 L = coshq((__float128)ri - (__float128)rj)
+                       + 2.0Q * sinhq((__float128)ri) * sinhq((__float128)rj) * s * s;
+    const __float128 C = coshq(D);
+    if (fabsq(L - C) <= C * 1e-30Q) st->ties++;
+    return L < C;
+}
+
+/* binary64 with a relative margin of 1e-9 (on D near 0 an absolute one),
+ * binary128 inside it.  shi, shj as in edge64s. */
+static int temp64s(double ri, double ti, double shi, double rj, double tj, double shj, double R, double T,
+                   uint64_t a, orc_stats *st)
+{
+    const uint64_t b = (1ull << 53) - a;
+    if (b == 0) return 0;
+    const double D = R + 2.0 * T * log((double)b / (double)a);
+    if (D < -1e-9) return 0;
+    if (D > 1e-9) {
+        double tmax = ti > tj ? ti : tj, tmin = ti > tj ? tj : ti;
+        double d = tmax - tmin;
+        if (d > M_PI) d = ((TWO_PI_D - tmax) + tmin) + TWO_PI_RES_D;
+        const double s = sin(0.5 * d);
+        const double L = cosh(ri - rj) + 2.0 * shi * shj * s * s;
+        const double C = cosh(D);
+        if (L < C * (1.0 - 1e-9)) return 1;
+        if (L > C * (1.0 + 1e-9)) return 0;
+    }
+    st->quad++;
+    return temp_quad(ri, ti, rj, tj, R, T, a, st);
+}
+
+/* Single pair decision for a given coin a (i != j assumed by the caller). */
+int orc_temp_is_edge(double ri, double ti, double rj, double tj, double R, double T, uint64_t a, int64_t stats[2])
+{
+    orc_stats st = {0, 0};
+    const int e = temp64s(ri, ti, sinh(ri), rj, tj, sinh(rj), R, T, a, &st);
+    if (stats) { stats[0] += st.quad; stats[1] += st.ties; }
+    return e;
+}
+
+/* binary128 only, for tests of the binary64 stage. */
+int orc_temp_is_edge_quad(double ri, double ti, double rj, double tj, double R, double T, uint64_t a)
+{
+    orc_stats st = {0, 0};
+    return temp_quad(ri, ti, rj, tj, R, T, a, &st);
+}
+
+/* Every pair i < j, each tested once with its own coin: the edges as
+ * (i, j) in out_i, out_j (capacity cap, in no particular order).  Returns
+ * the edge count (the lists hold the first cap of them). */
+int64_t orc_temp_edges(int64_t n, const double *r, const double *theta, double R, double T, uint64_t seed,
+                       int64_t *out_i, int64_t *out_j, int64_t cap, int nthreads, int64_t stats[2])
+{
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    double *sh = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    int64_t total = 0, q = 0, t = 0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) sh[j] = sinh(r[j]);
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+:q,t)
+    for (int64_t i = 0; i < n; ++i) {
+        orc_stats st = {0, 0};
+        for (int64_t j = i + 1; j < n; ++j) {
+            const uint64_t a = orc_temp_coin(seed, i, j);
+            if (temp64s(r[i], theta[i], sh[i], r[j], theta[j], sh[j], R, T, a, &st)) {
+                int64_t k;
+                #pragma omp atomic capture
+                k = total++;
+                if (k < cap) { out_i[k] = i; out_j[k] = j; }
+            }
+        }
+        q += st.quad; t += st.ties;
+    }
+    free(sh);
+    if (stats) { stats[0] += q; stats[1] += t; }
+    return total;
+}
+
+/* Neighbours of the vertices rows[0..nrows), ascending, each row tested
+ * against all n points with the pair's coin; as orc_rows otherwise. */
+int64_t orc_temp_rows(int64_t n, const double *r, const double *theta, double R, double T, uint64_t seed,
+                      const int64_t *rows, int64_t nrows, int64_t *out_ptr, int32_t *out, int64_t cap,
+                      int nthreads, int64_t stats[2])
+{
+    int64_t q = 0, t = 0, total = 0, overflow = 0;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const int NT = omp_get_max_threads();
+    double *sh = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    orc_list *hits = (orc_list *)calloc((size_t)NT, sizeof(orc_list));
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) sh[j] = sinh(r[j]);
+    out_ptr[0] = 0;
+    for (int64_t a0 = 0; a0 < nrows; a0 += ORC_ROW_BLOCK) {
+        const int64_t nb = nrows - a0 < ORC_ROW_BLOCK ? nrows - a0 : ORC_ROW_BLOCK;
+        #pragma omp parallel num_threads(NT) reduction(+:q,t)
+        {
+            orc_list *l = &hits[omp_get_thread_num()];
+            l->len = 0;
+            orc_stats st = {0, 0};
+            #pragma omp for schedule(static)
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t b = 0; b < nb; ++b) {
+                    const int64_t i = rows[a0 + b];
+                    if (j == i) continue;
+                    const uint64_t a = orc_temp_coin(seed, i, j);
+                    if (temp64s(r[i], theta[i], sh[i], r[j], theta[j], sh[j], R, T, a, &st))
+                        list_push(l, (b << 40) | j);
+                }
+            q += st.quad; t += st.ties;
+        }
+        for (int64_t b = 0; b < nb; ++b) {
+            for (int th = 0; th < NT; ++th)
+                for (int64_t k = 0; k < hits[th].len; ++k) {
+                    if ((hits[th].v[k] >> 40) != b) continue;
+                    if (total < cap) out[total] = (int32_t)(hits[th].v[k] & ((1LL << 40) - 1));
+                    else overflow = 1;
+                    ++total;
+                }
+            out_ptr[a0 + b + 1] = total;
+        }
+    }
+    for (int th = 0; th < NT; ++th) free(hits[th].v);
+    free(hits);
+    free(sh);
+    if (stats) { stats[0] += q; stats[1] += t; }
+    return overflow ? -1 : total;
+}

@@ -216,7 +216,8 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
  * for (twice the planner's upper estimate of 2m, plus 2^23; sort such a
  * graph with rhg_sort_rows instead).  The emit kernels check every row they
  * write against its count; a disagreement is RHG_EINTERNAL from the next
- * rhg_index_stats (rhg_generate checks it itself). */
+ * rhg_index_stats (rhg_generate checks it itself).  RHG_EINVAL if the
+ * index's last count pass was not rhg_count_edges. */
 rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx,
                           int64_t col_capacity, int canonical_rows, void *stream);
 
@@ -347,6 +348,49 @@ rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t see
                         const rhg_tuning *t /* host, may be NULL */,
                         rhg_alloc_fn alloc, void *alloc_ctx, int canonical_rows,
                         rhg_csr *out /* host */, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Temperature model.                                                  */
+/* ------------------------------------------------------------------ */
+
+/* The more general model of Krioukov et al. that Sec. 2.1 mentions and sets
+ * aside: a pair is joined with a probability that depends on its distance.
+ * Read here as their Fermi-Dirac form with curvature 1,
+ *     p(d) = 1 / (1 + e^{(d - R) / (2T)}),  temperature 0 < T < 1,
+ * which tends to the threshold rule d <= R as T -> 0.  Pair {i, j} draws one
+ * coin u = a 2^-53, a = k + 1 in [1, 2^53], k = the word (x1:x0) >> 11 of the
+ * Philox4x32-10 block with key (seed_lo, seed_hi) of the index's params and
+ * counter (min(i,j), max(i,j), 2, 0); the pair is an edge iff u < p(d),
+ * decided exactly on the binary64 points and the coin (an FP32 screen,
+ * binary64, then double-double; pairs that double-double cannot separate
+ * within a relative 1e-26 are counted as ties in rhg_index_stats).  Only
+ * pairs with d < R + 2T ln(2^53 - 1) can satisfy it (p(d) > 2^-53), so the
+ * search covers exactly those.  The disk is the threshold model's: R comes
+ * from the params as planned for the target degree (Eq. (22)), and at T > 0
+ * the mean degree is larger (by about pi T / sin(pi T) for large n).
+ *
+ * rhg_temp_count_edges: as rhg_count_edges for this rule (row_ptr: device,
+ * n + 1 int64, row_ptr[n] = 2m).  rhg_temp_emit_edges: as rhg_emit_edges;
+ * row_ptr must come from rhg_temp_count_edges on the same index at the same
+ * T with no other count pass in between (the two models share the index's
+ * search scratch), else RHG_EINVAL.  Rows are in search order, or ascending
+ * with canonical_rows = 1 (RHG_ECAPACITY if the graph has more entries than
+ * the index's row-sort scratch, which is sized from the threshold model:
+ * sort such a graph with rhg_sort_rows).  The innermost queries (the
+ * tuning's heavy_points) are split over workgroups; at larger T a larger
+ * heavy_points keeps the wider windows balanced.  Same diagnostics and
+ * row-length check as the threshold passes.
+ * Errors: RHG_EINVAL for a NULL argument or T outside (0, 1) (or NaN).
+ *
+ * rhg_temp_generate: rhg_generate with this rule (plan, sample, index,
+ * count, scan, emit; canonical rows beyond the index's scratch get a row-sort
+ * workspace of their own from `alloc`). */
+rhg_status rhg_temp_count_edges(rhg_index *idx, double T, int64_t *row_ptr, void *stream);
+rhg_status rhg_temp_emit_edges(rhg_index *idx, double T, const int64_t *row_ptr, int32_t *col_idx,
+                               int64_t col_capacity, int canonical_rows, void *stream);
+rhg_status rhg_temp_generate(int64_t n, double avg_degree, double gamma, double T, uint64_t seed,
+                             const rhg_tuning *t /* host, may be NULL */, rhg_alloc_fn alloc, void *alloc_ctx,
+                             int canonical_rows, rhg_csr *out /* host */, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Phase timing (HIP events on the caller's stream).                   */

@@ -122,6 +122,9 @@ def load():
                                    P(vp), P(i64), vp, i32, P(vp)]),
         "rhg_batch_launch": (i32, [vp, vp]),
         "rhg_batch_destroy": (None, [vp]),
+        "rhg_temp_count_edges": (i32, [vp, d, vp, vp]),
+        "rhg_temp_emit_edges": (i32, [vp, d, vp, vp, i64, i32, vp]),
+        "rhg_temp_generate": (i32, [i64, d, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
         "rhg_set_profiling": (i32, [i32]),
         "rhg_phase_times": (i32, [P(C.c_double), P(C.c_int64), i32]),
         "rhg_phase_name": (C.c_char_p, [i32]),
@@ -383,6 +386,46 @@ def rhg_generate(n: int, avg_degree: float, gamma: float, seed: int, tuning: Opt
     out = rhg_csr()
     _check(load().rhg_generate(n, avg_degree, gamma, seed, _tuning(tuning), cb, None,
                                1 if canonical_rows else 0, C.byref(out), _stream(stream)))
+
+    def view(ptr, dtype, count):
+        return held[ptr][: count * torch.empty((), dtype=dtype).element_size()].view(dtype)
+
+    return Graph(params=out.params,
+                 row_ptr=view(out.row_ptr, torch.int64, n + 1),
+                 col_idx=view(out.col_idx, torch.int32, out.nnz),
+                 r=view(out.r, torch.float64, n), theta=view(out.theta, torch.float64, n))
+
+
+def rhg_temp_count_edges(idx: Index, T: float, row_ptr, stream=None):
+    """Temperature model, count pass: row_ptr (device int64, n + 1)."""
+    import torch
+    assert row_ptr.dtype == torch.int64 and row_ptr.numel() >= idx.params.n + 1
+    _check(load().rhg_temp_count_edges(idx.handle, float(T), _ptr(row_ptr), _stream(stream)))
+
+
+def rhg_temp_emit_edges(idx: Index, T: float, row_ptr, col_idx, canonical_rows: bool = False, stream=None):
+    import torch
+    assert col_idx.dtype == torch.int32
+    _check(load().rhg_temp_emit_edges(idx.handle, float(T), _ptr(row_ptr), _ptr(col_idx), col_idx.numel(),
+                                      1 if canonical_rows else 0, _stream(stream)))
+
+
+def rhg_temp_generate(n: int, avg_degree: float, gamma: float, T: float, seed: int,
+                      tuning: Optional[dict] = None, canonical_rows: bool = False, device="cuda",
+                      stream=None) -> Graph:
+    """The temperature model end to end on the GPU; device memory from PyTorch."""
+    import torch
+    held = {}
+
+    def _alloc(nbytes, _ctx):
+        t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+        held[t.data_ptr()] = t
+        return t.data_ptr()
+
+    cb = ALLOC_FN(_alloc)
+    out = rhg_csr()
+    _check(load().rhg_temp_generate(n, avg_degree, gamma, float(T), seed, _tuning(tuning), cb, None,
+                                    1 if canonical_rows else 0, C.byref(out), _stream(stream)))
 
     def view(ptr, dtype, count):
         return held[ptr][: count * torch.empty((), dtype=dtype).element_size()].view(dtype)

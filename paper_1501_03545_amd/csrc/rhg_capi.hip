@@ -316,6 +316,7 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream)
     hipStream_t s = (hipStream_t)stream;
     RHG_HIP(launch_search(idx, row_ptr, nullptr, 0, s));
     idx->counted = 1;
+    idx->count_model = 1;
     if (idx->n > 0) {
         PhaseScope ps(RHG_PHASE_SCAN, s);
         RHG_HIP(inclusive_scan_i64(row_ptr + 1, idx->n, idx->tmp, s));
@@ -329,6 +330,7 @@ rhg_status rhg_emit_edges(rhg_index *idx, const int64_t *row_ptr, int32_t *col_i
     g_last_error.clear();
     if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_emit_edges: NULL argument");
     if (col_capacity < 0) return fail(RHG_EINVAL, "rhg_emit_edges: negative capacity");
+    if (idx->count_model != 1) return fail(RHG_EINVAL, "rhg_emit_edges: the index's last count pass was not rhg_count_edges");
     hipStream_t s = (hipStream_t)stream;
     int64_t nnz = 0;
     RHG_HIP(hipMemcpyAsync(&nnz, row_ptr + idx->n, 8, hipMemcpyDeviceToHost, s));
@@ -759,6 +761,121 @@ rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t see
     rhg_index_free(idx);
     if (e != hipSuccess) return check_hip(e, "rhg_generate (consistency check)");
     if (mismatch) return fail(RHG_EINTERNAL, "rhg_generate: the emit pass disagreed with the count pass");
+    out->n = n;
+    out->nnz = nnz;
+    out->row_ptr = row_ptr;
+    out->col_idx = col;
+    out->r = r;
+    out->theta = th;
+    out->params = p;
+    return RHG_OK;
+}
+
+// ---------------------------------------------------------------- temperature
+
+static rhg_status check_T(double T, const char *who)
+{
+    if (!(T > 0.0 && T < 1.0)) return fail(RHG_EINVAL, std::string(who) + ": temperature must lie in (0, 1)");
+    return RHG_OK;
+}
+
+rhg_status rhg_temp_count_edges(rhg_index *idx, double T, int64_t *row_ptr, void *stream)
+{
+    g_last_error.clear();
+    if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_temp_count_edges: NULL argument");
+    rhg_status st = check_T(T, "rhg_temp_count_edges");
+    if (st != RHG_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    RHG_HIP(launch_temp_search(idx, T, row_ptr, nullptr, 0, s, -1));
+    idx->counted = 0;  // the per-wavefront tallies are the threshold search's
+    idx->count_model = 2;
+    idx->count_T = T;
+    if (idx->n > 0) {
+        PhaseScope ps(RHG_PHASE_SCAN, s);
+        RHG_HIP(inclusive_scan_i64(row_ptr + 1, idx->n, idx->tmp, s));
+    }
+    return RHG_OK;
+}
+
+rhg_status rhg_temp_emit_edges(rhg_index *idx, double T, const int64_t *row_ptr, int32_t *col_idx,
+                               int64_t col_capacity, int canonical_rows, void *stream)
+{
+    g_last_error.clear();
+    if (!idx || !row_ptr) return fail(RHG_EINVAL, "rhg_temp_emit_edges: NULL argument");
+    rhg_status st = check_T(T, "rhg_temp_emit_edges");
+    if (st != RHG_OK) return st;
+    if (col_capacity < 0) return fail(RHG_EINVAL, "rhg_temp_emit_edges: negative capacity");
+    if (idx->count_model != 2 || idx->count_T != T)
+        return fail(RHG_EINVAL, "rhg_temp_emit_edges: the index's last count pass was not rhg_temp_count_edges "
+                                "at this temperature");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nnz = 0;
+    RHG_HIP(hipMemcpyAsync(&nnz, row_ptr + idx->n, 8, hipMemcpyDeviceToHost, s));
+    RHG_HIP(hipStreamSynchronize(s));
+    if (nnz > col_capacity)
+        return fail(RHG_ECAPACITY, "rhg_temp_emit_edges: col_idx holds " + std::to_string(col_capacity) +
+                                       " entries, the graph needs " + std::to_string(nnz));
+    if (nnz > 0 && !col_idx) return fail(RHG_EINVAL, "rhg_temp_emit_edges: col_idx is NULL");
+    if (canonical_rows && nnz > idx->rows_nnz_cap)
+        return fail(RHG_ECAPACITY, "rhg_temp_emit_edges: canonical rows of " + std::to_string(nnz) +
+                                       " entries (over twice the threshold model's expected count) need "
+                                       "rhg_sort_rows");
+    if (nnz > 0) RHG_HIP(launch_temp_search(idx, T, (int64_t *)row_ptr, col_idx, 1, s, col_capacity));
+    if (nnz > 0 && canonical_rows) {
+        PhaseScope ps(RHG_PHASE_ROWS, s);
+        RHG_HIP(launch_sort_rows(row_ptr, col_idx, idx->n, std::min<int64_t>(nnz, idx->n - 1), idx->rows_aux,
+                                 idx->rows_lcap, idx->rows_mapcap, s));
+    }
+    return RHG_OK;
+}
+
+rhg_status rhg_temp_generate(int64_t n, double avg_degree, double gamma, double T, uint64_t seed,
+                             const rhg_tuning *t, rhg_alloc_fn alloc, void *alloc_ctx, int canonical_rows,
+                             rhg_csr *out, void *stream)
+{
+    g_last_error.clear();
+    if (!alloc || !out) return fail(RHG_EINVAL, "rhg_temp_generate: NULL allocator or output");
+    memset(out, 0, sizeof(*out));
+    rhg_status st = check_T(T, "rhg_temp_generate");
+    if (st != RHG_OK) return st;
+    rhg_params p;
+    if ((st = plan(n, avg_degree, gamma, seed, &p)) != RHG_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    double *r = (double *)alloc(N * 8, alloc_ctx);
+    double *th = (double *)alloc(N * 8, alloc_ctx);
+    int64_t *row_ptr = (int64_t *)alloc((size_t)(n + 1) * 8, alloc_ctx);
+    const size_t wsb = rhg_index_workspace_bytes(&p, t);
+    void *ws = alloc(wsb, alloc_ctx);
+    if (!r || !th || !row_ptr || !ws) return fail(RHG_ENOMEM, "rhg_temp_generate: allocation callback failed");
+    if ((st = rhg_sample_points(&p, r, th, stream)) != RHG_OK) return st;
+    rhg_index *idx = nullptr;
+    if ((st = rhg_build_index(&p, r, th, t, ws, wsb, 0, &idx, stream)) != RHG_OK) return st;
+    if ((st = rhg_temp_count_edges(idx, T, row_ptr, stream)) != RHG_OK) { rhg_index_free(idx); return st; }
+    int64_t nnz = 0;
+    hipError_t e = hipMemcpyAsync(&nnz, row_ptr + n, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { rhg_index_free(idx); return check_hip(e, "rhg_temp_generate (edge count)"); }
+    int32_t *col = (int32_t *)alloc((size_t)(nnz > 0 ? nnz : 1) * 4, alloc_ctx);
+    if (!col) { rhg_index_free(idx); return fail(RHG_ENOMEM, "rhg_temp_generate: col_idx allocation failed"); }
+    // canonical rows beyond the index's row-sort scratch: a workspace of their own
+    const bool own_sort = canonical_rows && nnz > idx->rows_nnz_cap;
+    if ((st = rhg_temp_emit_edges(idx, T, row_ptr, col, nnz, canonical_rows && !own_sort, stream)) != RHG_OK) {
+        rhg_index_free(idx);
+        return st;
+    }
+    unsigned long long mismatch = 0;
+    e = hipMemcpyAsync(&mismatch, idx->stats + ST_EMIT_MISMATCH, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    rhg_index_free(idx);
+    if (e != hipSuccess) return check_hip(e, "rhg_temp_generate (consistency check)");
+    if (mismatch) return fail(RHG_EINTERNAL, "rhg_temp_generate: the emit pass disagreed with the count pass");
+    if (own_sort) {
+        const size_t sb = rhg_sort_rows_workspace_bytes(n, nnz);
+        void *sw = alloc(sb, alloc_ctx);
+        if (!sw) return fail(RHG_ENOMEM, "rhg_temp_generate: row-sort workspace allocation failed");
+        if ((st = rhg_sort_rows(n, row_ptr, col, nnz, sw, sb, stream)) != RHG_OK) return st;
+    }
     out->n = n;
     out->nnz = nnz;
     out->row_ptr = row_ptr;

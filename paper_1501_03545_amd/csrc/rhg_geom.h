@@ -1,0 +1,105 @@
+// rhg_geom.h -- device geometry shared by the threshold and temperature
+// searches: the angle key of the sort, the angle between two points, the
+// sorted-position runs of an angular window (through a band's cell
+// directory) and cosh of the hyperbolic distance in binary64 and in
+// double-double.
+//
+// The distance law is that of Sec. 2.1 in the native representation,
+//     cosh d = cosh r_q cosh r_c - sinh r_q sinh r_c cos(dtheta),
+// evaluated in the form with non-negative terms
+//     cosh d = cosh(r_q - r_c) + 2 sinh r_q sinh r_c sin^2(dtheta/2),
+// which has no cancellation.
+#pragma once
+#include "rhg_internal.h"
+
+namespace rhg {
+
+// The top 32 bits of theta / (2 pi) (the angle part of a sort key).
+__device__ __forceinline__ uint32_t angle_key_s(double t)
+{
+    const double k = t * (4294967296.0 / RHG_TWO_PI_D);
+    if (!(k > 0.0)) return 0u;
+    if (k >= 4294967295.0) return 4294967295u;
+    return (uint32_t)k;
+}
+
+// Angle between two points the short way round, in [0, pi].
+__device__ __forceinline__ double short_angle(double ta, double tb)
+{
+    double d = fabs(ta - tb);
+    if (d > RHG_PI_0) {
+        // the long way round: TWO_PI_D - tmax is exact (tmax > pi)
+        const double tmax = fmax(ta, tb), tmin = fmin(ta, tb);
+        d = ((RHG_TWO_PI_D - tmax) + tmin) + RHG_TWO_PI_RES_D;
+    }
+    return d;
+}
+
+// Sorted-position runs of a band (positions [s, e), 2^cb angular cells whose
+// starts are dir[0 .. 2^cb]) covering the angular window [lo, hi] (lo may be
+// < 0 and hi >= 2 pi: the window wraps).  Whole cells are taken, so the runs
+// may hold points just outside the window.  Returns the number of runs (0,
+// 1 or 2) in ascending position order.
+__device__ __forceinline__ int cell_runs(const int32_t *dir, int cb, double lo, double hi, int64_t s, int64_t e,
+                                         int64_t *ra, int64_t *rb)
+{
+    if (hi - lo >= RHG_TWO_PI_D) {
+        ra[0] = s; rb[0] = e;
+        return 1;
+    }
+    const int shift = 32 - cb;
+    const int64_t nc = (int64_t)1 << cb;
+    auto cell = [&](double t) -> int64_t { return cb ? (int64_t)(angle_key_s(t) >> shift) : 0; };
+    int64_t a0, a1, b0 = 1, b1 = 0;
+    if (lo < 0.0) {
+        a0 = 0; a1 = cell(hi);
+        b0 = cell(lo + RHG_TWO_PI_D); b1 = nc - 1;
+    } else if (hi >= RHG_TWO_PI_D) {
+        a0 = 0; a1 = cell(hi - RHG_TWO_PI_D);
+        b0 = cell(lo); b1 = nc - 1;
+    } else {
+        a0 = cell(lo); a1 = cell(hi);
+    }
+    if (b1 >= b0 && b0 <= a1 + 1) {  // the two runs meet
+        ra[0] = s; rb[0] = e;
+        return 1;
+    }
+    ra[0] = dir[a0]; rb[0] = dir[a1 + 1];
+    if (b1 >= b0) {
+        ra[1] = dir[b0]; rb[1] = dir[b1 + 1];
+        return 2;
+    }
+    return 1;
+}
+
+// cosh d in binary64 (a few ulps relative).
+__device__ __forceinline__ double cosh_dist64(double rq, double tq, double rc, double tc)
+{
+    const double x = 0.5 * short_angle(tq, tc);
+    double s;
+    if (x < 0x1p-7) {
+        const double x2 = x * x;
+        s = x * (1.0 - x2 * (1.0 / 6.0 - x2 * (1.0 / 120.0)));
+    } else {
+        s = sin(x);
+    }
+    const double ch = 0.5 * (exp(rq) * exp(-rc) + exp(-rq) * exp(rc));
+    return ch + 2.0 * (sinh(rq) * sinh(rc)) * (s * s);
+}
+
+// cosh d in double-double, the angle difference formed exactly.
+__device__ __forceinline__ dd cosh_dist_dd(double rq, double tq, double rc, double tc)
+{
+    const double tmax = fmax(tq, tc), tmin = fmin(tq, tc);
+    dd d = two_sum(tmax, -tmin);  // exact
+    if (dd_cmp(d, dd_make(RHG_PI_0, 1.2246467991473532e-16)) > 0) {
+        d = two_sum(RHG_TWO_PI_0 - tmax, tmin);  // RHG_TWO_PI_0 - tmax is exact
+        d = dd_add(d, dd_make(RHG_TWO_PI_1, RHG_TWO_PI_2));
+    }
+    const dd s = dd_sin(dd_mul_pow2(d, 0.5));
+    const dd dr = two_sum(rq, -rc);
+    return dd_add(dd_cosh(dr),
+                  dd_mul_pow2(dd_mul(dd_mul(dd_sinh(dd_make(rq)), dd_sinh(dd_make(rc))), dd_mul(s, s)), 2.0));
+}
+
+}  // namespace rhg

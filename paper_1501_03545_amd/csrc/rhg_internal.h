@@ -144,6 +144,8 @@ struct rhg_index {
     unsigned long long *stats;  // ST_COUNT counters
     void *wstat;           // per light wavefront of the last count pass: (tests, candidates swept)
     int counted;           // a count pass has run on this index
+    int count_model;       // the model of the last count pass: 0 none, 1 threshold, 2 temperature
+    double count_T;        // its temperature (model 2)
     uint64_t *dkeys;       // undecided-pair list (defer_cap): packed sorted positions
     int32_t *dchunk;       // its heavy chunk, or -1
     unsigned long long *dcount;  // [0] pairs listed, [1] overflow flag
@@ -176,6 +178,9 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
                               uint32_t *v0, uint32_t *v1, int validate, hipStream_t s);
 hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
                          int64_t col_cap = -1, int32_t *overflow = nullptr);
+// The temperature model's count (emit = 0) or emit pass over the index.
+hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_t *col_idx, int emit,
+                              hipStream_t s, int64_t col_cap);
 
 // The batch's small graphs: a device record per graph, filled on the host by
 // make_small_graph (false: workspace too small), and one persistent launch

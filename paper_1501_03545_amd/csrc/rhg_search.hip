@@ -43,6 +43,7 @@
 
 #include <algorithm>
 
+#include "rhg_geom.h"
 #include "rhg_internal.h"
 #include "rhg_sample.h"
 
@@ -100,44 +101,13 @@ enum { M_COUNT = 0, M_EMIT = 1 };
 constexpr float P32_ACC = 1.0f - 0x1p-18f;
 constexpr float P32_REJ = 1.0f + 0x1p-18f;
 
-__device__ __forceinline__ uint32_t angle_key_s(double t)
-{
-    const double k = t * (4294967296.0 / RHG_TWO_PI_D);
-    if (!(k > 0.0)) return 0u;
-    if (k >= 4294967295.0) return 4294967295u;
-    return (uint32_t)k;
-}
-
-// Angle between two points the short way round, in [0, pi].
-__device__ __forceinline__ double short_angle(double ta, double tb)
-{
-    double d = fabs(ta - tb);
-    if (d > RHG_PI_0) {
-        // the long way round: TWO_PI_D - tmax is exact (tmax > pi)
-        const double tmax = fmax(ta, tb), tmin = fmin(ta, tb);
-        d = ((RHG_TWO_PI_D - tmax) + tmin) + RHG_TWO_PI_RES_D;
-    }
-    return d;
-}
-
 // ------------------------------------------------------------ exact tests
 
 __device__ __noinline__ int edge_dd(double rq, double tq, double rc, double tc, double C, double C_lo,
                                     unsigned long long *stats)
 {
     atomicAdd(&stats[ST_DD], 1ull);
-    const double tmax = fmax(tq, tc), tmin = fmin(tq, tc);
-    dd d = two_sum(tmax, -tmin);  // exact
-    if (dd_cmp(d, dd_make(RHG_PI_0, 1.2246467991473532e-16)) > 0) {
-        d = two_sum(RHG_TWO_PI_0 - tmax, tmin);  // RHG_TWO_PI_0 - tmax is exact
-        d = dd_add(d, dd_make(RHG_TWO_PI_1, RHG_TWO_PI_2));
-    }
-    const dd s = dd_sin(dd_mul_pow2(d, 0.5));
-    const dd dr = two_sum(rq, -rc);
-    const dd L = dd_add(dd_cosh(dr), dd_mul_pow2(dd_mul(dd_mul(dd_sinh(dd_make(rq)), dd_sinh(dd_make(rc))),
-                                                        dd_mul(s, s)),
-                                                 2.0));
-    const dd diff = dd_sub(L, dd_make(C, C_lo));
+    const dd diff = dd_sub(cosh_dist_dd(rq, tq, rc, tc), dd_make(C, C_lo));
     if (fabs(diff.hi) <= 1e-26 * C) atomicAdd(&stats[ST_TIES], 1ull);
     return diff.hi <= 0.0;
 }
@@ -146,16 +116,7 @@ __device__ __noinline__ int edge_dd(double rq, double tq, double rc, double tc, 
 __device__ __noinline__ int edge_p64(double rq, double tq, double rc, double tc, double C, double C_lo,
                                      unsigned long long *stats)
 {
-    const double x = 0.5 * short_angle(tq, tc);
-    double s;
-    if (x < 0x1p-7) {
-        const double x2 = x * x;
-        s = x * (1.0 - x2 * (1.0 / 6.0 - x2 * (1.0 / 120.0)));
-    } else {
-        s = sin(x);
-    }
-    const double ch = 0.5 * (exp(rq) * exp(-rc) + exp(-rq) * exp(rc));
-    const double L = ch + 2.0 * (sinh(rq) * sinh(rc)) * (s * s);
+    const double L = cosh_dist64(rq, tq, rc, tc);
     if (L < C * (1.0 - 0x1p-30)) return 1;
     if (L > C * (1.0 + 0x1p-30)) return 0;
     return edge_dd(rq, tq, rc, tc, C, C_lo, stats);
@@ -272,35 +233,7 @@ __device__ __forceinline__ double window_w(const SearchArgs &A, float eq, float 
 __device__ __forceinline__ int window_runs(const SearchArgs &A, int j, double lo, double hi, int64_t s, int64_t e,
                                            int64_t *ra, int64_t *rb)
 {
-    if (hi - lo >= RHG_TWO_PI_D) {
-        ra[0] = s; rb[0] = e;
-        return 1;
-    }
-    const int cb = A.cbits[j];
-    const int32_t *dir = A.dir + A.dir_base[j];
-    const int shift = 32 - cb;
-    const int64_t nc = (int64_t)1 << cb;
-    auto cell = [&](double t) -> int64_t { return cb ? (int64_t)(angle_key_s(t) >> shift) : 0; };
-    int64_t a0, a1, b0 = 1, b1 = 0;
-    if (lo < 0.0) {
-        a0 = 0; a1 = cell(hi);
-        b0 = cell(lo + RHG_TWO_PI_D); b1 = nc - 1;
-    } else if (hi >= RHG_TWO_PI_D) {
-        a0 = 0; a1 = cell(hi - RHG_TWO_PI_D);
-        b0 = cell(lo); b1 = nc - 1;
-    } else {
-        a0 = cell(lo); a1 = cell(hi);
-    }
-    if (b1 >= b0 && b0 <= a1 + 1) {  // the two runs meet
-        ra[0] = s; rb[0] = e;
-        return 1;
-    }
-    ra[0] = dir[a0]; rb[0] = dir[a1 + 1];
-    if (b1 >= b0) {
-        ra[1] = dir[b0]; rb[1] = dir[b1 + 1];
-        return 2;
-    }
-    return 1;
+    return cell_runs(A.dir + A.dir_base[j], A.cbits[j], lo, hi, s, e, ra, rb);
 }
 
 // Values every lane of the wave holds equally, made visibly uniform so that

@@ -1,0 +1,517 @@
+// rhg_temp.hip -- the neighbour search of the temperature model: the
+// distance-dependent connection probability that Sec. 2.1 sets aside, taken
+// in Krioukov et al.'s Fermi-Dirac form with curvature 1,
+//     p(d) = 1 / (1 + e^{(d - R) / (2T)}),  0 < T < 1.
+// Pair {i, j} draws one coin u = a 2^-53, a = k + 1 in [1, 2^53], k the top
+// 53 bits of the word (x1:x0) of the Philox4x32-10 block with key
+// (seed_lo, seed_hi) and counter (min(i,j), max(i,j), 2, 0), and is an edge
+// iff u < p(d).  With b = 2^53 - a (so that (1 - u)/u = b/a exactly):
+//     u < p(d)  <=>  d < D = R + 2T ln(b/a)  <=>  cosh d < cosh D,
+// never when b = 0 or D <= 0.
+//
+// Truncation.  The smallest coin is 2^-53, so a pair can be an edge only if
+// p(d) > 2^-53, i.e. d < rho = R + 2T ln(2^53 - 1): the search is the
+// threshold search of radius rho on the same index (bands, cells, sorted
+// records), and the rule cuts nothing the model could join.
+//
+// Exact decision per candidate inside the windows:
+//   P32  P = cosh d / cosh R from the FP32 records, as in the threshold
+//        search (relative error <= 21 u, u = 2^-24, plus 2^-34 absolute);
+//        P > K (1 + 2^-16), K = cosh(rho) / cosh(R): beyond rho, no coin.
+//   coin, then in FP32 the threshold c = cosh D / cosh R
+//        = (e^x + e^{-2R - x}) / (1 + e^{-2R}),  x = 2T ln(b/a),
+//        from log2f / exp2f of the coin's integers (relative error of c
+//        below 2^-15 for T < 1; see the design notes), so P and c more than
+//        2^-12 max(P, c) + 2^-32 apart decide the pair;
+//   P64  binary64 (cosh d and cosh D, margin 2^-30), and
+//   DD   double-double for the rest.
+//
+// Work split.  As in the threshold search: the innermost (heavy) queries
+// are split into (query, band, chunk) work items of a workgroup each; every
+// other query is one lane of a wavefront of 64 consecutive sorted
+// positions, which walks its own window in every band.  Rows come out in
+// (band, position) order; the emit pass repeats the count pass's work in
+// the same order.
+#include <string.h>
+
+#include <algorithm>
+
+#include "rhg_geom.h"
+#include "rhg_internal.h"
+#include "rhg_philox.h"
+
+namespace rhg {
+
+struct TempArgs {
+    double E[RHG_MAX_BANDS + 1];      // band edges
+    float ep_lo[RHG_MAX_BANDS];       // e'(E[j]), m'(E[j]), s'(E[j]) of the records
+    float em_lo[RHG_MAX_BANDS];
+    float sh_lo[RHG_MAX_BANDS];
+    int64_t dir_base[RHG_MAX_BANDS + 1];
+    int cbits[RHG_MAX_BANDS];
+    int B;
+    int64_t n;
+    int64_t heavy_cap, max_chunks;
+    int heavy_blocks;
+    double R, twoT;                   // R and 2T
+    float K;                          // cosh(rho) / cosh(R), rounded up
+    float Ktr;                        // K (1 + 2^-16): the truncation test
+    float twoTf;                      // 2T
+    float RL2E;                       // R log2(e)
+    float R2L2E;                      // 2 R log2(e)
+    float f1;                         // 1 / (1 + e^{-2R})
+    int use_p32;
+    uint32_t k0, k1;                  // coin key
+    const int32_t *band_start;
+    const int32_t *dir;
+    const double *sr, *st;
+    const float4 *rec;
+    const int32_t *heavy_end;
+    int64_t *hplan, *hcnt;
+    int32_t *hitem;
+    int64_t *hscal;
+    unsigned long long *stats;
+    int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
+};
+
+enum { T_COUNT = 0, T_EMIT = 1 };
+
+// The pair's coin: a = k + 1 in [1, 2^53].
+__device__ __forceinline__ uint64_t temp_coin(uint32_t ida, uint32_t idb, uint32_t k0, uint32_t k1)
+{
+    uint32_t c0 = min(ida, idb), c1 = max(ida, idb), c2 = 2u, c3 = 0u;
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    return ((((uint64_t)c1 << 32) | c0) >> 11) + 1;
+}
+
+// binary64, then double-double: u = a 2^-53 < p(d) for the points (rq, tq)
+// and (rc, tc).  Rare (pairs the FP32 stage leaves undecided).
+__device__ __noinline__ int temp_exact(double rq, double tq, double rc, double tc, uint64_t a, double R,
+                                       double twoT, unsigned long long *stats, int count_pass)
+{
+    if (count_pass) atomicAdd(&stats[ST_FP32_UNDECIDED], 1ull);
+    const uint64_t b = (1ull << 53) - a;
+    if (b == 0) return 0;
+    const double ad = (double)a, bd = (double)b;  // exact
+    const double D = R + twoT * log(bd / ad);
+    if (D < -0x1p-30) return 0;
+    if (D > 0x1p-30) {
+        const double L = cosh_dist64(rq, tq, rc, tc);
+        const double C = cosh(D);
+        if (L < C * (1.0 - 0x1p-30)) return 1;
+        if (L > C * (1.0 + 0x1p-30)) return 0;
+    }
+    atomicAdd(&stats[ST_DD], 1ull);
+    // ln(b/a) = +-log1p(|b - a| / min(a, b)); b - a is exact
+    const dd lr = bd >= ad ? dd_log1p(dd_div(dd_make(bd - ad), dd_make(ad)))
+                           : dd_neg(dd_log1p(dd_div(dd_make(ad - bd), dd_make(bd))));
+    const dd Dd = dd_add_d(dd_mul_d(lr, twoT), R);
+    if (fabs(Dd.hi) <= 1e-26) atomicAdd(&stats[ST_TIES], 1ull);
+    if (Dd.hi <= 0.0) return 0;
+    const dd C = dd_cosh(Dd);
+    const dd diff = dd_sub(cosh_dist_dd(rq, tq, rc, tc), C);
+    if (fabs(diff.hi) <= 1e-26 * C.hi) atomicAdd(&stats[ST_TIES], 1ull);
+    return diff.hi < 0.0;
+}
+
+// The pair (query q, candidate c, both sorted positions).  1 edge, 0 not.
+template <int MODE>
+__device__ __forceinline__ int temp_decide(const TempArgs &A, int64_t q, double tq, float4 fq, int64_t c,
+                                           double tc, float4 fc)
+{
+    const uint32_t idq = (uint32_t)__float_as_int(fq.w), idc = (uint32_t)__float_as_int(fc.w);
+    if (!A.use_p32)
+        return temp_exact(A.sr[q], tq, A.sr[c], tc, temp_coin(idq, idc, A.k0, A.k1), A.R, A.twoT, A.stats, 0);
+    // P = cosh d / cosh R: e'_q m'_c + m'_q e'_c + s'_q s'_c sin^2(dtheta/2),
+    // sin by its degree-11 Taylor polynomial (any angle up to pi)
+    const float x = (float)(0.5 * short_angle(tq, tc));
+    const float x2 = x * x;
+    float p = -1.0f / 39916800.0f;
+    p = fmaf(p, x2, 1.0f / 362880.0f);
+    p = fmaf(p, x2, -1.0f / 5040.0f);
+    p = fmaf(p, x2, 1.0f / 120.0f);
+    p = fmaf(p, x2, -1.0f / 6.0f);
+    p = fmaf(p, x2, 1.0f);
+    const float s = x * p;
+    float P = fmaf(fq.x, fc.y, fq.y * fc.x);
+    P = fmaf(fq.z * fc.z, s * s, P);
+    if (P > A.Ktr) return 0;  // d > rho: p(d) <= 2^-53 <= u
+    const uint64_t a = temp_coin(idq, idc, A.k0, A.k1);
+    const uint64_t b = (1ull << 53) - a;
+    if (b == 0) return 0;
+    // y = 2T log2(b/a) = x log2(e);  D > 0  <=>  R log2(e) + y > 0
+    const float y = (log2f((float)b) - log2f((float)a)) * A.twoTf;
+    const float Dl = A.RL2E + y;
+    int v = 2;
+    if (Dl < -0x1p-10f) {
+        v = 0;
+    } else if (Dl > 0x1p-10f) {
+        const float cr = (exp2f(y) + exp2f(-A.R2L2E - y)) * A.f1;  // cosh D / cosh R
+        const float tol = 0x1p-12f * fmaxf(P, cr) + 0x1p-32f;
+        v = P < cr - tol ? 1 : (P > cr + tol ? 0 : 2);
+    }
+    if (v != 2) return v;
+    return temp_exact(A.sr[q], tq, A.sr[c], tc, a, A.R, A.twoT, A.stats, MODE == T_COUNT);
+}
+
+// ------------------------------------------------------------ windows
+
+// Conservative half-width of band j's window of radius rho for a query with
+// record (eq, mq, sq); >= 3 means the whole band.  A point at radius r and
+// angle difference dtheta is within rho iff sin^2(dtheta/2) <= X(r) =
+// (cosh rho - cosh(r_q - r)) / (2 sinh r_q sinh r) = (K - N) / (s'_q s'(r)),
+// N = cosh(r_q - r) / cosh R, and X decreases in r (rho >= r_q), so the
+// band's inner edge gives a window for the whole band.  N carries at most
+// 4 u relative error and K is rounded up, so with K - N >= K/64 (else the
+// whole band) the computed X is within about 330 u of the exact one; the
+// factor 1 + 2^-12 and the 2^-40 absolute pad keep the window conservative,
+// as in the threshold search.
+__device__ __forceinline__ double temp_window(const TempArgs &A, float eq, float mq, float sq, int j)
+{
+    const float shl = A.sh_lo[j];
+    if (A.E[j] < 0.25 || shl == 0.0f || sq == 0.0f) return 4.0;
+    const float num = A.K - fmaf(eq, A.em_lo[j], mq * A.ep_lo[j]);
+    if (!(num >= 0x1p-6f * A.K)) return 4.0;  // also catches NaN
+    const float X = num / (sq * shl);
+    if (!(X < 0.25f)) {
+        if (!(X < 0.999f)) return 4.0;
+        return 2.0 * asin(sqrt((double)X * (1.0 + 0x1p-12))) * (1.0 + 0x1p-12) + 0x1p-40;
+    }
+    const float Xp = fmaxf(X, 0.0f);
+    return (double)(2.0f * sqrtf(Xp) * fmaf(Xp, 0.2f, 1.0f)) * (1.0 + 0x1p-12) + 0x1p-40;
+}
+
+// Position runs [a0, b0), [a1, b1) of band j that hold query q's window.
+struct TRuns {
+    int64_t a0, b0, a1, b1;
+};
+
+__device__ __forceinline__ TRuns temp_runs(const TempArgs &A, double tq, float4 fq, int j)
+{
+    TRuns t;
+    t.a0 = t.b0 = t.a1 = t.b1 = 0;
+    const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+    if (s == e) return t;
+    const double w = temp_window(A, fq.x, fq.y, fq.z, j);
+    int64_t ra[2], rb[2];
+    int nr;
+    if (w >= 3.0) {
+        ra[0] = s; rb[0] = e; nr = 1;
+    } else {
+        nr = cell_runs(A.dir + A.dir_base[j], A.cbits[j], tq - w, tq + w, s, e, ra, rb);
+    }
+    t.a0 = ra[0]; t.b0 = rb[0];
+    if (nr == 2) { t.a1 = ra[1]; t.b1 = rb[1]; }
+    return t;
+}
+
+__device__ __forceinline__ int64_t tuni64(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// ------------------------------------------------------------ heavy plan
+
+// Before the count pass: heavy_end = the first light position (the end of
+// the heavy bands, capped); row_ptr[0] = 0; the candidate total cleared.
+__global__ void temp_prologue(TempArgs A, int jh, int32_t *heavy_end, int64_t *row_ptr)
+{
+    if (threadIdx.x == 0) {
+        int64_t h = jh > 0 ? (int64_t)A.band_start[jh] : 0;
+        if (h > A.heavy_cap) h = A.heavy_cap;
+        *heavy_end = (int32_t)h;
+        row_ptr[0] = 0;
+        A.hscal[0] = 0;
+    }
+}
+
+// Candidates of every heavy item (query, band); 0 past the heavy queries.
+__global__ void __launch_bounds__(256) temp_plan_len(TempArgs A)
+{
+    __shared__ long long part[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    long long len = 0;
+    if (i < A.heavy_cap * A.B) {
+        const int64_t q = i / A.B;
+        const int j = (int)(i % A.B);
+        if (q < *A.heavy_end) {
+            const TRuns t = temp_runs(A, A.st[q], A.rec[q], j);
+            len = (t.b0 - t.a0) + (t.b1 - t.a1);
+        }
+        A.hplan[i] = len;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len += __shfl_xor(len, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = len;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd((unsigned long long *)&A.hscal[0], (unsigned long long)t);
+    }
+}
+
+// Chunks per item, with the chunk size CH chosen so the table cannot
+// overflow (each item adds at most one partial chunk).
+__global__ void __launch_bounds__(256) temp_plan_chunks(TempArgs A)
+{
+    const int64_t items = A.heavy_cap * A.B;
+    const int64_t room = A.max_chunks - items;  // > 0 by construction
+    const int64_t total = A.hscal[0];
+    int64_t ch = RHG_HEAVY_CHUNK;
+    if (total / ch >= room) ch = total / room + 1;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) A.hscal[1] = ch;
+    if (i < items) {
+        const int64_t len = A.hplan[i];
+        A.hplan[i] = len ? (len + ch - 1) / ch : 0;
+    }
+}
+
+// Chunk -> item table: after the scan, item i owns chunks [hplan[i-1], hplan[i]).
+__global__ void __launch_bounds__(256) temp_chunk_items(TempArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.heavy_cap * A.B) return;
+    const int64_t b = i ? A.hplan[i - 1] : 0, e = A.hplan[i];
+    for (int64_t c = b; c < e; ++c) A.hitem[c] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(256) temp_zero(int64_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// After the count pass and the scan of the chunk counts: heavy degrees.
+__global__ void __launch_bounds__(256) temp_heavy_degrees(TempArgs A, int64_t *__restrict__ row_ptr)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= *A.heavy_end) return;
+    const int64_t f = q ? A.hplan[q * A.B - 1] : 0;   // first chunk of q
+    const int64_t l = A.hplan[q * A.B + A.B - 1];     // one past its last chunk
+    const int64_t hi = l ? A.hcnt[l - 1] : 0, lo = f ? A.hcnt[f - 1] : 0;
+    row_ptr[__float_as_int(A.rec[q].w) + 1] = hi - lo;
+}
+
+// ------------------------------------------------------------ heavy chunks
+
+// One chunk of a heavy item: a workgroup decides its candidates 256 at a
+// time; the emit pass places them by the prefix of the count pass's chunk
+// counts (row order: band, chunk, candidate).
+template <int MODE>
+__device__ void temp_chunk(const TempArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
+{
+    constexpr bool EMIT = MODE == T_EMIT;
+    __shared__ int wave_cnt[2][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t item = tuni64(A.hitem[c]);
+    const int64_t first = item ? tuni64(A.hplan[item - 1]) : 0;
+    const int64_t q = item / A.B;
+    const int j = (int)(item % A.B);
+    const int64_t ch = tuni64(A.hscal[1]);
+    const double tq = A.st[q];
+    const float4 fq = A.rec[q];
+    const TRuns t = temp_runs(A, tq, fq, j);
+    const int64_t a0 = tuni64(t.a0), b0 = tuni64(t.b0), a1 = tuni64(t.a1), b1 = tuni64(t.b1);
+    const int64_t len0 = b0 - a0, len = len0 + (b1 - a1);
+    const int64_t v0 = (c - first) * ch, v1 = min(len, v0 + ch);
+    const int32_t id = __float_as_int(fq.w);
+    int64_t out = 0, row_end = 0;
+    if (EMIT) {
+        const int64_t qfirst = q ? tuni64(A.hplan[q * A.B - 1]) : 0;
+        const int64_t base_c = c ? tuni64(A.hcnt[c - 1]) : 0;
+        const int64_t base_q = qfirst ? tuni64(A.hcnt[qfirst - 1]) : 0;
+        out = row_ptr[id] + (base_c - base_q);
+        row_end = row_ptr[id + 1];
+        if (A.col_cap >= 0 && row_end > A.col_cap) row_end = A.col_cap;
+    }
+    int64_t total = 0;
+    for (int64_t vb = v0; vb < v1; vb += 256) {
+        const int64_t v = vb + threadIdx.x;
+        int acc = 0;
+        int32_t cid = 0;
+        if (v < v1) {
+            const int64_t pos = (v < len0) ? a0 + v : a1 + (v - len0);
+            const float4 fc = A.rec[pos];
+            cid = __float_as_int(fc.w);
+            if (pos != q) acc = temp_decide<MODE>(A, q, tq, fq, pos, A.st[pos], fc);
+        }
+        const uint64_t bal = __ballot(acc);
+        const int buf = (int)(((vb - v0) >> 8) & 1);
+        if (lane == 0) wave_cnt[buf][wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0, blk = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2) {
+            const int x = wave_cnt[buf][w2];
+            if (w2 < wave) before += x;
+            blk += x;
+        }
+        if (EMIT && acc) {
+            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+            const int64_t o = out + total + before + __popcll(bal & lt);
+            if (o < row_end) col[o] = cid;
+        }
+        total += blk;
+    }
+    __syncthreads();
+    if (!EMIT && threadIdx.x == 0) A.hcnt[c] = total;
+    if (EMIT && threadIdx.x == 0 && total != A.hcnt[c] - (c ? A.hcnt[c - 1] : 0))
+        atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+}
+
+// ------------------------------------------------------------ light queries
+
+// One lane per query: every band's window, candidate by candidate.  The
+// count pass writes the degree to row_ptr[id + 1]; the emit pass writes the
+// row and checks its length.
+template <int MODE>
+__device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32_t *col)
+{
+    constexpr bool EMIT = MODE == T_EMIT;
+    const bool active = q < A.n && q >= *A.heavy_end;
+    double tq = 0.0;
+    float4 fq = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active) {
+        tq = A.st[q];
+        fq = A.rec[q];
+    }
+    const int32_t id = __float_as_int(fq.w);
+    int64_t out = 0, row_end = 0;
+    if (EMIT && active) {
+        out = row_ptr[id];
+        row_end = row_ptr[id + 1];
+    }
+    const int64_t row_start = out;
+    const int64_t cap_end = (EMIT && A.col_cap >= 0) ? A.col_cap : INT64_MAX;
+    int64_t cnt = 0;
+    for (int j = 0; j < A.B; ++j) {
+        TRuns t;
+        t.a0 = t.b0 = t.a1 = t.b1 = 0;
+        if (active) t = temp_runs(A, tq, fq, j);
+        for (int r = 0; r < 2; ++r) {
+            const int64_t a = r ? t.a1 : t.a0, b = r ? t.b1 : t.b0;
+            for (int64_t c = a; c < b; ++c) {
+                if (c == q) continue;
+                const float4 fc = A.rec[c];
+                if (!temp_decide<MODE>(A, q, tq, fq, c, A.st[c], fc)) continue;
+                if (EMIT) {
+                    const int64_t o = row_start + cnt;
+                    if (o < row_end && o < cap_end) col[o] = __float_as_int(fc.w);
+                }
+                ++cnt;
+            }
+        }
+    }
+    if (!active) return;
+    if (!EMIT) row_ptr[id + 1] = cnt;
+    else if (cnt != row_end - row_start) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) temp_kernel(TempArgs A, int64_t *__restrict__ row_ptr,
+                                                   int32_t *__restrict__ col_idx)
+{
+    // emit pass into a buffer too small for the graph: write nothing
+    if (MODE == T_EMIT && A.col_cap >= 0 && tuni64(row_ptr[A.n]) > A.col_cap) return;
+    if ((int)blockIdx.x < A.heavy_blocks) {
+        const int64_t nch = tuni64(A.hplan[A.heavy_cap * A.B - 1]);
+        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) temp_chunk<MODE>(A, c, row_ptr, col_idx);
+        return;
+    }
+    const int64_t q = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + threadIdx.x;
+    temp_light<MODE>(A, q, row_ptr, col_idx);
+}
+
+hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_t *col_idx, int emit,
+                              hipStream_t s, int64_t col_cap)
+{
+    const Layout &L = idx->L;
+    const rhg_params &p = idx->p;
+    TempArgs A;
+    memset(&A, 0, sizeof(A));
+    const double inv = 1.0 / sqrt(2.0 * p.cosh_R), sc = sqrt(2.0 / p.cosh_R);
+    for (int j = 0; j <= L.B; ++j) {
+        A.E[j] = L.E[j];
+        A.dir_base[j] = L.dir_base[j];
+    }
+    for (int j = 0; j < L.B; ++j) {
+        A.ep_lo[j] = (float)(exp(L.E[j]) * inv);
+        A.em_lo[j] = (float)(exp(-L.E[j]) * inv);
+        A.sh_lo[j] = (float)(sinh(L.E[j]) * sc);
+        A.cbits[j] = L.cbits[j];
+    }
+    A.B = L.B;
+    A.n = idx->n;
+    A.heavy_cap = idx->heavy_cap;
+    A.max_chunks = idx->max_chunks;
+    A.heavy_blocks = idx->heavy_cap > 0 ? RHG_HEAVY_BLOCKS : 0;
+    A.R = p.R;
+    A.twoT = 2.0 * T;
+    // rho = R + 2T ln(2^53 - 1); K = cosh(rho) / cosh(R) rounded up, with
+    // 2^-20 relative to spare for the binary64 evaluation
+    const double rho = p.R + 2.0 * T * log(9007199254740991.0);
+    const double K = cosh(rho) / cosh(p.R) * (1.0 + 0x1p-20);
+    A.K = nextafterf((float)K, INFINITY);
+    A.Ktr = nextafterf((float)(K * (1.0 + 0x1p-16)), INFINITY);
+    A.twoTf = (float)(2.0 * T);
+    A.RL2E = (float)(p.R * 1.4426950408889634);
+    A.R2L2E = (float)(2.0 * p.R * 1.4426950408889634);
+    A.f1 = (float)(1.0 / (1.0 + exp(-2.0 * p.R)));
+    A.use_p32 = (!L.fp64_only && p.R < 80.0) ? 1 : 0;
+    A.k0 = (uint32_t)p.seed;
+    A.k1 = (uint32_t)(p.seed >> 32);
+    A.band_start = idx->band_start;
+    A.dir = idx->dir;
+    A.sr = idx->sr;
+    A.st = idx->st;
+    A.rec = idx->rec;
+    A.heavy_end = idx->heavy_end;
+    A.hplan = idx->hplan;
+    A.hcnt = idx->hcnt;
+    A.hitem = idx->hitem;
+    A.hscal = idx->hscal;
+    A.stats = idx->stats;
+    A.col_cap = col_cap;
+    const int64_t n = idx->n;
+    const int64_t items = idx->heavy_cap * L.B;
+    hipError_t e;
+    if (!emit) {
+        PhaseScope ps(RHG_PHASE_PLAN, s);
+        hipLaunchKernelGGL(temp_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (n <= 0) return hipSuccess;
+        if (items > 0) {
+            const unsigned g = (unsigned)((items + 255) / 256);
+            hipLaunchKernelGGL(temp_plan_len, dim3(g), dim3(256), 0, s, A);
+            hipLaunchKernelGGL(temp_plan_chunks, dim3(g), dim3(256), 0, s, A);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = inclusive_scan_i64(idx->hplan, items, idx->tmp, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(temp_chunk_items, dim3(g), dim3(256), 0, s, A);
+            hipLaunchKernelGGL(temp_zero, dim3((unsigned)((idx->max_chunks + 255) / 256)), dim3(256), 0, s,
+                               idx->hcnt, idx->max_chunks);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    } else if (n <= 0) {
+        return hipSuccess;
+    }
+    const dim3 g((unsigned)(A.heavy_blocks + (n + 255) / 256)), b(256);
+    {
+        PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
+        if (emit) hipLaunchKernelGGL(temp_kernel<T_EMIT>, g, b, 0, s, A, row_ptr, col_idx);
+        else hipLaunchKernelGGL(temp_kernel<T_COUNT>, g, b, 0, s, A, row_ptr, col_idx);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!emit && items > 0) {
+        PhaseScope ps(RHG_PHASE_PLAN, s);
+        if ((e = inclusive_scan_i64(idx->hcnt, idx->max_chunks, idx->tmp, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(temp_heavy_degrees, dim3((unsigned)((idx->heavy_cap + 255) / 256)), dim3(256), 0, s, A,
+                           row_ptr);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace rhg

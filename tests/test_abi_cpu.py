@@ -218,3 +218,28 @@ def test_layout_bands_follow_the_tuning():
     E = P.rhg_layout_bands(p, {"inner_radius": 10.0, "band_width": 2.0})
     assert E[:2] == [0.0, 10.0] and E[-1] == p.R
     assert all(0.0 < b - a <= 2.0 + 1e-12 for a, b in zip(E[1:], E[2:]))
+
+
+def test_temperature_arguments_are_checked_before_any_device_work():
+    """The temperature calls refuse T outside (0, 1) and NULL arguments on
+    the host; rhg_temp_generate does so before its allocator is called."""
+    import ctypes as C
+    lib = P.load()
+    calls = []
+
+    def _alloc(nbytes, _ctx):
+        calls.append(nbytes)
+        return None
+
+    cb = P.ALLOC_FN(_alloc)
+    out = P.rhg_csr()
+    for T in (0.0, -1.0, 1.0, 2.0, float("nan"), float("inf")):
+        assert lib.rhg_temp_generate(1000, 6.0, 2.5, T, 1, None, cb, None, 0, C.byref(out), None) == P.RHG_EINVAL
+        assert b"temperature" in lib.rhg_last_error()
+    assert calls == []
+    # a valid T reaches the planner and then the allocator (which fails here)
+    assert lib.rhg_temp_generate(1000, 6.0, 2.5, 0.5, 1, None, cb, None, 0, C.byref(out), None) == P.RHG_ENOMEM
+    assert lib.rhg_temp_generate(1000, 6.0, 1.5, 0.5, 1, None, cb, None, 0, C.byref(out), None) == P.RHG_EINVAL
+    fake = C.c_void_p(0x1000)
+    assert lib.rhg_temp_count_edges(None, 0.5, fake, None) == P.RHG_EINVAL
+    assert lib.rhg_temp_emit_edges(None, 0.5, fake, fake, 10, 0, None) == P.RHG_EINVAL

@@ -118,6 +118,11 @@ typedef struct {
                               * those longer than 4096 entries, or all of
                               * them with no_stream_stage; the rest are
                               * staged in LDS                                 */
+    int64_t temp_candidates; /* the last temperature count pass: pairs
+                              * inside the windows of radius
+                              * R + 2T ln(2^53 - 1) that were screened     */
+    int64_t temp_coins;      /* the last temperature count pass: coins drawn
+                              * (screened pairs closer than that radius)  */
 } rhg_stats;
 
 typedef struct rhg_index rhg_index;  /* opaque, host-side handle */

@@ -44,7 +44,8 @@ class rhg_tuning(C.Structure):
 class rhg_stats(C.Structure):
     _fields_ = [("fp32_undecided", C.c_int64), ("dd_fallbacks", C.c_int64), ("ties", C.c_int64),
                 ("swept", C.c_int64), ("tests", C.c_int64),
-                ("register_streams", C.c_int64)]
+                ("register_streams", C.c_int64), ("temp_candidates", C.c_int64),
+                ("temp_coins", C.c_int64)]
 
 
 class rhg_graph_summary(C.Structure):
@@ -334,7 +335,8 @@ def rhg_index_stats(idx: Index, stream=None) -> dict:
     st = rhg_stats()
     _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
     return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties,
-            "swept": st.swept, "tests": st.tests, "register_streams": st.register_streams}
+            "swept": st.swept, "tests": st.tests, "register_streams": st.register_streams,
+            "temp_candidates": st.temp_candidates, "temp_coins": st.temp_coins}
 
 
 PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count", "scan", "emit", "rows"]

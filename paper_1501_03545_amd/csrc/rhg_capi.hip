@@ -464,6 +464,8 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
     out->dd_fallbacks = (int64_t)h[ST_DD];
     out->ties = (int64_t)h[ST_TIES];
     out->register_streams = (int64_t)h[ST_REG_STREAMS];
+    out->temp_candidates = (int64_t)h[ST_TEMP_CAND];
+    out->temp_coins = (int64_t)h[ST_TEMP_COINS];
     // the last count pass's per-wavefront tallies (zero before any count pass)
     out->swept = out->tests = 0;
     if (idx->counted && idx->n > 0) {

@@ -1,8 +1,9 @@
-// rhg_geom.h -- device geometry shared by the threshold and temperature
+// rhg_geom.h -- device helpers shared by the threshold and temperature
 // searches: the angle key of the sort, the angle between two points, the
 // sorted-position runs of an angular window (through a band's cell
-// directory) and cosh of the hyperbolic distance in binary64 and in
-// double-double.
+// directory), cosh of the hyperbolic distance in binary64 and in
+// double-double, and the keys of the set of pairs decided after a count
+// pass.
 //
 // The distance law is that of Sec. 2.1 in the native representation,
 //     cosh d = cosh r_q cosh r_c - sinh r_q sinh r_c cos(dtheta),
@@ -100,6 +101,22 @@ __device__ __forceinline__ dd cosh_dist_dd(double rq, double tq, double rc, doub
     const dd dr = two_sum(rq, -rc);
     return dd_add(dd_cosh(dr),
                   dd_mul_pow2(dd_mul(dd_mul(dd_sinh(dd_make(rq)), dd_sinh(dd_make(rc))), dd_mul(s, s)), 2.0));
+}
+
+// A listed pair (query and candidate sorted positions) as a set key: never
+// 0, the empty slot.
+__device__ __forceinline__ uint64_t pair_key(int64_t q, int64_t c)
+{
+    return (1ull << 63) | ((uint64_t)(uint32_t)q << 32) | (uint32_t)c;
+}
+
+// Slot of a key in the open-addressing set: SplitMix64's finaliser (Steele,
+// Lea and Flood, OOPSLA 2014) as the hash.
+__device__ __forceinline__ uint64_t slot_hash(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
 }
 
 }  // namespace rhg

@@ -117,7 +117,7 @@ struct PhaseScope {
 
 // Device-side counters (one 64-bit word each).
 enum { ST_FP32_UNDECIDED = 0, ST_DD = 1, ST_TIES = 2, ST_BAD_INPUT = 3, ST_EMIT_MISMATCH = 4,
-       ST_REG_STREAMS = 5, ST_COUNT = 6 };
+       ST_REG_STREAMS = 5, ST_TEMP_CAND = 6, ST_TEMP_COINS = 7, ST_COUNT = 8 };
 
 }  // namespace rhg
 

@@ -147,18 +147,6 @@ __device__ __forceinline__ int p32(double tq, float eq, float mq, float sq, doub
     return L < P32_ACC ? 1 : (L > P32_REJ ? 0 : 2);
 }
 
-// A listed pair as a set key: never 0, the empty slot.
-__device__ __forceinline__ uint64_t pair_key(int64_t q, int64_t c)
-{
-    return (1ull << 63) | ((uint64_t)(uint32_t)q << 32) | (uint32_t)c;
-}
-__device__ __forceinline__ uint64_t slot_hash(uint64_t z)
-{
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
 // The pair (query at sorted position q, candidate c): the FP32 screen, then
 // the exact test.  EXACT decides it here (binary64, then double-double; the
 // calls need a stack and spill the caller's registers, so the fast kernels

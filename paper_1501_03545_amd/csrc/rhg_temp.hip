@@ -71,7 +71,19 @@ struct TempArgs {
     int32_t *hitem;
     int64_t *hscal;
     unsigned long long *stats;
+    // pairs the FP32 stage leaves undecided (as in the threshold search):
+    // listed by the count pass, decided by the resolving kernel, which adds
+    // the edges to the degrees and to the set the emit pass reads
+    uint64_t *dkeys;
+    int32_t *dchunk;
+    unsigned long long *dcount;       // [0] pairs listed, [1] the list overflowed
+    int64_t dcap;
+    uint64_t *hset;
+    int64_t hmask;
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
+    int tally;                        // count pass: this launch adds to the candidate and coin tallies
+    longlong2 *tal;                   // per-wavefront table of (candidates, coins)
+    int64_t tal_slots;
 };
 
 enum { T_COUNT = 0, T_EMIT = 1 };
@@ -114,44 +126,74 @@ __device__ __noinline__ int temp_exact(double rq, double tq, double rc, double t
     return diff.hi < 0.0;
 }
 
-// The pair (query q, candidate c, both sorted positions).  1 edge, 0 not.
-template <int MODE>
+// The pair (query q, candidate c, both sorted positions): the FP32 stage,
+// then the exact test.  EXACT decides it here (temp_exact is a call that
+// needs a stack and the caller's registers, so the fast kernels keep it
+// out): the count pass instead lists the pair for the resolving kernel and
+// counts it there if it is an edge, and the emit pass finds the resolved
+// edges in the set.  1 edge, 0 not.  The count pass tallies the coins it
+// draws in `coins`; `chunk` is the heavy chunk of the pair (-1: light).
+template <int MODE, bool EXACT>
 __device__ __forceinline__ int temp_decide(const TempArgs &A, int64_t q, double tq, float4 fq, int64_t c,
-                                           double tc, float4 fc)
+                                           double tc, float4 fc, int &coins, int64_t chunk)
 {
     const uint32_t idq = (uint32_t)__float_as_int(fq.w), idc = (uint32_t)__float_as_int(fc.w);
-    if (!A.use_p32)
-        return temp_exact(A.sr[q], tq, A.sr[c], tc, temp_coin(idq, idc, A.k0, A.k1), A.R, A.twoT, A.stats, 0);
-    // P = cosh d / cosh R: e'_q m'_c + m'_q e'_c + s'_q s'_c sin^2(dtheta/2),
-    // sin by its degree-11 Taylor polynomial (any angle up to pi)
-    const float x = (float)(0.5 * short_angle(tq, tc));
-    const float x2 = x * x;
-    float p = -1.0f / 39916800.0f;
-    p = fmaf(p, x2, 1.0f / 362880.0f);
-    p = fmaf(p, x2, -1.0f / 5040.0f);
-    p = fmaf(p, x2, 1.0f / 120.0f);
-    p = fmaf(p, x2, -1.0f / 6.0f);
-    p = fmaf(p, x2, 1.0f);
-    const float s = x * p;
-    float P = fmaf(fq.x, fc.y, fq.y * fc.x);
-    P = fmaf(fq.z * fc.z, s * s, P);
-    if (P > A.Ktr) return 0;  // d > rho: p(d) <= 2^-53 <= u
-    const uint64_t a = temp_coin(idq, idc, A.k0, A.k1);
-    const uint64_t b = (1ull << 53) - a;
-    if (b == 0) return 0;
-    // y = 2T log2(b/a) = x log2(e);  D > 0  <=>  R log2(e) + y > 0
-    const float y = (log2f((float)b) - log2f((float)a)) * A.twoTf;
-    const float Dl = A.RL2E + y;
     int v = 2;
-    if (Dl < -0x1p-10f) {
-        v = 0;
-    } else if (Dl > 0x1p-10f) {
-        const float cr = (exp2f(y) + exp2f(-A.R2L2E - y)) * A.f1;  // cosh D / cosh R
-        const float tol = 0x1p-12f * fmaxf(P, cr) + 0x1p-32f;
-        v = P < cr - tol ? 1 : (P > cr + tol ? 0 : 2);
+    uint64_t a = 0;
+    if (!A.use_p32) {
+        if (MODE == T_COUNT) ++coins;
+        a = temp_coin(idq, idc, A.k0, A.k1);
+    } else {
+        // P = cosh d / cosh R: e'_q m'_c + m'_q e'_c + s'_q s'_c sin^2(dtheta/2),
+        // sin by its degree-11 Taylor polynomial (any angle up to pi)
+        const float x = (float)(0.5 * short_angle(tq, tc));
+        const float x2 = x * x;
+        float p = -1.0f / 39916800.0f;
+        p = fmaf(p, x2, 1.0f / 362880.0f);
+        p = fmaf(p, x2, -1.0f / 5040.0f);
+        p = fmaf(p, x2, 1.0f / 120.0f);
+        p = fmaf(p, x2, -1.0f / 6.0f);
+        p = fmaf(p, x2, 1.0f);
+        const float s = x * p;
+        float P = fmaf(fq.x, fc.y, fq.y * fc.x);
+        P = fmaf(fq.z * fc.z, s * s, P);
+        if (P > A.Ktr) return 0;  // d > rho: p(d) <= 2^-53 <= u
+        if (MODE == T_COUNT) ++coins;
+        a = temp_coin(idq, idc, A.k0, A.k1);
+        const uint64_t b = (1ull << 53) - a;
+        if (b == 0) return 0;
+        // y = 2T log2(b/a) = x log2(e), the ratio formed first so that
+        // coins near 1/2 keep their small logarithm accurate;
+        // D > 0  <=>  Dl = R log2(e) + y > 0
+        const float y = log2f((float)b / (float)a) * A.twoTf;
+        const float Dl = A.RL2E + y;
+        if (Dl < -0x1p-10f) {
+            v = 0;
+        } else if (Dl > 0x1p-10f) {
+            const float cr = (exp2f(y) + exp2f(-A.R2L2E - y)) * A.f1;  // cosh D / cosh R
+            // the stage's error is below (33 + 3 |y|) 2^-24 relative (plus
+            // 2^-34 absolute) where e^{-2D} <= 2^-16, below 2^-15 elsewhere
+            const float rel = Dl >= 8.0f ? fmaf(fabsf(y), 0x1p-21f, 0x1p-17f) : 0x1p-12f;
+            const float tol = rel * fmaxf(P, cr) + 0x1p-32f;
+            v = P < cr - tol ? 1 : (P > cr + tol ? 0 : 2);
+        }
+        if (v != 2) return v;
     }
-    if (v != 2) return v;
-    return temp_exact(A.sr[q], tq, A.sr[c], tc, a, A.R, A.twoT, A.stats, MODE == T_COUNT);
+    if (EXACT) return temp_exact(A.sr[q], tq, A.sr[c], tc, a, A.R, A.twoT, A.stats, MODE == T_COUNT && A.use_p32);
+    const uint64_t key = pair_key(q, c);
+    if (MODE == T_COUNT) {
+        const unsigned long long k = atomicAdd(&A.dcount[0], 1ull);
+        if ((int64_t)k < A.dcap) {
+            A.dkeys[k] = key;
+            A.dchunk[k] = (int32_t)chunk;
+        }
+        return 0;
+    }
+    for (uint64_t h = slot_hash(key) & (uint64_t)A.hmask;; h = (h + 1) & (uint64_t)A.hmask) {
+        const uint64_t z = A.hset[h];
+        if (z == key) return 1;
+        if (z == 0) return 0;
+    }
 }
 
 // ------------------------------------------------------------ windows
@@ -224,6 +266,53 @@ __global__ void temp_prologue(TempArgs A, int jh, int32_t *heavy_end, int64_t *r
         *heavy_end = (int32_t)h;
         row_ptr[0] = 0;
         A.hscal[0] = 0;
+        A.stats[ST_TEMP_CAND] = 0;
+        A.stats[ST_TEMP_COINS] = 0;
+        A.dcount[0] = 0;
+        A.dcount[1] = 0;
+    }
+}
+
+// Count pass: a wavefront's tallies of screened candidates and coins, added
+// to slot `slot` of the per-wavefront table (one device-wide atomic counter
+// for every wavefront would serialise them), summed by temp_tally_sum.
+__device__ __forceinline__ void temp_tally(const TempArgs &A, long long cand, long long coins, int64_t slot)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        cand += __shfl_xor(cand, o, 64);
+        coins += __shfl_xor(coins, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && (cand | coins)) {
+        atomicAdd((unsigned long long *)&A.tal[slot].x, (unsigned long long)cand);
+        atomicAdd((unsigned long long *)&A.tal[slot].y, (unsigned long long)coins);
+    }
+}
+
+// After the count pass: the table's sums into the index's diagnostics.
+__global__ void __launch_bounds__(256) temp_tally_sum(TempArgs A, int64_t slots)
+{
+    __shared__ long long part[2][4];
+    long long c = 0, k = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < slots; i += (int64_t)gridDim.x * 256) {
+        c += A.tal[i].x;
+        k += A.tal[i].y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        k += __shfl_xor(k, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = c;
+        part[1][threadIdx.x >> 6] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        k = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        if (c) atomicAdd(&A.stats[ST_TEMP_CAND], (unsigned long long)c);
+        if (k) atomicAdd(&A.stats[ST_TEMP_COINS], (unsigned long long)k);
     }
 }
 
@@ -300,7 +389,7 @@ __global__ void __launch_bounds__(256) temp_heavy_degrees(TempArgs A, int64_t *_
 // One chunk of a heavy item: a workgroup decides its candidates 256 at a
 // time; the emit pass places them by the prefix of the count pass's chunk
 // counts (row order: band, chunk, candidate).
-template <int MODE>
+template <int MODE, bool EXACT>
 __device__ void temp_chunk(const TempArgs &A, int64_t c, const int64_t *row_ptr, int32_t *col)
 {
     constexpr bool EMIT = MODE == T_EMIT;
@@ -328,6 +417,7 @@ __device__ void temp_chunk(const TempArgs &A, int64_t c, const int64_t *row_ptr,
         if (A.col_cap >= 0 && row_end > A.col_cap) row_end = A.col_cap;
     }
     int64_t total = 0;
+    int cand = 0, coins = 0;
     for (int64_t vb = v0; vb < v1; vb += 256) {
         const int64_t v = vb + threadIdx.x;
         int acc = 0;
@@ -336,7 +426,10 @@ __device__ void temp_chunk(const TempArgs &A, int64_t c, const int64_t *row_ptr,
             const int64_t pos = (v < len0) ? a0 + v : a1 + (v - len0);
             const float4 fc = A.rec[pos];
             cid = __float_as_int(fc.w);
-            if (pos != q) acc = temp_decide<MODE>(A, q, tq, fq, pos, A.st[pos], fc);
+            if (pos != q) {
+                ++cand;
+                acc = temp_decide<MODE, EXACT>(A, q, tq, fq, pos, A.st[pos], fc, coins, c);
+            }
         }
         const uint64_t bal = __ballot(acc);
         const int buf = (int)(((vb - v0) >> 8) & 1);
@@ -357,6 +450,7 @@ __device__ void temp_chunk(const TempArgs &A, int64_t c, const int64_t *row_ptr,
         total += blk;
     }
     __syncthreads();
+    if (!EMIT && A.tally) temp_tally(A, cand, coins, c % A.tal_slots);
     if (!EMIT && threadIdx.x == 0) A.hcnt[c] = total;
     if (EMIT && threadIdx.x == 0 && total != A.hcnt[c] - (c ? A.hcnt[c - 1] : 0))
         atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
@@ -367,7 +461,7 @@ __device__ void temp_chunk(const TempArgs &A, int64_t c, const int64_t *row_ptr,
 // One lane per query: every band's window, candidate by candidate.  The
 // count pass writes the degree to row_ptr[id + 1]; the emit pass writes the
 // row and checks its length.
-template <int MODE>
+template <int MODE, bool EXACT>
 __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32_t *col)
 {
     constexpr bool EMIT = MODE == T_EMIT;
@@ -387,6 +481,7 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
     const int64_t row_start = out;
     const int64_t cap_end = (EMIT && A.col_cap >= 0) ? A.col_cap : INT64_MAX;
     int64_t cnt = 0;
+    int cand = 0, coins = 0;
     for (int j = 0; j < A.B; ++j) {
         TRuns t;
         t.a0 = t.b0 = t.a1 = t.b1 = 0;
@@ -396,7 +491,8 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
             for (int64_t c = a; c < b; ++c) {
                 if (c == q) continue;
                 const float4 fc = A.rec[c];
-                if (!temp_decide<MODE>(A, q, tq, fq, c, A.st[c], fc)) continue;
+                ++cand;
+                if (!temp_decide<MODE, EXACT>(A, q, tq, fq, c, A.st[c], fc, coins, -1)) continue;
                 if (EMIT) {
                     const int64_t o = row_start + cnt;
                     if (o < row_end && o < cap_end) col[o] = __float_as_int(fc.w);
@@ -405,24 +501,55 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
             }
         }
     }
+    if (!EMIT && A.tally) temp_tally(A, cand, coins, (q >> 6) % A.tal_slots);
     if (!active) return;
     if (!EMIT) row_ptr[id + 1] = cnt;
     else if (cnt != row_end - row_start) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
 }
 
-template <int MODE>
+// Heavy chunks on the first heavy_blocks workgroups, light queries (256 a
+// workgroup) striding over the rest.  With `gate` the kernel runs only if
+// the count pass's undecided-pair list overflowed (EXACT) or did not (fast).
+template <int MODE, bool EXACT>
 __global__ void __launch_bounds__(256) temp_kernel(TempArgs A, int64_t *__restrict__ row_ptr,
-                                                   int32_t *__restrict__ col_idx)
+                                                   int32_t *__restrict__ col_idx, int gate)
 {
     // emit pass into a buffer too small for the graph: write nothing
     if (MODE == T_EMIT && A.col_cap >= 0 && tuni64(row_ptr[A.n]) > A.col_cap) return;
+    if (gate && (__builtin_amdgcn_readfirstlane((int)A.dcount[1]) != 0) != EXACT) return;
     if ((int)blockIdx.x < A.heavy_blocks) {
         const int64_t nch = tuni64(A.hplan[A.heavy_cap * A.B - 1]);
-        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) temp_chunk<MODE>(A, c, row_ptr, col_idx);
+        for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) temp_chunk<MODE, EXACT>(A, c, row_ptr, col_idx);
         return;
     }
-    const int64_t q = ((int64_t)blockIdx.x - A.heavy_blocks) * 256 + threadIdx.x;
-    temp_light<MODE>(A, q, row_ptr, col_idx);
+    const int64_t lb = (A.n + 255) / 256, nb = (int64_t)gridDim.x - A.heavy_blocks;
+    for (int64_t b = (int64_t)blockIdx.x - A.heavy_blocks; b < lb; b += nb)
+        temp_light<MODE, EXACT>(A, b * 256 + threadIdx.x, row_ptr, col_idx);
+}
+
+// After the fast count pass: decide the listed pairs exactly, count the
+// edges among them (the light query's degree, or the heavy chunk's count)
+// and enter them in the set the emit pass reads.  Flags an overflowed list.
+__global__ void __launch_bounds__(256) temp_resolve(TempArgs A, int64_t *__restrict__ row_ptr)
+{
+    const unsigned long long cnt = A.dcount[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)cnt > A.dcap) A.dcount[1] = 1;
+    if ((int64_t)cnt > A.dcap) return;
+    const int64_t m = (int64_t)cnt, stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += stride) {
+        const uint64_t key = A.dkeys[i];
+        const int64_t q = (int64_t)((key >> 32) & 0x7fffffffull), c = (int64_t)(key & 0xffffffffull);
+        const float4 fq = A.rec[q], fc = A.rec[c];
+        const uint64_t a = temp_coin((uint32_t)__float_as_int(fq.w), (uint32_t)__float_as_int(fc.w), A.k0, A.k1);
+        if (!temp_exact(A.sr[q], A.st[q], A.sr[c], A.st[c], a, A.R, A.twoT, A.stats, 1)) continue;
+        for (uint64_t h = slot_hash(key) & (uint64_t)A.hmask;; h = (h + 1) & (uint64_t)A.hmask) {
+            const unsigned long long prev = atomicCAS((unsigned long long *)&A.hset[h], 0ull, (unsigned long long)key);
+            if (prev == 0ull || prev == key) break;
+        }
+        const int32_t ch = A.dchunk[i];
+        if (ch >= 0) atomicAdd((unsigned long long *)&A.hcnt[ch], 1ull);
+        else atomicAdd((unsigned long long *)&row_ptr[__float_as_int(fq.w) + 1], 1ull);
+    }
 }
 
 hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_t *col_idx, int emit,
@@ -474,7 +601,16 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
     A.hitem = idx->hitem;
     A.hscal = idx->hscal;
     A.stats = idx->stats;
+    A.dkeys = idx->dkeys;
+    A.dchunk = idx->dchunk;
+    A.dcount = idx->dcount;
+    A.dcap = L.defer_cap;
+    A.hset = idx->hset;
+    A.hmask = idx->hset_slots - 1;
     A.col_cap = col_cap;
+    A.tally = 1;
+    A.tal = (longlong2 *)idx->wstat;
+    A.tal_slots = std::max<int64_t>((idx->n + 63) / 64, 1);
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
     hipError_t e;
@@ -498,10 +634,44 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
         return hipSuccess;
     }
     const dim3 g((unsigned)(A.heavy_blocks + (n + 255) / 256)), b(256);
+    // the EXACT kernels, when they only stand by for an overflowed list, run
+    // on a smaller grid (a smaller heavy pool; the light part strides)
+    TempArgs Ax = A;
+    Ax.heavy_blocks = std::min(A.heavy_blocks, 64);
+    Ax.tally = 0;
+    const dim3 gx((unsigned)(Ax.heavy_blocks + std::min<int64_t>((n + 255) / 256, 64)));
+    // with no FP32 stage (or on request) every pair is decided in place
+    const bool exact_only = !A.use_p32 || L.exact_inline;
+    if (!emit && !exact_only)
+        hipLaunchKernelGGL(temp_zero, dim3((unsigned)((A.hmask + 256) / 256)), dim3(256), 0, s, (int64_t *)A.hset,
+                           A.hmask + 1);
+    if (!emit)
+        hipLaunchKernelGGL(temp_zero, dim3((unsigned)((2 * A.tal_slots + 255) / 256)), dim3(256), 0, s,
+                           (int64_t *)A.tal, 2 * A.tal_slots);
     {
         PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
-        if (emit) hipLaunchKernelGGL(temp_kernel<T_EMIT>, g, b, 0, s, A, row_ptr, col_idx);
-        else hipLaunchKernelGGL(temp_kernel<T_COUNT>, g, b, 0, s, A, row_ptr, col_idx);
+        if (exact_only) {
+            if (emit) hipLaunchKernelGGL((temp_kernel<T_EMIT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
+            else hipLaunchKernelGGL((temp_kernel<T_COUNT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
+        } else if (emit) {
+            hipLaunchKernelGGL((temp_kernel<T_EMIT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
+        } else {
+            hipLaunchKernelGGL((temp_kernel<T_COUNT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!exact_only) {
+        PhaseScope ps(RHG_PHASE_PLAN, s);
+        if (!emit) {
+            hipLaunchKernelGGL(temp_resolve, dim3(256), dim3(256), 0, s, A, row_ptr);
+            hipLaunchKernelGGL((temp_kernel<T_COUNT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+        } else {
+            hipLaunchKernelGGL((temp_kernel<T_EMIT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!emit) {
+        hipLaunchKernelGGL(temp_tally_sum, dim3(256), dim3(256), 0, s, A, A.tal_slots);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!emit && items > 0) {

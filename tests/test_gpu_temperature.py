@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 import paper_1501_03545_amd as P
-from gpu_util import canonical, check_simple_symmetric, oracle_check
+from gpu_util import canonical, check_simple_symmetric
 
 pytestmark = pytest.mark.gpu
 
@@ -76,8 +76,9 @@ def test_temperature_edge_set_equals_oracle(case):
     assert np.array_equal(canonical(rp, col), ocol)
 
 
-TUNINGS = [{"fp64_only": 1}, {"heavy_points": 64}, {"heavy_points": 1 << 16}, {"band_width": 1.0},
-           {"band_width": 3.0, "cell_target": 4}, {"inner_radius": 1e-9}]
+TUNINGS = [{"fp64_only": 1}, {"exact_inline": 1}, {"defer_cap": 1}, {"heavy_points": 64},
+           {"heavy_points": 1 << 16}, {"band_width": 1.0}, {"band_width": 3.0, "cell_target": 4},
+           {"inner_radius": 1e-9}]
 
 
 def test_temperature_tunings_give_the_same_edges():
@@ -97,18 +98,67 @@ def test_temperature_tunings_give_the_same_edges():
     assert np.array_equal(col, ocol)
 
 
-def test_temperature_exact_stages_are_reached_and_agree():
-    # a cold graph: the coin's boundary D(u) stays near R, where many
-    # candidates lie, so the FP32 screen leaves pairs undecided
+def test_temperature_cold_graph_in_every_exact_mode():
+    # a cold graph: the coins' boundaries D(u) stay near R, where many pairs lie
     n, k, g, T, seed = 20_000, 10.0, 2.3, 0.01, 11
     p, a, R, r, t = _oracle_points(n, k, g, seed)
     orp, ocol, _, ties = O.temp_csr(r, t, R, T, seed)
     assert ties == 0
-    rp, col, st = _run_temp(p, r, t, T)
-    _say("stats", st)
-    assert st["fp32_undecided"] > 0
-    assert np.array_equal(rp, orp)
-    assert np.array_equal(canonical(rp, col), ocol)
+    for tu in (None, {"exact_inline": 1}, {"defer_cap": 2}):
+        rp, col, st = _run_temp(p, r, t, T, tuning=tu)
+        _say("stats", tu, st)
+        assert st["ties"] == 0
+        assert 0 < st["temp_coins"] <= st["temp_candidates"]
+        assert np.array_equal(rp, orp)
+        assert np.array_equal(canonical(rp, col), ocol)
+
+
+def _near_boundary_points(n, k, g, T, seed, m, rng):
+    """The sampler's points, then m of them moved so that their pair with
+    point 0 lies at a relative distance 2^-e (e = 12 .. 44) from the pair's
+    coin boundary D(u) = R + 2T ln((1 - u)/u): the FP32 stage cannot decide
+    these pairs, and the closest ones reach double-double."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    a, R = O.solve_R(n, k, g)
+    r, t, _ = O.sample(seed, a, R, n)
+    r, t = r.copy(), t.copy()
+    r[0], t[0] = 0.8 * R, 1.0
+    placed = 0
+    for j in range(1, n):
+        if placed == m:
+            break
+        cu = mp.mpf(O.temp_coin(seed, 0, j)) / 2**53
+        D = mp.mpf(R) + 2 * mp.mpf(T) * mp.log((1 - cu) / cu)
+        rj = float(R * (0.55 + 0.45 * rng.random()))
+        e = int(rng.integers(12, 45))
+        target = D * (1 + (1 if rng.random() < 0.5 else -1) * mp.mpf(2) ** (-e))
+        if not (abs(r[0] - rj) < target < r[0] + rj):
+            continue
+        c = (mp.cosh(target) - mp.cosh(mp.mpf(r[0]) - rj)) / (2 * mp.sinh(r[0]) * mp.sinh(rj))
+        tj = float(t[0] + 2 * mp.asin(mp.sqrt(c)) * (1 if rng.random() < 0.5 else -1))
+        if not (0.0 <= tj < 6.283185307179586):
+            continue
+        r[j], t[j] = rj, tj
+        placed += 1
+    assert placed == m
+    return P.rhg_plan_radius(n, a, R, seed), R, r, t
+
+
+@pytest.mark.parametrize("T", [0.05, 0.5])
+def test_temperature_pairs_at_the_coin_boundary(T):
+    rng = np.random.default_rng(int(T * 100))
+    p, R, r, t = _near_boundary_points(4_000, 8.0, 2.5, T, 31, 300, rng)
+    orp, ocol, quad, ties = O.temp_csr(r, t, R, T, 31)
+    assert ties == 0 and quad > 0
+    for tu in (None, {"fp64_only": 1}, {"exact_inline": 1}):
+        rp, col, st = _run_temp(p, r, t, T, tuning=tu)
+        _say("near boundary", T, tu, st)
+        assert st["ties"] == 0
+        if tu is None:
+            assert st["fp32_undecided"] > 0 and st["dd_fallbacks"] > 0
+        assert np.array_equal(rp, orp)
+        assert np.array_equal(canonical(rp, col), ocol)
 
 
 def test_temperature_whole_pipeline_against_oracle():

@@ -285,6 +285,86 @@ def run_serve(duration_s, rate_hz=200.0, slots=16, budget=200e9, hold_s=1.0, sat
     return st, capacity
 
 
+# Temperature model: the coins' Philox blocks bound the rate.  One coin is a
+# Philox4x32-10 block: 10 rounds of two 32 x 32 -> 64-bit products (one
+# v_mad_u64_u32 each) and four 32-bit xors, 60 vector instructions.  The
+# chip issues 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 32-bit lane
+# operations per second (the 157.3 TFLOP/s FP32 figure counts each as a
+# packed pair of FMAs, 4 flops).
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+COIN_VALU_OPS = 60
+COIN_PEAK_PER_S = VALU_LANE_OPS_PER_S / COIN_VALU_OPS
+
+
+def run_temperature(cfg, T, reps=3, band_width=0.7, oracle_pts=40_000):
+    """The temperature model on the single-graph workload: index once, then
+    count + scan + emit passes timed with the library's phase events; the
+    oracle's brute force timed on the first `oracle_pts` points."""
+    import statistics
+    import torch
+    import paper_1501_03545_amd as P
+    n = cfg["n"]
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    tuning = {"band_width": band_width}
+    p = P.rhg_plan(n, cfg["avg_degree"], cfg["gamma"], cfg["seed"])
+    r = torch.empty(n, dtype=torch.float64, device=dev)
+    th = torch.empty(n, dtype=torch.float64, device=dev)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    P.rhg_sample_points(p, r, th, stream)
+    idx = P.rhg_build_index(p, r, th, tuning=tuning, validate=False, stream=stream)
+    P.rhg_temp_count_edges(idx, T, row_ptr, stream)
+    nnz = int(row_ptr[n].item())
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    P.rhg_temp_emit_edges(idx, T, row_ptr, col[:nnz], stream=stream)
+    torch.cuda.synchronize()
+    P.rhg_set_profiling(True)
+    walls = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.rhg_temp_count_edges(idx, T, row_ptr, stream)
+        P.rhg_temp_emit_edges(idx, T, row_ptr, col[:nnz], stream=stream)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+    phases = P.rhg_phase_times()
+    P.rhg_set_profiling(False)
+    st = P.rhg_index_stats(idx, stream)
+    idx.free()
+    del col
+    torch.cuda.empty_cache()
+    m = nnz // 2
+    ms = statistics.median(walls)
+    count_ms = phases["count"][0]
+    coin_rate = st["temp_coins"] / (count_ms / 1e3)
+    # the oracle: every pair with its coin, on the first oracle_pts points
+    import oracle as O
+    O.build(force=False)
+    k = min(oracle_pts, n)
+    ro, to, _ = O.sample(cfg["seed"], p.alpha, p.R, k, nthreads=O.threads())
+    t0 = time.perf_counter()
+    O.temp_csr(ro, to, p.R, T, cfg["seed"], nthreads=O.threads())
+    o_s = time.perf_counter() - t0
+    o_rate = k * (k - 1) / 2 / o_s
+    return {"workload": "rhg n=%d avg_degree=%g gamma=%g seed=%d, temperature T=%g (Fermi-Dirac p(d), one Philox "
+                        "coin per pair), band_width %g" % (n, cfg["avg_degree"], cfg["gamma"], cfg["seed"], T,
+                                                           band_width),
+            "undirected_edges": m, "ms_count_scan_emit": ms, "edges_per_s": m / (ms / 1e3),
+            "phases_ms": {kk: round(v[0] * v[1] / reps, 4) for kk, v in phases.items() if v[1]},
+            "candidates": st["temp_candidates"], "coins": st["temp_coins"], "fp32_undecided": st["fp32_undecided"],
+            "dd_fallbacks": st["dd_fallbacks"], "ties": st["ties"],
+            "roofline": {"bound": "alu", "kernel": "temp_kernel (count pass)", "achieved": coin_rate,
+                         "peak": COIN_PEAK_PER_S, "unit": "coins/s", "frac": coin_rate / COIN_PEAK_PER_S,
+                         "avg_launch_ms": count_ms,
+                         "peak_basis": "Philox4x32-10 alone: 60 VALU instructions per coin (20 v_mad_u64_u32, "
+                                       "40 v_xor_b32) at 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-ops/s"},
+            "cpu_baseline": {"kind": "oracle", "cores": O.threads(),
+                             "sample": "oracle temp_csr (every pair with its coin) over the first %d points: %.2f s"
+                                       % (k, o_s),
+                             "pairs_per_s": o_rate,
+                             "value": m / (n * (n - 1) / 2 / o_rate), "unit": "undirected edges/s (extrapolated)"}}
+
+
 def copy_calibration(nbytes=4 << 30, reps=5):
     """A plain device-to-device copy of known size: its event-timed rate is
     the practical HBM ceiling, and under rocprofv3 --pmc its FETCH_SIZE and
@@ -364,6 +444,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving run (0: skip)")
     ap.add_argument("--band-width", type=float, default=0.0)
+    ap.add_argument("--temperature", type=float, default=0.1, help="temperature-model leg at this T (0: skip)")
     ap.add_argument("--cell-target", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -444,9 +525,16 @@ def main():
     }
     _log("validation statistics with triangles (n=1e7)")
     out["validation_triangles"] = run_validation_triangles()
-    if args.batch > 0:
+    if args.temperature > 0:
         import torch
         del res
+        torch.cuda.empty_cache()
+        _log("temperature model, T =", args.temperature)
+        out["temperature"] = run_temperature(cfg, args.temperature)
+        _log("temperature done: %.2f ms, %.3g edges/s" % (out["temperature"]["ms_count_scan_emit"],
+                                                          out["temperature"]["edges_per_s"]))
+    if args.batch > 0:
+        import torch
         torch.cuda.empty_cache()
         _log("batch of", args.batch)
         out["batch"] = run_batch(args.batch, args.batch_reps)

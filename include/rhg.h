@@ -389,7 +389,10 @@ rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t see
  *
  * rhg_temp_generate: rhg_generate with this rule (plan, sample, index,
  * count, scan, emit; canonical rows beyond the index's scratch get a row-sort
- * workspace of their own from `alloc`). */
+ * workspace of their own from `alloc`).  A band_width of 0 (or a NULL
+ * tuning) means 0.7 here: the windows are taken at each band's inner edge,
+ * and narrower bands than the threshold search's default leave fewer
+ * candidates outside them. */
 rhg_status rhg_temp_count_edges(rhg_index *idx, double T, int64_t *row_ptr, void *stream);
 rhg_status rhg_temp_emit_edges(rhg_index *idx, double T, const int64_t *row_ptr, int32_t *col_idx,
                                int64_t col_capacity, int canonical_rows, void *stream);

@@ -842,6 +842,14 @@ rhg_status rhg_temp_generate(int64_t n, double avg_degree, double gamma, double 
     if (st != RHG_OK) return st;
     rhg_params p;
     if ((st = plan(n, avg_degree, gamma, seed, &p)) != RHG_OK) return st;
+    // the temperature search's windows (radius R + 2T ln(2^53 - 1)) are
+    // computed at each band's inner edge, so narrower bands than the
+    // threshold search's test fewer candidates outside them
+    rhg_tuning tt;
+    memset(&tt, 0, sizeof(tt));
+    if (t) tt = *t;
+    if (!(tt.band_width > 0.0)) tt.band_width = RHG_TEMP_BAND_WIDTH;
+    t = &tt;
     hipStream_t s = (hipStream_t)stream;
     const size_t N = (size_t)(n > 0 ? n : 1);
     double *r = (double *)alloc(N * 8, alloc_ctx);

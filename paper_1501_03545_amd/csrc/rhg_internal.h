@@ -16,6 +16,7 @@
 #define RHG_KAP_SUB 4             // sub-intervals per band of the entry estimate
 #define RHG_ROWS_TILE 8192        // LDS tile (entries) of the row sort
 #define RHG_SMALL_GRAPH 16384     // a batch's graphs of at most this many points share one persistent launch
+#define RHG_TEMP_BAND_WIDTH 0.7   // rhg_temp_generate's default band width
 
 namespace rhg {
 

@@ -163,15 +163,17 @@ __device__ __forceinline__ int temp_decide(const TempArgs &A, int64_t q, double 
         const uint64_t b = (1ull << 53) - a;
         if (b == 0) return 0;
         // y = 2T log2(b/a) = x log2(e), the ratio formed first so that
-        // coins near 1/2 keep their small logarithm accurate;
-        // D > 0  <=>  Dl = R log2(e) + y > 0
-        const float y = log2f((float)b / (float)a) * A.twoTf;
+        // coins near 1/2 keep their small logarithm accurate (a and b are
+        // exact in binary64, so each float is rounded once; v_rcp_f32 is
+        // within 1 ulp); D > 0  <=>  Dl = R log2(e) + y > 0
+        const float af = (float)(double)a, bf = (float)(double)b;
+        const float y = log2f(bf * __builtin_amdgcn_rcpf(af)) * A.twoTf;
         const float Dl = A.RL2E + y;
         if (Dl < -0x1p-10f) {
             v = 0;
         } else if (Dl > 0x1p-10f) {
             const float cr = (exp2f(y) + exp2f(-A.R2L2E - y)) * A.f1;  // cosh D / cosh R
-            // the stage's error is below (33 + 3 |y|) 2^-24 relative (plus
+            // the stage's error is below (36 + 3 |y|) 2^-24 relative (plus
             // 2^-34 absolute) where e^{-2D} <= 2^-16, below 2^-15 elsewhere
             const float rel = Dl >= 8.0f ? fmaf(fabsf(y), 0x1p-21f, 0x1p-17f) : 0x1p-12f;
             const float tol = rel * fmaxf(P, cr) + 0x1p-32f;
@@ -488,11 +490,23 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
         if (active) t = temp_runs(A, tq, fq, j);
         for (int r = 0; r < 2; ++r) {
             const int64_t a = r ? t.a1 : t.a0, b = r ? t.b1 : t.b0;
+            // each candidate's record is loaded one step ahead
+            float4 fn = make_float4(0.f, 0.f, 0.f, 0.f);
+            double tn = 0.0;
+            if (a < b) {
+                fn = A.rec[a];
+                tn = A.st[a];
+            }
             for (int64_t c = a; c < b; ++c) {
+                const float4 fc = fn;
+                const double tc = tn;
+                if (c + 1 < b) {
+                    fn = A.rec[c + 1];
+                    tn = A.st[c + 1];
+                }
                 if (c == q) continue;
-                const float4 fc = A.rec[c];
                 ++cand;
-                if (!temp_decide<MODE, EXACT>(A, q, tq, fq, c, A.st[c], fc, coins, -1)) continue;
+                if (!temp_decide<MODE, EXACT>(A, q, tq, fq, c, tc, fc, coins, -1)) continue;
                 if (EMIT) {
                     const int64_t o = row_start + cnt;
                     if (o < row_end && o < cap_end) col[o] = __float_as_int(fc.w);

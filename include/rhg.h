@@ -401,6 +401,54 @@ rhg_status rhg_temp_generate(int64_t n, double avg_degree, double gamma, double 
                              int canonical_rows, rhg_csr *out /* host */, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Dynamic model: vertices move, the graph follows.                    */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 5 notes that the incremental construction of the polar quadtree
+ * admits a dynamic model with vertex movement (future work there).  Here a
+ * state holds n points, their index and the threshold graph on them as a
+ * CSR with ascending rows; each rhg_dyn_move applies a batch of moves (ids
+ * with new coordinates) and leaves exactly the graph that generation from
+ * scratch on the moved points gives (same edge rule and exactness as
+ * rhg_count_edges), updating the index by a merge instead of a rebuild and
+ * recomputing only the rows that change (the moved vertices' rows and the
+ * rows that lose or gain a moved neighbour).  The movement itself is the
+ * caller's: the paper fixes none.
+ *
+ * The state's device memory is the library's own (hipMalloc at creation,
+ * grown when a step needs more, released by rhg_dyn_free); about
+ * 100 B per point plus two CSR column buffers.
+ *
+ * rhg_dyn_create: p (host) as from rhg_plan / rhg_plan_radius with
+ * 1 <= n <= 2^31 - 1; r, theta: device, n doubles each, copied (the caller
+ * keeps them); 0 <= r <= R and 0 <= theta < 2 pi are checked (RHG_EINVAL).
+ * Synchronises.  *out receives the state.
+ *
+ * rhg_dyn_move: k moves (0 <= k <= n; k = 0 does nothing): ids (device
+ * int32, distinct, in [0, n)), r and theta (device doubles, the new
+ * coordinates, 0 <= r <= R, 0 <= theta < 2 pi).  A batch that breaks these
+ * rules is refused with RHG_EINVAL and leaves the state unchanged.  Runs on
+ * `stream` and synchronises it a few times (to size the step's buffers).
+ * Calls on one state must not overlap.  After a device error the state is
+ * undefined.
+ *
+ * rhg_dyn_graph: the current graph (*out, host): device pointers to
+ * row_ptr (n + 1), col_idx (nnz, ascending rows), r and theta (the current
+ * points), and the params.  Valid until the next rhg_dyn_move or
+ * rhg_dyn_free; the caller must not write through them.
+ *
+ * rhg_dyn_last_step: rows rewritten by the last move (the changed unmoved
+ * rows plus the k moved rows) and entries of the moved rows. */
+typedef struct rhg_dyn rhg_dyn;
+rhg_status rhg_dyn_create(const rhg_params *p /* host */, const rhg_tuning *t /* host, may be NULL */,
+                          const double *r, const double *theta, rhg_dyn **out /* host */, void *stream);
+rhg_status rhg_dyn_move(rhg_dyn *d, int64_t k, const int32_t *ids, const double *r, const double *theta,
+                        void *stream);
+rhg_status rhg_dyn_graph(rhg_dyn *d, rhg_csr *out /* host */);
+rhg_status rhg_dyn_last_step(rhg_dyn *d, int64_t *changed_rows /* host */, int64_t *moved_entries /* host */);
+void rhg_dyn_free(rhg_dyn *d);
+
+/* ------------------------------------------------------------------ */
 /* Phase timing (HIP events on the caller's stream).                   */
 /* ------------------------------------------------------------------ */
 

@@ -455,3 +455,19 @@ def temp_rows(r, theta, R, T, seed, which, nthreads: int = 0):
         if tot >= 0:
             return ptr, col[:tot].copy(), int(st[0]), int(st[1])
         cap = int(ptr[-1]) + 1
+
+
+# --------------------------------------------------------------------------
+# Dynamic model (vertex movement, Sec. 5): after a batch of moves the graph
+# is, by definition, the threshold graph of the moved points, so the oracle
+# applies the moves and regenerates by brute force.
+# --------------------------------------------------------------------------
+
+def apply_moves(r, theta, ids, r_new, theta_new):
+    """The points after the moves (new arrays)."""
+    r = np.array(r, dtype=np.float64, copy=True)
+    theta = np.array(theta, dtype=np.float64, copy=True)
+    ids = np.asarray(ids, dtype=np.int64)
+    r[ids] = np.asarray(r_new, dtype=np.float64)
+    theta[ids] = np.asarray(theta_new, dtype=np.float64)
+    return r, theta

@@ -126,6 +126,11 @@ def load():
         "rhg_temp_count_edges": (i32, [vp, d, vp, vp]),
         "rhg_temp_emit_edges": (i32, [vp, d, vp, vp, i64, i32, vp]),
         "rhg_temp_generate": (i32, [i64, d, d, d, u64, P(rhg_tuning), ALLOC_FN, vp, i32, P(rhg_csr), vp]),
+        "rhg_dyn_create": (i32, [P(rhg_params), P(rhg_tuning), vp, vp, P(vp), vp]),
+        "rhg_dyn_move": (i32, [vp, i64, vp, vp, vp, vp]),
+        "rhg_dyn_graph": (i32, [vp, P(rhg_csr)]),
+        "rhg_dyn_last_step": (i32, [vp, P(i64), P(i64)]),
+        "rhg_dyn_free": (None, [vp]),
         "rhg_set_profiling": (i32, [i32]),
         "rhg_phase_times": (i32, [P(C.c_double), P(C.c_int64), i32]),
         "rhg_phase_name": (C.c_char_p, [i32]),
@@ -469,6 +474,49 @@ def _view(ptr, n, typestr):
         dt = {"<i8": torch.int64, "<i4": torch.int32, "<f8": torch.float64}[typestr]
         return torch.empty(0, dtype=dt, device="cuda")
     return torch.as_tensor(DeviceView(ptr, n, typestr), device="cuda")
+
+
+class DynGraph:
+    """The dynamic model (rhg_dyn_*): a graph whose vertices move.  move()
+    applies a batch of (id, r, theta) moves; graph() gives device views of
+    the current CSR (ascending rows) and points, valid until the next move."""
+
+    def __init__(self, p: rhg_params, r, theta, tuning: Optional[dict] = None, stream=None):
+        self.handle = C.c_void_p()
+        self.params = p
+        _check(load().rhg_dyn_create(C.byref(p), _tuning(tuning), _ptr(r), _ptr(theta), C.byref(self.handle),
+                                     _stream(stream)))
+
+    def move(self, ids, r, theta, stream=None):
+        import torch
+        assert ids.dtype == torch.int32 and r.dtype == torch.float64 and theta.dtype == torch.float64
+        k = ids.numel()
+        assert r.numel() == k and theta.numel() == k
+        _check(load().rhg_dyn_move(self.handle, k, _ptr(ids), _ptr(r), _ptr(theta), _stream(stream)))
+
+    def graph(self) -> Graph:
+        out = rhg_csr()
+        _check(load().rhg_dyn_graph(self.handle, C.byref(out)))
+        n = out.n
+        return Graph(params=out.params, row_ptr=_view(out.row_ptr, n + 1, "<i8"),
+                     col_idx=_view(out.col_idx, out.nnz, "<i4"), r=_view(out.r, n, "<f8"),
+                     theta=_view(out.theta, n, "<f8"))
+
+    def last_step(self) -> dict:
+        a, b = C.c_int64(), C.c_int64()
+        _check(load().rhg_dyn_last_step(self.handle, C.byref(a), C.byref(b)))
+        return {"changed_rows": a.value, "moved_entries": b.value}
+
+    def close(self):
+        if self.handle:
+            load().rhg_dyn_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class RhgServer:

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librhg.so")
 SOURCES = ["rhg_plan.hip", "rhg_sample.hip", "rhg_sort.hip", "rhg_index.hip", "rhg_search.hip",
-           "rhg_rows.hip", "rhg_lr.hip", "rhg_stats.hip", "rhg_capi.hip", "rhg_server.hip", "rhg_temp.hip"]
+           "rhg_rows.hip", "rhg_lr.hip", "rhg_stats.hip", "rhg_capi.hip", "rhg_server.hip", "rhg_temp.hip",
+           "rhg_dyn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -24,6 +24,34 @@ __device__ __forceinline__ uint32_t angle_key_s(double t)
     return (uint32_t)k;
 }
 
+// Band of radius r: the largest j with E[j] <= r (exact comparisons).
+__device__ __forceinline__ int band_of_r(const double *E, int B, double r)
+{
+    int lo = 0, hi = B - 1;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (E[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Sort key of a point: its band in the top band_bits bits, then the top
+// angle bits.  Sorted (key, id) pairs order the index by band, then angle.
+__device__ __forceinline__ uint32_t point_key(const double *E, int B, int band_bits, double r, double t)
+{
+    const uint32_t b = (uint32_t)band_of_r(E, B, r);
+    const uint32_t ak = angle_key_s(t);
+    return band_bits ? ((b << (32 - band_bits)) | (ak >> band_bits)) : ak;
+}
+
+// The FP32 screen record of a point: e^r / sqrt(2 cosh R), e^-r /
+// sqrt(2 cosh R), sinh r sqrt(2 / cosh R) (inv = 1 / sqrt(2 cosh R),
+// sc = sqrt(2 / cosh R)) and the id as raw bits.
+__device__ __forceinline__ float4 point_record(double r, uint32_t id, double inv, double sc)
+{
+    return make_float4((float)(exp(r) * inv), (float)(exp(-r) * inv), (float)(sinh(r) * sc), __int_as_float((int)id));
+}
+
 // Angle between two points the short way round, in [0, pi].
 __device__ __forceinline__ double short_angle(double ta, double tb)
 {

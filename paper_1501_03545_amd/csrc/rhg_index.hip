@@ -9,6 +9,7 @@
 // directory gives, for every cell, the first sorted position at or after it.
 // A range query then reads whole runs of sorted points instead of walking a
 // tree.
+#include "rhg_geom.h"
 #include "rhg_internal.h"
 
 namespace rhg {
@@ -19,27 +20,6 @@ struct KeyArgs {
     int band_bits;
     double R;
 };
-
-// 32-bit angular key: floor(theta * 2^32 / TWO_PI_D), clamped.  Monotone
-// non-decreasing in theta, so any angular interval maps to a key interval.
-__device__ __forceinline__ uint32_t angle_key(double t)
-{
-    const double k = t * (4294967296.0 / RHG_TWO_PI_D);
-    if (!(k > 0.0)) return 0u;
-    if (k >= 4294967295.0) return 4294967295u;
-    return (uint32_t)k;
-}
-
-// Band of radius r: the largest j with E[j] <= r (exact comparisons).
-__device__ __forceinline__ int band_of(const KeyArgs &A, double r)
-{
-    int lo = 0, hi = A.B - 1;  // answer in [lo, hi]
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (A.E[mid] <= r) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 // rt (may be NULL): (r, theta) interleaved in sample order, so that the
 // gather after the sort reads each point with one 16-byte access.
@@ -54,9 +34,7 @@ __global__ void __launch_bounds__(256) key_kernel(KeyArgs A, int64_t n, const do
         if (rt) rt[i] = make_double2(ri, ti);
         if (validate && !(ri >= 0.0 && ri <= A.R && ti >= 0.0 && ti <= RHG_TWO_PI_D))
             atomicAdd(&stats[ST_BAD_INPUT], 1ull);
-        const uint32_t b = (uint32_t)band_of(A, ri);
-        const uint32_t ak = angle_key(ti);
-        keys[i] = A.band_bits ? ((b << (32 - A.band_bits)) | (ak >> A.band_bits)) : ak;
+        keys[i] = point_key(A.E, A.B, A.band_bits, ri, ti);
         vals[i] = (uint32_t)i;
     }
 }
@@ -155,8 +133,7 @@ __global__ void __launch_bounds__(256) gather_kernel(int64_t n, const double *__
         }
         sr[p] = ri;
         st[p] = ti;
-        rec[p] = make_float4((float)(exp(ri) * inv), (float)(exp(-ri) * inv), (float)(sinh(ri) * sc),
-                             __int_as_float((int)id));
+        rec[p] = point_record(ri, id, inv, sc);
     }
 }
 
@@ -166,6 +143,28 @@ static unsigned grid_for(int64_t n, int64_t cap = 65536)
     if (b < 1) b = 1;
     if (b > cap) b = cap;
     return (unsigned)b;
+}
+
+// Band starts and the cell directory of the sorted keys idx->keys.
+hipError_t launch_index_directory(rhg_index *idx, hipStream_t s)
+{
+    const int64_t n = idx->n;
+    const Layout &L = idx->L;
+    hipLaunchKernelGGL(band_start_kernel, dim3(1), dim3(128), 0, s, idx->keys, n, L.B, L.band_bits,
+                       idx->band_start);
+    hipError_t e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    DirArgs da;
+    for (int j = 0; j <= L.B; ++j) da.dir_base[j] = L.dir_base[j];
+    for (int j = 0; j < L.B; ++j) da.cbits[j] = L.cbits[j];
+    da.B = L.B;
+    da.band_bits = L.band_bits;
+    da.total = L.dir_total;
+    if (n > 0)
+        hipLaunchKernelGGL(dir_fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, da, n, idx->keys, idx->band_start,
+                           idx->dir);
+    hipLaunchKernelGGL(dir_empty_kernel, dim3((unsigned)L.B), dim3(256), 0, s, da, idx->band_start, idx->dir);
+    return hipGetLastError();
 }
 
 hipError_t launch_build_index(rhg_index *idx, const double *r, const double *theta, uint32_t *k1,
@@ -188,20 +187,7 @@ hipError_t launch_build_index(rhg_index *idx, const double *r, const double *the
         if ((e = radix_sort_pairs(idx->keys, v0, k1, v1, n, 32, idx->tmp, s)) != hipSuccess) return e;
     }
     PhaseScope ps_index(RHG_PHASE_INDEX, s);
-    hipLaunchKernelGGL(band_start_kernel, dim3(1), dim3(128), 0, s, idx->keys, n, L.B, L.band_bits,
-                       idx->band_start);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    DirArgs da;
-    for (int j = 0; j <= L.B; ++j) da.dir_base[j] = L.dir_base[j];
-    for (int j = 0; j < L.B; ++j) da.cbits[j] = L.cbits[j];
-    da.B = L.B;
-    da.band_bits = L.band_bits;
-    da.total = L.dir_total;
-    if (n > 0)
-        hipLaunchKernelGGL(dir_fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, da, n, idx->keys, idx->band_start,
-                           idx->dir);
-    hipLaunchKernelGGL(dir_empty_kernel, dim3((unsigned)L.B), dim3(256), 0, s, da, idx->band_start, idx->dir);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_index_directory(idx, s)) != hipSuccess) return e;
     phase_end(ps_index.rec, s);
     ps_index.rec = nullptr;
     if (n > 0) {

@@ -177,8 +177,14 @@ hipError_t inclusive_scan_i64(int64_t *x, int64_t n, void *tmp, hipStream_t s);
 
 hipError_t launch_build_index(rhg_index *idx, const double *r, const double *theta, uint32_t *k1,
                               uint32_t *v0, uint32_t *v1, int validate, hipStream_t s);
+// Band starts and cell directory of the index's sorted keys (part of the build).
+hipError_t launch_index_directory(rhg_index *idx, hipStream_t s);
 hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
                          int64_t col_cap = -1, int32_t *overflow = nullptr);
+// The rows of the vertices at sorted positions qpos[0..k) on the index:
+// their lengths into cnt (emit = 0), or the rows into ocol[optr[i] ..).
+hipError_t launch_query_rows(rhg_index *idx, const int32_t *qpos, int64_t k, int64_t *cnt, const int64_t *optr,
+                             int32_t *ocol, int emit, hipStream_t s);
 // The temperature model's count (emit = 0) or emit pass over the index.
 hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_t *col_idx, int emit,
                               hipStream_t s, int64_t col_cap);

@@ -1075,12 +1075,11 @@ __global__ void __launch_bounds__(256) heavy_degrees(SearchArgs A, int64_t *__re
     row_ptr[__float_as_int(A.rec[q].w) + 1] = hi - lo;
 }
 
-hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
-                         int64_t col_cap, int32_t *overflow)
+// The search's launch arguments for an index (the emit pass sets col_cap).
+static void make_search_args(rhg_index *idx, SearchArgs &A)
 {
     const Layout &L = idx->L;
     const rhg_params &p = idx->p;
-    SearchArgs A;
     memset(&A, 0, sizeof(A));
     const double inv = 1.0 / sqrt(2.0 * p.cosh_R), sc = sqrt(2.0 / p.cosh_R);
     for (int j = 0; j <= L.B; ++j) {
@@ -1129,6 +1128,14 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     A.dcap = L.defer_cap;
     A.hset = idx->hset;
     A.hmask = idx->hset_slots - 1;
+}
+
+hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
+                         int64_t col_cap, int32_t *overflow)
+{
+    const Layout &L = idx->L;
+    SearchArgs A;
+    make_search_args(idx, A);
     A.col_cap = col_cap;
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
@@ -1205,6 +1212,84 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     return e;
 }
 
+
+// ------------------------------------------------------------ listed rows
+//
+// The rows of a list of vertices (their sorted positions qpos[0..k)) on the
+// whole index: a wavefront per query, every band's window (or the whole
+// band inside the circle) tested 64 candidates at a time with the exact
+// decision in place.  The count pass writes each row's length to cnt[i];
+// the emit pass writes row i to ocol[optr[i] ..) in (band, position) order.
+template <int MODE>
+__global__ void __launch_bounds__(256) query_rows_kernel(SearchArgs A, const int32_t *__restrict__ qpos, int64_t k,
+                                                         int64_t *__restrict__ cnt, const int64_t *__restrict__ optr,
+                                                         int32_t *__restrict__ ocol)
+{
+    constexpr bool EMIT = MODE == M_EMIT;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < k; i += waves) {
+        const int64_t q = qpos[i];
+        const double rq = A.sr[q], tq = A.st[q];
+        const float4 fq = A.rec[q];
+        int64_t c_out = 0, base = 0, lim = 0;
+        if (EMIT) {
+            base = optr[i];
+            lim = optr[i + 1] - base;
+        }
+        for (int j = 0; j < A.B; ++j) {
+            const int64_t s = A.band_start[j], e = A.band_start[j + 1];
+            if (s == e) continue;
+            int64_t ra[2], rb[2];
+            int nr = 1;
+            bool inside = false, fp = true;
+            if (band_inside(A, rq, j)) {
+                ra[0] = s; rb[0] = e; inside = true;
+            } else {
+                const double w = window_w(A, fq.x, fq.y, fq.z, j);
+                if (w >= 3.0) { ra[0] = s; rb[0] = e; }
+                else nr = window_runs(A, j, tq - w, tq + w, s, e, ra, rb);
+                fp = !(w + RHG_TWO_PI_D * ldexp(1.0, -A.cbits[j]) < 0x1p-5);
+            }
+            for (int r = 0; r < nr; ++r) {
+                for (int64_t c0 = ra[r]; c0 < rb[r]; c0 += 64) {
+                    const int64_t c = c0 + lane;
+                    int acc = 0;
+                    float4 fc = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (c < rb[r] && c != q) {
+                        fc = A.rec[c];
+                        acc = inside ? 1
+                                     : decide<MODE, true>(A, q, tq, fq.x, fq.y, fq.z, c, A.st[c], fc.x, fc.y, fc.z,
+                                                          fp, -1);
+                    }
+                    const uint64_t bal = __ballot(acc);
+                    if (EMIT && acc) {
+                        const int64_t o = c_out + __popcll(bal & lt);
+                        if (o < lim) ocol[base + o] = __float_as_int(fc.w);
+                    }
+                    c_out += __popcll(bal);
+                }
+            }
+        }
+        if (lane == 0) {
+            if (!EMIT) cnt[i] = c_out;
+            else if (c_out != lim) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+        }
+    }
+}
+
+hipError_t launch_query_rows(rhg_index *idx, const int32_t *qpos, int64_t k, int64_t *cnt, const int64_t *optr,
+                             int32_t *ocol, int emit, hipStream_t s)
+{
+    if (k <= 0) return hipSuccess;
+    SearchArgs A;
+    make_search_args(idx, A);
+    const unsigned g = (unsigned)std::min<int64_t>((k + 3) / 4, 16384);
+    if (emit) hipLaunchKernelGGL(query_rows_kernel<M_EMIT>, dim3(g), dim3(256), 0, s, A, qpos, k, cnt, optr, ocol);
+    else hipLaunchKernelGGL(query_rows_kernel<M_COUNT>, dim3(g), dim3(256), 0, s, A, qpos, k, cnt, optr, ocol);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------ small graphs
 //

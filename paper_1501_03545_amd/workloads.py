@@ -52,3 +52,17 @@ def serve_stream(duration_s: float = 60.0, rate_hz: float = 200.0, seed: int = 5
         out.append((t, p))
         k += 1
     return out
+
+
+def move_batch(rng, r, theta, k: int, R: float, angle_step: float = 0.01, radius_step: float = 0.05):
+    """k distinct vertices drawn uniformly; each drifts in angle by
+    U(-angle_step, angle_step) (wrapped into [0, 2 pi)) and in radius by
+    U(-radius_step, radius_step) (clipped into [0, R]).  numpy in, numpy out:
+    (ids int32, new r, new theta)."""
+    n = r.shape[0]
+    ids = rng.choice(n, size=k, replace=False).astype(np.int32)
+    t = theta[ids] + rng.uniform(-angle_step, angle_step, size=k)
+    t = np.mod(t, 2 * np.pi)
+    t = np.where(t >= 6.283185307179586, 0.0, t)
+    rr = np.clip(r[ids] + rng.uniform(-radius_step, radius_step, size=k), 0.0, R)
+    return ids, rr, t

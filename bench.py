@@ -19,6 +19,7 @@ same workload and extrapolates to the full job.
 from __future__ import annotations
 
 import argparse
+import math
 import glob
 import hashlib
 import json
@@ -365,6 +366,73 @@ def run_temperature(cfg, T, reps=3, band_width=0.7, oracle_pts=40_000):
                              "value": m / (n * (n - 1) / 2 / o_rate), "unit": "undirected edges/s (extrapolated)"}}
 
 
+def run_dynamic(cfg, regen_ms, moves=(10_000, 1_000_000), steps=4, angle_step=0.01, radius_step=0.05):
+    """The dynamic model on the single-graph workload: the graph of the n
+    sampled points is kept up to date while batches of k vertices move
+    (each drifting by U(-0.01, 0.01) in angle and U(-0.05, 0.05) in radius,
+    clipped to the disk); every step leaves the graph that regeneration
+    from scratch with ascending rows would give.  regen_ms: that
+    regeneration's time (one step of the main workload plus its row sort)."""
+    import statistics
+    import torch
+    import paper_1501_03545_amd as P
+    n = cfg["n"]
+    dev = torch.device("cuda", 0)
+    p = P.rhg_plan(n, cfg["avg_degree"], cfg["gamma"], cfg["seed"])
+    r = torch.empty(n, dtype=torch.float64, device=dev)
+    th = torch.empty(n, dtype=torch.float64, device=dev)
+    P.rhg_sample_points(p, r, th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = P.DynGraph(p, r, th)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(cfg["seed"] + 17)
+    out = {"workload": "rhg n=%d avg_degree=%g gamma=%g seed=%d; per step k distinct vertices drift by U(-%g, %g) "
+                       "in angle and U(-%g, %g) in radius (clipped to the disk)"
+                       % (n, cfg["avg_degree"], cfg["gamma"], cfg["seed"], angle_step, angle_step, radius_step,
+                          radius_step),
+           "create_ms": create_ms, "regenerate_ms": regen_ms, "steps": []}
+    for k in moves:
+        k = min(k, n)
+        times, changed, entries = [], [], []
+        for _ in range(steps + 1):
+            cur = d.graph()
+            ids = torch.randperm(n, generator=gen, device=dev)[:k].to(torch.int32)
+            rn = (cur.r[ids.long()] + (torch.rand(k, generator=gen, device=dev, dtype=torch.float64) * 2 - 1)
+                  * radius_step).clamp_(0.0, p.R)
+            tn = torch.remainder(cur.theta[ids.long()] + (torch.rand(k, generator=gen, device=dev,
+                                                                     dtype=torch.float64) * 2 - 1) * angle_step,
+                                 2 * math.pi)
+            tn = torch.where(tn >= 6.283185307179586, torch.zeros_like(tn), tn)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            d.move(ids, rn, tn)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            st = d.last_step()
+            changed.append(st["changed_rows"])
+            entries.append(st["moved_entries"])
+        ms = statistics.median(times[1:])
+        out["steps"].append({"k": k, "ms_per_step": ms, "moves_per_s": k / (ms / 1e3),
+                             "changed_rows": int(statistics.median(changed[1:])),
+                             "moved_rows_entries": int(statistics.median(entries[1:])),
+                             "speedup_vs_regenerate": regen_ms / ms})
+    nnz = d.graph().nnz
+    d.close()
+    # method's bytes of a step at these sizes: the index's sorted arrays read
+    # and written (key, id, r, theta, FP32 record: 40 B a point), the row
+    # offsets read and written (16 B a point) and every CSR entry read and
+    # written (8 B an entry)
+    alg = 96 * n + 8 * nnz
+    out["roofline"] = {"bound": "hbm", "kernel": "rhg_dyn_move (whole step, k = %d)" % out["steps"][0]["k"],
+                       "algorithmic_bytes": alg, "achieved": alg / (out["steps"][0]["ms_per_step"] / 1e3) / 1e9,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": alg / (out["steps"][0]["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def copy_calibration(nbytes=4 << 30, reps=5):
     """A plain device-to-device copy of known size: its event-timed rate is
     the practical HBM ceiling, and under rocprofv3 --pmc its FETCH_SIZE and
@@ -445,6 +513,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving run (0: skip)")
     ap.add_argument("--band-width", type=float, default=0.0)
     ap.add_argument("--temperature", type=float, default=0.1, help="temperature-model leg at this T (0: skip)")
+    ap.add_argument("--dynamic", type=int, default=1, help="dynamic-model leg (0: skip)")
     ap.add_argument("--cell-target", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -533,6 +602,12 @@ def main():
         out["temperature"] = run_temperature(cfg, args.temperature)
         _log("temperature done: %.2f ms, %.3g edges/s" % (out["temperature"]["ms_count_scan_emit"],
                                                           out["temperature"]["edges_per_s"]))
+    if args.dynamic:
+        import torch
+        torch.cuda.empty_cache()
+        _log("dynamic model")
+        out["dynamic"] = run_dynamic(cfg, out["ms_per_step"] + out["canonical_rows"]["ms"])
+        _log("dynamic done: %s" % ", ".join("k=%d %.2f ms" % (x["k"], x["ms_per_step"]) for x in out["dynamic"]["steps"]))
     if args.batch > 0:
         import torch
         torch.cuda.empty_cache()

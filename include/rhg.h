@@ -437,14 +437,21 @@ rhg_status rhg_temp_generate(int64_t n, double avg_degree, double gamma, double 
  * points), and the params.  Valid until the next rhg_dyn_move or
  * rhg_dyn_free; the caller must not write through them.
  *
+ * A batch with k (1 + mean degree) above share * n (share = 1/8 unless
+ * rhg_dyn_set_regenerate_share says otherwise; 0: always) is applied by
+ * regeneration instead (index rebuilt, both passes, rows sorted): same
+ * graph, less work when most rows would change.
+ *
  * rhg_dyn_last_step: rows rewritten by the last move (the changed unmoved
- * rows plus the k moved rows) and entries of the moved rows. */
+ * rows plus the k moved rows, or n after a regeneration) and entries of
+ * the moved rows (or all entries). */
 typedef struct rhg_dyn rhg_dyn;
 rhg_status rhg_dyn_create(const rhg_params *p /* host */, const rhg_tuning *t /* host, may be NULL */,
                           const double *r, const double *theta, rhg_dyn **out /* host */, void *stream);
 rhg_status rhg_dyn_move(rhg_dyn *d, int64_t k, const int32_t *ids, const double *r, const double *theta,
                         void *stream);
 rhg_status rhg_dyn_graph(rhg_dyn *d, rhg_csr *out /* host */);
+rhg_status rhg_dyn_set_regenerate_share(rhg_dyn *d, double share);
 rhg_status rhg_dyn_last_step(rhg_dyn *d, int64_t *changed_rows /* host */, int64_t *moved_entries /* host */);
 void rhg_dyn_free(rhg_dyn *d);
 

@@ -130,6 +130,7 @@ def load():
         "rhg_dyn_move": (i32, [vp, i64, vp, vp, vp, vp]),
         "rhg_dyn_graph": (i32, [vp, P(rhg_csr)]),
         "rhg_dyn_last_step": (i32, [vp, P(i64), P(i64)]),
+        "rhg_dyn_set_regenerate_share": (i32, [vp, d]),
         "rhg_dyn_free": (None, [vp]),
         "rhg_set_profiling": (i32, [i32]),
         "rhg_phase_times": (i32, [P(C.c_double), P(C.c_int64), i32]),
@@ -501,6 +502,11 @@ class DynGraph:
         return Graph(params=out.params, row_ptr=_view(out.row_ptr, n + 1, "<i8"),
                      col_idx=_view(out.col_idx, out.nnz, "<i4"), r=_view(out.r, n, "<f8"),
                      theta=_view(out.theta, n, "<f8"))
+
+    def set_regenerate_share(self, share: float):
+        """Batches with k (1 + mean degree) above share * n are applied by
+        regeneration (0: always; a huge share: never)."""
+        _check(load().rhg_dyn_set_regenerate_share(self.handle, float(share)))
 
     def last_step(self) -> dict:
         a, b = C.c_int64(), C.c_int64()

@@ -28,13 +28,16 @@ def setup_module(_):
     P.load()
 
 
-def _start(n, k, g, seed, tuning=None):
+def _start(n, k, g, seed, tuning=None, share=1e30):
+    """A state on the oracle's points; by default every batch is applied
+    incrementally (share 1e30), the path under test."""
     import torch
     a, R = O.solve_R(n, k, g)
     r, t, hard = O.sample(seed, a, R, n)
     assert hard == 0
     p = P.rhg_plan_radius(n, a, R, seed)
     d = P.DynGraph(p, torch.from_numpy(r).cuda(), torch.from_numpy(t).cuda(), tuning=tuning)
+    d.set_regenerate_share(share)
     return d, R, r, t
 
 
@@ -58,10 +61,13 @@ def _check_full(d, R, r, t, allow_ties=False):
     assert np.array_equal(G.col_idx.cpu().numpy(), ocol)
 
 
-@pytest.mark.parametrize("cfg", [(20_000, 10.0, 2.5, 1), (8_000, 30.0, 2.1, 2), (12_000, 6.0, 3.0, 3)])
+@pytest.mark.parametrize("cfg", [(20_000, 10.0, 2.5, 1, 1e30), (8_000, 30.0, 2.1, 2, 1e30), (12_000, 6.0, 3.0, 3, 1e30),
+                                 (20_000, 10.0, 2.5, 1, 0.125), (9_000, 8.0, 2.6, 4, 0.0)])
 def test_moves_keep_the_graph_equal_to_regeneration(cfg):
-    n, k, g, seed = cfg
-    d, R, r, t = _start(n, k, g, seed)
+    """Incremental steps (share 1e30), the default policy (some steps
+    regenerate) and regeneration only (share 0)."""
+    n, k, g, seed, share = cfg
+    d, R, r, t = _start(n, k, g, seed, share=share)
     _check_full(d, R, r, t)
     rng = np.random.default_rng(seed)
     for step, kk in enumerate([1, 7, 100, 1000, n // 4, n]):
@@ -72,6 +78,8 @@ def test_moves_keep_the_graph_equal_to_regeneration(cfg):
         _check_full(d, R, r, t)
         st = d.last_step()
         assert st["changed_rows"] >= kk
+        if share == 0.0:
+            assert st["changed_rows"] == n
     d.close()
 
 

@@ -99,6 +99,16 @@ typedef struct {
                             * 65536 + n/1024); when the count pass finds
                             * more, both passes rerun with in-place
                             * decisions; same bytes out                     */
+    int32_t stage;         /* 1: the count pass also writes each light
+                            * query's row into a staging area of the index
+                            * (a slot per query sized from its band's
+                            * expected degree) and the emit pass copies the
+                            * rows out instead of searching again (a row
+                            * that outgrew its slot is searched again);
+                            * -1: count and search again; 0: automatic
+                            * (staged from n = 2^19); same bytes out        */
+    int32_t stage_pct;     /* slot size, percent of the expected degree at
+                            * the band's inner edge, plus 16 (0: 150)      */
 } rhg_tuning;
 
 /* Device-side diagnostics of the count and emit passes over an index.  The
@@ -123,6 +133,10 @@ typedef struct {
                               * R + 2T ln(2^53 - 1) that were screened     */
     int64_t temp_coins;      /* the last temperature count pass: coins drawn
                               * (screened pairs closer than that radius)  */
+    int64_t staged_waves;    /* the last threshold count pass, when staged:
+                              * light wavefronts (64 sorted positions)       */
+    int64_t stage_overflows; /* of those, wavefronts with a row longer than
+                              * its slot (the emit pass searches them again) */
 } rhg_stats;
 
 typedef struct rhg_index rhg_index;  /* opaque, host-side handle */

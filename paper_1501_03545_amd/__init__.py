@@ -38,14 +38,15 @@ class rhg_tuning(C.Structure):
     _fields_ = [("band_width", C.c_double), ("inner_radius", C.c_double),
                 ("cell_target", C.c_int32), ("heavy_points", C.c_int32), ("sweep_max", C.c_int32),
                 ("sweep_linear", C.c_int32), ("fp64_only", C.c_int32), ("no_stream_stage", C.c_int32),
-                ("exact_inline", C.c_int32), ("defer_cap", C.c_int32)]
+                ("exact_inline", C.c_int32), ("defer_cap", C.c_int32), ("stage", C.c_int32),
+                ("stage_pct", C.c_int32)]
 
 
 class rhg_stats(C.Structure):
     _fields_ = [("fp32_undecided", C.c_int64), ("dd_fallbacks", C.c_int64), ("ties", C.c_int64),
                 ("swept", C.c_int64), ("tests", C.c_int64),
                 ("register_streams", C.c_int64), ("temp_candidates", C.c_int64),
-                ("temp_coins", C.c_int64)]
+                ("temp_coins", C.c_int64), ("staged_waves", C.c_int64), ("stage_overflows", C.c_int64)]
 
 
 class rhg_graph_summary(C.Structure):
@@ -176,6 +177,8 @@ def _tuning(t: Optional[dict]):
     tu.no_stream_stage = 1 if t.get("no_stream_stage") else 0
     tu.exact_inline = 1 if t.get("exact_inline") else 0
     tu.defer_cap = int(t.get("defer_cap", 0))
+    tu.stage = int(t.get("stage", 0))
+    tu.stage_pct = int(t.get("stage_pct", 0))
     return C.byref(tu)
 
 
@@ -342,7 +345,8 @@ def rhg_index_stats(idx: Index, stream=None) -> dict:
     _check(load().rhg_index_stats(idx.handle, C.byref(st), _stream(stream)))
     return {"fp32_undecided": st.fp32_undecided, "dd_fallbacks": st.dd_fallbacks, "ties": st.ties,
             "swept": st.swept, "tests": st.tests, "register_streams": st.register_streams,
-            "temp_candidates": st.temp_candidates, "temp_coins": st.temp_coins}
+            "temp_candidates": st.temp_candidates, "temp_coins": st.temp_coins,
+            "staged_waves": st.staged_waves, "stage_overflows": st.stage_overflows}
 
 
 PHASES = ["sample", "keys+sort", "index", "gather", "plan", "count", "scan", "emit", "rows"]

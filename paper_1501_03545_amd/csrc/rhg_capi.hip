@@ -68,7 +68,7 @@ void phase_end(void *rec, hipStream_t s)
 
 struct WsPlan {
     size_t keys, v0, band_start, dir, sr, st, rec, rt, heavy_end, hplan, hcnt, hitem, hscal, stats, wstat, dkeys, dchunk,
-        dcount, hset, raux, tmp, total, tmp_bytes;
+        dcount, hset, dslot, stage, sslot, sovf, sbase, raux, tmp, total, tmp_bytes;
     int64_t max_chunks, rows_lcap, rows_mapcap, rows_nnz_cap;
 };
 
@@ -107,6 +107,11 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.dchunk = take((size_t)L.defer_cap * 4);
     w.dcount = take(16);
     w.hset = take((size_t)L.hset_slots * 8);
+    w.dslot = take(L.staged ? (size_t)L.defer_cap * 8 : 8);
+    w.stage = take(L.staged ? (size_t)L.stage_cap * 4 : 4);
+    w.sslot = take(L.staged ? N * 4 : 4);
+    w.sovf = take(L.staged ? (N + 63) / 64 : 1);
+    w.sbase = take((size_t)(L.B + 1) * 8);
     // canonical rows: room for the long rows and tiles of a graph of up to
     // twice the estimated entries (plus 2^23)
     w.rows_nnz_cap = (int64_t)std::min(9.0e18, 2.0 * L.entries_est + 8388608.0);
@@ -272,6 +277,11 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->dchunk = (int32_t *)(base + w.dchunk);
     idx->dcount = (unsigned long long *)(base + w.dcount);
     idx->hset = (uint64_t *)(base + w.hset);
+    idx->dslot = (int64_t *)(base + w.dslot);
+    idx->stage = (int32_t *)(base + w.stage);
+    idx->sslot = (int32_t *)(base + w.sslot);
+    idx->sovf = (uint8_t *)(base + w.sovf);
+    idx->sbase = (int64_t *)(base + w.sbase);
     idx->hset_slots = idx->L.hset_slots;
     idx->rows_aux = base + w.raux;
     idx->rows_lcap = w.rows_lcap;
@@ -478,6 +488,18 @@ rhg_status rhg_index_stats(rhg_index *idx, rhg_stats *out, void *stream)
             out->swept += w[2 * i + 1];
         }
     }
+    // the staged count's overflow flags, one byte per wavefront
+    out->staged_waves = out->stage_overflows = 0;
+    if (idx->staged_count && idx->n > 0) {
+        const size_t nw = (size_t)(idx->n + 63) / 64;
+        std::vector<uint8_t> f(nw);
+        int32_t hend = 0;
+        RHG_HIP(hipMemcpyAsync(f.data(), idx->sovf, nw, hipMemcpyDeviceToHost, s));
+        RHG_HIP(hipMemcpyAsync(&hend, idx->heavy_end, sizeof(hend), hipMemcpyDeviceToHost, s));
+        RHG_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < nw; ++i) out->stage_overflows += f[i] != 0;
+        out->staged_waves = (int64_t)nw - (int64_t)std::max(hend, 0) / 64;
+    }
     if (h[ST_EMIT_MISMATCH]) return fail(RHG_EINTERNAL, "emit pass disagreed with the count pass");
     return RHG_OK;
 }
@@ -522,6 +544,12 @@ rhg_status rhg_generate_async_noalloc(const rhg_params *p, const rhg_tuning *t, 
     g_last_error.clear();
     rhg_status st = check_params(p, "rhg_generate_async_noalloc");
     if (st != RHG_OK) return st;
+    // no staging area in the library's array: the emit pass searches again
+    rhg_tuning tt;
+    memset(&tt, 0, sizeof(tt));
+    if (t) tt = *t;
+    tt.stage = -1;
+    t = &tt;
     const size_t need = rhg_index_workspace_bytes(p, t);
     if (need > RHG_NOALLOC_SCRATCH_BYTES)
         return fail(RHG_ECAPACITY, "rhg_generate_async_noalloc: the index needs " + std::to_string(need) +

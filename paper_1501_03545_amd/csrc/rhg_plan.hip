@@ -241,6 +241,29 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     int64_t hs = 1;
     while (hs < 2 * L->defer_cap) hs <<= 1;
     L->hset_slots = hs;
+    // Staged count: each light query gets a slot of scap[j] words: its
+    // row's length, then room for its band's expected degree at the band's
+    // inner edge (the largest in the band) times stage_pct %, plus 16; a
+    // row that outgrows its slot is searched again by the emit pass.  The
+    // workspace holds the expected band populations plus ten standard
+    // deviations.
+    const int st = t ? t->stage : 0;
+    L->staged = (st > 0 || (st == 0 && p.n >= (int64_t)1 << 19)) && p.n >= 1 ? 1 : 0;
+    L->stage_cap = 0;
+    if (L->staged) {
+        const double pct = (t && t->stage_pct > 0) ? t->stage_pct / 100.0 : 1.5;
+        double cap = 0.0;
+        for (int j = 0; j < B; ++j) {
+            const double ed = expected_degree(n, a, R, L->E[j]);
+            const double sc = std::min(n, ceil(pct * ed) + 16.0) + 1.0;
+            L->scap[j] = (int32_t)sc;
+            const double F0 = (cosh(a * L->E[j]) - 1.0) / denom;
+            const double F1 = (cosh(a * L->E[j + 1]) - 1.0) / denom;
+            const double pts = n * std::max(0.0, std::min(1.0, F1) - F0);
+            cap += (pts + 10.0 * sqrt(pts) + 64.0) * sc;
+        }
+        L->stage_cap = (int64_t)std::min(cap, 4.0e9 * 8);
+    }
 }
 
 }  // namespace rhg

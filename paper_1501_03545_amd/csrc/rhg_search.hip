@@ -93,10 +93,31 @@ struct SearchArgs {
     uint64_t *hset;                   // open-addressing set of listed edges (0 = empty slot)
     int64_t hmask;                    // its size - 1 (a power of two, at least twice dcap)
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
+    // staged count: each light query's row goes to a slot of scap[band]
+    // entries at sbase[band] + (position - band start) * scap[band], its
+    // length first (-1: the wavefront outgrew a slot), then its entries;
+    // the count pass leaves each light row's position + 1 in sslot[id] (0:
+    // heavy row); the emit pass copies the slots out and searches again
+    // only the wavefronts flagged in sovf
+    int32_t scap[RHG_MAX_BANDS];
+    int64_t stage_cap;
+    int32_t *stage;
+    int32_t *sslot;
+    uint8_t *sovf;
+    int64_t *sbase;
+    int64_t *dslot;                   // the listed pair's staging entry (-1: none)
+    int staged;                       // this count pass stages (its emit pass copies)
+    int light_skip;                   // emit pass after a staged count: heavy chunks only
 };
 
 // Passes of the search kernels: count, emit.
-enum { M_COUNT = 0, M_EMIT = 1 };
+enum { M_COUNT = 0, M_EMIT = 1, M_STAGE = 2 };
+
+// A staged row's entry whose decision the resolving kernel makes: the
+// candidate's id with this bit; the kernel rewrites it to the id or to
+// STAGE_REJECT.
+constexpr uint32_t STAGE_PENDING = 0x80000000u;
+constexpr int32_t STAGE_REJECT = -1;
 
 constexpr float P32_ACC = 1.0f - 0x1p-18f;
 constexpr float P32_REJ = 1.0f + 0x1p-18f;
@@ -162,11 +183,13 @@ __device__ __forceinline__ int decide(const SearchArgs &A, int64_t q, double tq,
     if (A.use_p32) v = p32(tq, eq, mq, sq, tc, ec, mc, sc, full_poly);
     if (v != 2) return v;
     if (EXACT) {
-        if (A.use_p32 && MODE == M_COUNT) atomicAdd(&A.stats[ST_FP32_UNDECIDED], 1ull);
+        if (A.use_p32 && MODE != M_EMIT) atomicAdd(&A.stats[ST_FP32_UNDECIDED], 1ull);
         return edge_p64(A.sr[q], tq, A.sr[c], tc, A.C, A.C_lo, A.stats);
     }
+    // a staged light row lists the pair itself, with its staging entry
+    if (MODE == M_STAGE && chunk < 0) return 2;
     const uint64_t key = pair_key(q, c);
-    if (MODE == M_COUNT) {
+    if (MODE != M_EMIT) {
         const unsigned long long k = atomicAdd(&A.dcount[0], 1ull);
         if ((int64_t)k < A.dcap) {
             A.dkeys[k] = key;
@@ -178,6 +201,18 @@ __device__ __forceinline__ int decide(const SearchArgs &A, int64_t q, double tq,
         const uint64_t x = A.hset[h];
         if (x == key) return 1;
         if (x == 0) return 0;
+    }
+}
+
+// A staged light row's undecided pair: listed with its staging entry
+// (-1: beyond the slot) for the resolving kernel.
+__device__ __forceinline__ void list_staged(const SearchArgs &A, int64_t q, int64_t c, int64_t slot)
+{
+    const unsigned long long k = atomicAdd(&A.dcount[0], 1ull);
+    if ((int64_t)k < A.dcap) {
+        A.dkeys[k] = pair_key(q, c);
+        A.dchunk[k] = -1;
+        A.dslot[k] = slot;
     }
 }
 
@@ -533,7 +568,11 @@ static_assert(STREAM_STEPS == 64, "one word per lane is cleared");
 template <int MODE, bool EXACT>
 __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, int32_t *col)
 {
-    constexpr bool EMIT = MODE == M_EMIT;
+    // STAGE: counted like the count pass, written like the emit pass into
+    // the query's staging slot
+    constexpr bool STAGE = MODE == M_STAGE;
+    constexpr bool EMIT = MODE == M_EMIT || STAGE;
+    constexpr bool COUNTING = MODE != M_EMIT;
     __shared__ WaveLds lds[4];
     WaveLds &SM = lds[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
@@ -550,7 +589,7 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     const int64_t hend = uni64(*A.heavy_end);
     const bool active = inb && p >= hend;
     if (__ballot(active) == 0) {
-        if (!EMIT && lane == 0 && base < A.n) A.wstat[base >> 6] = make_longlong2(0, 0);
+        if (COUNTING && lane == 0 && base < A.n) A.wstat[base >> 6] = make_longlong2(0, 0);
         return;
     }
     if (!active) {
@@ -561,10 +600,17 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     const int32_t id = __float_as_int(fq.w);
     int32_t *out = nullptr;  // EMIT: entry k of the row goes to out[k] while k < lim
     int64_t lim = 0;
-    if (EMIT && active) {
+    if (MODE == M_EMIT && active) {
         out = col + row_ptr[id];
         lim = row_ptr[id + 1] - row_ptr[id];
     }
+    if (STAGE && active) {
+        const int jb = A.band_bits ? (int)(A.keys[p] >> (32 - A.band_bits)) : 0;
+        const int64_t sb = A.sbase[jb] + (p - A.band_start[jb]) * (int64_t)A.scap[jb];
+        out = A.stage + sb + 1;  // word 0 of the slot: the row's length
+        lim = max<int64_t>(0, min<int64_t>(A.scap[jb] - 1, A.stage_cap - sb - 1));
+    }
+    int64_t pend = 0;  // STAGE: entries of the row still pending
     const int B = A.B;
     // the innermost query of the wave has the widest windows
     const double rmin = wave_min(active ? rq : 1e300);
@@ -648,9 +694,14 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     // exact decision, counted and (EMIT) put into the row.
     auto take = [&](int64_t c, double tc, float4 fc, bool fp, SweepStage &S) {
         ++tests;
-        if (decide<MODE, EXACT>(A, p, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp, -1)) {
+        const int v = decide<MODE, EXACT>(A, p, tq, fq.x, fq.y, fq.z, c, tc, fc.x, fc.y, fc.z, fp, -1);
+        if (v) {
+            if (STAGE && v == 2) {
+                list_staged(A, p, c, cnt < lim ? (int64_t)(out - A.stage) + cnt : -1);
+                ++pend;
+            }
             if (EMIT && cnt < lim) {
-                S.row[nb][lane] = __float_as_int(fc.w);
+                S.row[nb][lane] = __float_as_int(fc.w) | (STAGE && v == 2 ? (int)STAGE_PENDING : 0);
                 if (++nb == ROWBUF) {
                     // a full buffer: fl + ROWBUF <= lim
 #pragma unroll
@@ -883,8 +934,10 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
                 const int64_t at = __shfl(cnt, l, 64) + __popcll(bal & seg & lt_mask);
                 int32_t *const lout = (int32_t *)__shfl((int64_t)out, l, 64);
                 const int64_t llim = __shfl(lim, l, 64);
-                if (acc && at < llim) lout[at] = cid;
+                if (STAGE && acc == 2) list_staged(A, lp, c, at < llim ? (int64_t)(lout - A.stage) + at : -1);
+                if (acc && at < llim) lout[at] = cid | (STAGE && acc == 2 ? (int)STAGE_PENDING : 0);
             }
+            if (STAGE) pend += __popcll(__ballot(acc == 2) & lom & him);
             cnt += got;
         };
         if (small) {
@@ -950,13 +1003,22 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
             step(t0, l, c, tc, fc);
         }
     }
-    if (!EMIT) {
+    if (COUNTING) {
         int tt;
         wave_excl_sum(tests, lane, &tt);
         if (lane == 0) A.wstat[base >> 6] = make_longlong2(tt, swept);
     }
+    // a row that outgrew its slot: the emit pass searches this wavefront again
+    const bool wovf = STAGE && __ballot(active && cnt > lim) != 0;
+    if (wovf && lane == 0) A.sovf[base >> 6] = 1;
     if (!active) return;
-    if (EMIT) {
+    if (STAGE) {
+        // the degree, with the position + 1 above it (split off before the
+        // row scan), and the slot's length word
+        row_ptr[id + 1] = (int64_t)(((uint64_t)(p + 1) << 32) | (uint64_t)(cnt - pend));
+        const int64_t sb = (int64_t)(out - A.stage) - 1;
+        if (sb < A.stage_cap) A.stage[sb] = wovf ? -1 : (int32_t)cnt;
+    } else if (EMIT) {
         if (cnt != lim) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
     } else {
         row_ptr[id + 1] = cnt;
@@ -987,10 +1049,147 @@ search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr, int32_t *__restrict__
         for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) heavy_chunk<MODE, EXACT>(A, c, row_ptr, col_idx);
         return;
     }
+    // emit pass after a staged count: the light rows are copied (and the
+    // wavefronts whose rows outgrew their slots searched again) by the
+    // kernels below
+    if (A.light_skip) return;
     const int64_t lb = (A.n + 255) / 256, nb = (int64_t)gridDim.x - A.heavy_blocks;
     for (int64_t b = (int64_t)blockIdx.x - A.heavy_blocks; b < lb; b += nb) {
         light_wave<MODE, EXACT>(A, b * 256 + (threadIdx.x & ~63), row_ptr, col_idx);
         if (!EXACT) break;
+    }
+}
+
+// After a staged count: each light row's degree carries its sorted
+// position + 1 in the upper 32 bits; they move to sslot (0 for the heavy
+// rows, whose degrees heavy_degrees wrote) before the row scan.
+__global__ void __launch_bounds__(256) stage_split_kernel(int64_t *__restrict__ row_ptr, int32_t *__restrict__ sslot,
+                                                          int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t v = (uint64_t)row_ptr[i + 1];
+    sslot[i] = (int32_t)(v >> 32);
+    row_ptr[i + 1] = (int64_t)(v & 0xffffffffull);
+}
+
+// Emit pass after a staged count: the light rows copied from their slots,
+// 64 consecutive ids to a wavefront, so that row_ptr and sslot are read in
+// order and the wavefront's rows fill one stretch of col_idx.  A row is
+// taken as flat (its slot holds exactly its row_ptr length) and joins a
+// stream of entries that the wavefront copies 64 at a time, each lane
+// finding its entry's row by a binary search over the rows' starts; the
+// entries are loaded together with the slots' length words and stored only
+// for the rows whose length word matches, so that a wavefront waits for
+// memory about once per batch.  A row whose slot holds more (entries that
+// the resolving kernel rejected) is compacted on its own; a length word of
+// -1 leaves the row to stage_redo_kernel; one below the row_ptr length is
+// an emit mismatch.  Few registers, so that many wavefronts keep their
+// loads in flight.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+stage_copy_kernel(SearchArgs A, const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col)
+{
+    // a col_idx buffer too small for the graph: write nothing
+    if (A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
+    __shared__ int32_t bstart[RHG_MAX_BANDS + 1], bcap[RHG_MAX_BANDS + 1];
+    __shared__ int64_t bbase[RHG_MAX_BANDS + 1];
+    for (int j = threadIdx.x; j <= A.B; j += 256) {
+        bstart[j] = A.band_start[j];
+        bbase[j] = A.sbase[j];
+        bcap[j] = j < A.B ? A.scap[j] : 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t wstride = (int64_t)gridDim.x * 4;
+    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w * 64 < A.n; w += wstride) {
+        const int64_t id = w * 64 + lane;
+        int64_t dst = 0, rl = 0, sb = 0;
+        int dl = 0;  // entries the slot holds at most
+        bool has = false;
+        if (id < A.n) {
+            const int32_t sp = A.sslot[id];
+            dst = row_ptr[id];
+            rl = row_ptr[id + 1] - dst;
+            if (sp > 0 && rl > 0) {
+                const int64_t p = sp - 1;
+                int j = 0;  // the last band starting at or before p
+#pragma unroll
+                for (int h = 32; h > 0; h >>= 1)
+                    if (j + h < A.B && bstart[j + h] <= p) j += h;
+                sb = bbase[j] + (p - bstart[j]) * (int64_t)bcap[j];
+                if (sb < A.stage_cap) {
+                    has = true;
+                    dl = (int)min<int64_t>(bcap[j] - 1, A.stage_cap - sb - 1);
+                }
+            }
+        }
+        int len = -2;
+        if (has) len = A.stage[sb];
+        int tot;
+        const int pre = wave_excl_sum(has ? (int)min<int64_t>(rl, dl) : 0, lane, &tot);
+        constexpr int COPY_BATCH = 5;
+        for (int e0 = 0; e0 < tot; e0 += 64 * COPY_BATCH) {
+            int32_t v[COPY_BATCH];
+            int64_t at[COPY_BATCH];
+            int rr[COPY_BATCH];
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u) {
+                const int e = e0 + 64 * u + lane;
+                int r = 0;  // the last row starting at or before e
+#pragma unroll
+                for (int h = 32; h > 0; h >>= 1)
+                    if (__shfl(pre, r + h, 64) <= e) r += h;
+                const int k = e - __shfl(pre, r, 64);
+                const int64_t so = __shfl(sb, r, 64);
+                at[u] = __shfl(dst, r, 64) + k;
+                rr[u] = r;
+                v[u] = e < tot ? A.stage[so + 1 + k] : 0;
+            }
+            const int flat = has && (int64_t)len == rl;
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u) {
+                const int ok = __shfl(flat, rr[u], 64);
+                if (ok && e0 + 64 * u + lane < tot) {
+                    if (v[u] < 0) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+                    col[at[u]] = v[u];
+                }
+            }
+        }
+        if (has && len >= 0 && (int64_t)len < rl) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+        for (uint64_t m = __ballot(has && (int64_t)len > rl); m; m &= m - 1) {
+            const int l = __ffsll((unsigned long long)m) - 1;
+            const int64_t lo = uni_lane64(sb, l) + 1, ld = uni_lane64(dst, l), le = ld + uni_lane64(rl, l);
+            const int lu = __builtin_amdgcn_readlane(len, l);
+            int64_t o = 0;
+            for (int k0 = 0; k0 < lu; k0 += 64) {
+                const int k = k0 + lane;
+                const int32_t x = k < lu ? A.stage[lo + k] : STAGE_REJECT;
+                const bool keep = x != STAGE_REJECT;
+                const uint64_t bal = __ballot(keep);
+                const int64_t at = ld + o + __popcll(bal & lt);
+                if (keep && at < le) col[at] = x;
+                o += __popcll(bal);
+            }
+            if (lane == 0 && ld + o != le) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+        }
+    }
+}
+
+// Emit pass after a staged count: the wavefronts whose rows outgrew their
+// slots, searched again.  Each wavefront reads 64 flags at a time.
+template <bool EXACT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+stage_redo_kernel(SearchArgs A, int64_t *__restrict__ row_ptr, int32_t *__restrict__ col, int gate)
+{
+    if (A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
+    if (gate && (__builtin_amdgcn_readfirstlane((int)A.dcount[1]) != 0) != EXACT) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (A.n + 63) / 64;
+    for (int64_t g0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; g0 < waves; g0 += (int64_t)gridDim.x * 256) {
+        const int64_t w = g0 + lane;
+        for (uint64_t m = __ballot(w < waves && A.sovf[w]); m; m &= m - 1)
+            light_wave<M_EMIT, EXACT>(A, (g0 + __ffsll((unsigned long long)m) - 1) * 64, row_ptr, col);
     }
 }
 
@@ -1009,12 +1208,17 @@ __global__ void __launch_bounds__(256) resolve_kernel(SearchArgs A, int64_t *__r
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += stride) {
         const uint64_t key = A.dkeys[i];
         const int64_t q = (int64_t)((key >> 32) & 0x7fffffffull), c = (int64_t)(key & 0xffffffffull);
-        if (!edge_p64(A.sr[q], A.st[q], A.sr[c], A.st[c], A.C, A.C_lo, A.stats)) continue;
+        const int32_t ch = A.dchunk[i];
+        const int edge = edge_p64(A.sr[q], A.st[q], A.sr[c], A.st[c], A.C, A.C_lo, A.stats);
+        if (A.staged && ch < 0) {  // the staged row's pending entry, decided
+            const int64_t slot = A.dslot[i];
+            if (slot >= 0) A.stage[slot] = edge ? (int32_t)A.ids[c] : STAGE_REJECT;
+        }
+        if (!edge) continue;
         for (uint64_t h = slot_hash(key) & (uint64_t)A.hmask;; h = (h + 1) & (uint64_t)A.hmask) {
             const unsigned long long prev = atomicCAS((unsigned long long *)&A.hset[h], 0ull, (unsigned long long)key);
             if (prev == 0ull || prev == key) break;
         }
-        const int32_t ch = A.dchunk[i];
         if (ch >= 0) atomicAdd((unsigned long long *)&A.hcnt[ch], 1ull);
         else atomicAdd((unsigned long long *)&row_ptr[__float_as_int(A.rec[q].w) + 1], 1ull);
     }
@@ -1032,7 +1236,21 @@ __global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_
         A.hscal[0] = 0;
         A.dcount[0] = 0;
         A.dcount[1] = 0;
+        if (A.staged) {
+            int64_t b = 0;
+            for (int j = 0; j < A.B; ++j) {
+                A.sbase[j] = b;
+                b += (int64_t)(A.band_start[j + 1] - A.band_start[j]) * A.scap[j];
+            }
+            A.sbase[A.B] = b;
+        }
     }
+}
+
+__global__ void __launch_bounds__(256) fill_u8(uint8_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // Chunk -> item table: after the scan, item i owns chunks
@@ -1128,6 +1346,15 @@ static void make_search_args(rhg_index *idx, SearchArgs &A)
     A.dcap = L.defer_cap;
     A.hset = idx->hset;
     A.hmask = idx->hset_slots - 1;
+    for (int j = 0; j < L.B; ++j) A.scap[j] = L.scap[j];
+    A.stage_cap = L.stage_cap;
+    A.stage = idx->stage;
+    A.sslot = idx->sslot;
+    A.sovf = idx->sovf;
+    A.sbase = idx->sbase;
+    A.dslot = idx->dslot;
+    A.staged = L.staged;
+    A.light_skip = 0;
 }
 
 hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int emit, hipStream_t s,
@@ -1176,13 +1403,39 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     if (!emit && !exact_only && A.hmask >= 0)
         hipLaunchKernelGGL(zero_i64, dim3((unsigned)((A.hmask + 256) / 256)), dim3(256), 0, s, (int64_t *)A.hset,
                            A.hmask + 1);
+    // staged: the count pass writes the light rows into their slots, the
+    // emit pass copies them, emits the heavy chunks and searches again the
+    // wavefronts whose rows outgrew their slots
+    const bool staged = emit ? idx->staged_count != 0 : L.staged != 0;
+    const int64_t waves = (n + 63) / 64;
+    if (!emit && staged)
+        hipLaunchKernelGGL(fill_u8, dim3((unsigned)((waves + 255) / 256)), dim3(256), 0, s, A.sovf, waves);
+    if (emit && staged) {
+        A.light_skip = 1;
+        Ax.light_skip = 1;
+    }
+    const dim3 gh((unsigned)std::max(A.heavy_blocks, 1)), ghx((unsigned)std::max(Ax.heavy_blocks, 1));
+    const int64_t lwaves = (n + 63) / 64;
+    const dim3 gc((unsigned)std::max<int64_t>(1, std::min<int64_t>((lwaves + 3) / 4, 16384)));
+    const dim3 gr((unsigned)std::max<int64_t>(1, std::min<int64_t>((lwaves + 255) / 256, 4096)));
     {
         PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
-        if (exact_only) {
+        if (emit && staged) {
+            if (A.heavy_blocks > 0) {
+                if (exact_only) hipLaunchKernelGGL((search_kernel<M_EMIT, true>), gh, b, 0, s, A, row_ptr, col_idx, 0);
+                else hipLaunchKernelGGL((search_kernel<M_EMIT, false>), gh, b, 0, s, A, row_ptr, col_idx, 1);
+            }
+            hipLaunchKernelGGL(stage_copy_kernel, gc, b, 0, s, A, row_ptr, col_idx);
+            if (exact_only) hipLaunchKernelGGL(stage_redo_kernel<true>, gr, b, 0, s, A, row_ptr, col_idx, 0);
+            else hipLaunchKernelGGL(stage_redo_kernel<false>, gr, b, 0, s, A, row_ptr, col_idx, 1);
+        } else if (exact_only) {
             if (emit) hipLaunchKernelGGL((search_kernel<M_EMIT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
+            else if (staged) hipLaunchKernelGGL((search_kernel<M_STAGE, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
             else hipLaunchKernelGGL((search_kernel<M_COUNT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
         } else if (emit) {
             hipLaunchKernelGGL((search_kernel<M_EMIT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
+        } else if (staged) {
+            hipLaunchKernelGGL((search_kernel<M_STAGE, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
         } else {
             hipLaunchKernelGGL((search_kernel<M_COUNT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
         }
@@ -1192,12 +1445,18 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         PhaseScope ps(RHG_PHASE_PLAN, s);
         if (!emit) {
             hipLaunchKernelGGL(resolve_kernel, dim3(256), dim3(256), 0, s, A, row_ptr);
-            hipLaunchKernelGGL((search_kernel<M_COUNT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+            if (staged) hipLaunchKernelGGL((search_kernel<M_STAGE, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+            else hipLaunchKernelGGL((search_kernel<M_COUNT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+        } else if (staged) {
+            if (A.heavy_blocks > 0)
+                hipLaunchKernelGGL((search_kernel<M_EMIT, true>), ghx, b, 0, s, Ax, row_ptr, col_idx, 1);
+            hipLaunchKernelGGL(stage_redo_kernel<true>, dim3(std::min(gr.x, 64u)), b, 0, s, Ax, row_ptr, col_idx, 1);
         } else {
             hipLaunchKernelGGL((search_kernel<M_EMIT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (!emit) idx->staged_count = staged ? 1 : 0;
     if (emit && overflow) {
         hipLaunchKernelGGL(emit_epilogue, dim3(1), dim3(64), 0, s, (const unsigned long long *)idx->stats, overflow);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1207,6 +1466,12 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         if ((e = inclusive_scan_i64(idx->hcnt, idx->max_chunks, idx->tmp, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(heavy_degrees, dim3((unsigned)((idx->heavy_cap + 255) / 256)), dim3(256), 0, s, A,
                            row_ptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!emit && staged) {
+        PhaseScope ps(RHG_PHASE_PLAN, s);
+        hipLaunchKernelGGL(stage_split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, row_ptr, idx->sslot,
+                           n);
         e = hipGetLastError();
     }
     return e;

@@ -117,6 +117,12 @@ def test_sweep_and_per_query_paths_give_the_same_rows():
         # the same tested pairs in the same order: the same bytes
         assert np.array_equal(col_s, col_l)
         assert np.array_equal(col_q, col_r)
+        # rows staged by the count pass and copied by the emit pass, with
+        # slots large enough and with slots too small for most rows (those
+        # wavefronts searched again): the same bytes
+        for st in ({"stage": 1}, {"stage": 1, "stage_pct": 1}):
+            rp_x, col_x, _ = run_search(P, params, r, t, tuning=dict(tun, **st))
+            assert np.array_equal(rp_x, rp_s) and np.array_equal(col_x, col_s), st
         for rp_x, col_x in ((rp_s, col_s), (rp_w, col_w), (rp_q, col_q), (rp_m, col_m)):
             assert np.array_equal(canonical(rp_x, col_x), ocol)
 
@@ -250,6 +256,10 @@ def test_c2_full_graph_invariants_and_sampled_rows():
     # longest streams) instead of the LDS stage: the same bytes
     rp4, col4, _ = run_search(P, P.rhg_plan_radius(n, a, R, 2), r_o, t_o, tuning={"no_stream_stage": 1})
     assert np.array_equal(rp4, rp2) and np.array_equal(col4, col2)
+    # rows counted and searched again instead of staged (staging is the
+    # default from n = 2^19): the same bytes
+    rp5, col5, _ = run_search(P, P.rhg_plan_radius(n, a, R, 2), r_o, t_o, tuning={"stage": -1})
+    assert np.array_equal(rp5, rp2) and np.array_equal(col5, col2)
 
 
 def test_c3_full_size_points_and_sampled_rows():

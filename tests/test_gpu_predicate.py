@@ -26,6 +26,12 @@ TUNINGS = {
     # short for them (both passes rerun with in-place decisions)
     "exact_inline": {"exact_inline": 1},
     "list_overflow": {"heavy_points": 64, "defer_cap": 8},
+    # the count pass stages the light rows and the emit pass copies them;
+    # slots too small for most rows (those wavefronts searched again), and
+    # both with the overflowing list
+    "staged": {"heavy_points": 64, "stage": 1},
+    "staged_small_slots": {"heavy_points": 64, "stage": 1, "stage_pct": 1},
+    "staged_list_overflow": {"heavy_points": 64, "stage": 1, "defer_cap": 8},
 }
 
 

@@ -18,7 +18,9 @@ pytestmark = pytest.mark.gpu
 TUNINGS = [None, {"band_width": 0.5}, {"band_width": 3.0}, {"cell_target": 8}, {"heavy_points": 256},
            {"no_stream_stage": 1, "sweep_max": -1}, {"fp64_only": 1}, {"sweep_max": 1 << 30}, {"sweep_linear": 1},
            {"exact_inline": 1}, {"defer_cap": 1},
-           {"band_width": 1.0, "cell_target": 2, "heavy_points": 1024}]
+           {"band_width": 1.0, "cell_target": 2, "heavy_points": 1024},
+           {"stage": 1}, {"stage": 1, "stage_pct": 1}, {"stage": 1, "defer_cap": 1}, {"stage": 1, "exact_inline": 1},
+           {"stage": 1, "fp64_only": 1}, {"stage": 1, "band_width": 0.5, "stage_pct": 20, "heavy_points": 64}]
 
 
 def _cases(count=20, seed=20261202):

@@ -533,8 +533,11 @@ def main():
     m = res["nnz"] // 2
     sec = res["ms_per_step"] / 1000.0
     phases = res["phases"]
-    # the dominant kernel: the longer of the two search kernels (each phase
-    # brackets exactly that one launch on the library's stream)
+    # the dominant kernel: the longer of the two search passes.  The count
+    # phase brackets exactly the search kernel's launch on the library's
+    # stream; after a staged count the emit phase brackets the emit pass's
+    # launches (heavy chunks, the copy of the staged rows, the standby
+    # re-search), otherwise the one emit search kernel.
     dom = max((k for k in ("count", "emit") if phases.get(k, (0, 0))[1]), key=lambda k: phases[k][0])
     dom_ms = phases[dom][0]
     alg = algorithmic_bytes(dom, n, m)

@@ -68,7 +68,7 @@ void phase_end(void *rec, hipStream_t s)
 
 struct WsPlan {
     size_t keys, v0, band_start, dir, sr, st, rec, rt, heavy_end, hplan, hcnt, hitem, hscal, stats, wstat, dkeys, dchunk,
-        dcount, hset, dslot, stage, sslot, sovf, sbase, raux, tmp, total, tmp_bytes;
+        dcount, hset, dslot, stage, sslot, sovf, wsum, raux, tmp, total, tmp_bytes;
     int64_t max_chunks, rows_lcap, rows_mapcap, rows_nnz_cap;
 };
 
@@ -111,7 +111,7 @@ static WsPlan ws_plan(int64_t n, const Layout &L)
     w.stage = take(L.staged ? (size_t)L.stage_cap * 4 : 4);
     w.sslot = take(L.staged ? N * 4 : 4);
     w.sovf = take(L.staged ? (N + 63) / 64 : 1);
-    w.sbase = take((size_t)(L.B + 1) * 8);
+    w.wsum = take(L.staged ? (size_t)((N + 63) / 64) * 8 : 8);
     // canonical rows: room for the long rows and tiles of a graph of up to
     // twice the estimated entries (plus 2^23)
     w.rows_nnz_cap = (int64_t)std::min(9.0e18, 2.0 * L.entries_est + 8388608.0);
@@ -279,9 +279,9 @@ rhg_status rhg_build_index(const rhg_params *p, const double *r, const double *t
     idx->hset = (uint64_t *)(base + w.hset);
     idx->dslot = (int64_t *)(base + w.dslot);
     idx->stage = (int32_t *)(base + w.stage);
-    idx->sslot = (int32_t *)(base + w.sslot);
+    idx->sslot = (uint32_t *)(base + w.sslot);
     idx->sovf = (uint8_t *)(base + w.sovf);
-    idx->sbase = (int64_t *)(base + w.sbase);
+    idx->wsum = (int64_t *)(base + w.wsum);
     idx->hset_slots = idx->L.hset_slots;
     idx->rows_aux = base + w.raux;
     idx->rows_lcap = w.rows_lcap;

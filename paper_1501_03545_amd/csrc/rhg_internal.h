@@ -54,8 +54,10 @@ struct Layout {
     int64_t defer_cap;                // capacity of the undecided-pair list
     int64_t hset_slots;               // slots of the resolved-edge set (a power of two >= 2 defer_cap)
     int staged;                       // the count pass stages the light rows (the emit pass copies them)
-    int32_t scap[RHG_MAX_BANDS];      // staging slot per light query of band j (entries)
-    int64_t stage_cap;                // staging entries the workspace holds
+    float lmu_in[RHG_MAX_BANDS];      // staging slots: log2 of the expected degree at band j's edges
+    float lmu_out[RHG_MAX_BANDS];     //   (raised to bound the curve between them)
+    float stage_f;                    // staging slots: stage_pct / 100
+    int64_t stage_cap;                // staging words the workspace holds
 };
 
 // Expected degree of a point at radius r (threshold model): the other n - 1
@@ -155,10 +157,10 @@ struct rhg_index {
     unsigned long long *dcount;  // [0] pairs listed, [1] overflow flag
     uint64_t *hset;        // resolved edges (hset_slots)
     int64_t *dslot;        // staged count: the listed pair's staging entry (-1: none)
-    int32_t *stage;        // staged count: the light rows, a slot of scap[band] entries per sorted position
-    int32_t *sslot;        // staged count: per id, the light row's sorted position + 1 (0: heavy)
+    int32_t *stage;        // staged count: the light rows, one slot per light sorted position
+    uint32_t *sslot;       // staged count: per id, the slot's start / 4 + 1 (0: heavy, ~0: none)
     uint8_t *sovf;         // staged count: per light wavefront, a row outgrew its slot
-    int64_t *sbase;        // staged count: first staging entry of each band (B + 1)
+    int64_t *wsum;         // staged count: per wavefront, the inclusive prefix of its slots' words
     int staged_count;      // the last count pass staged its rows
     int64_t hset_slots;
     void *rows_aux;        // row sort: counters, long-row list, tile map

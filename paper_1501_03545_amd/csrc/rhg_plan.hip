@@ -241,28 +241,51 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     int64_t hs = 1;
     while (hs < 2 * L->defer_cap) hs <<= 1;
     L->hset_slots = hs;
-    // Staged count: each light query gets a slot of scap[j] words: its
-    // row's length, then room for its band's expected degree at the band's
-    // inner edge (the largest in the band) times stage_pct %, plus 16; a
-    // row that outgrows its slot is searched again by the emit pass.  The
-    // workspace holds the expected band populations plus ten standard
-    // deviations.
+    // Staged count: a light query's slot holds its row's length, then room
+    // for stage_pct % of mu + 5 sqrt(mu) + 8 entries (at most 2^24), mu the
+    // expected degree at the query's radius (log-linear between its band's
+    // edges, raised by the largest ratio of the true curve to that line at
+    // 15 inner points), in a multiple of 4 words.  A row that outgrows its
+    // slot is searched again by the emit pass.  The workspace holds the
+    // slots' expected total over the light bands' radii plus ten standard
+    // deviations and 64 of the largest slots; a slot's start / 4 + 1 must
+    // fit in 32 bits.
     const int st = t ? t->stage : 0;
     L->staged = (st > 0 || (st == 0 && p.n >= (int64_t)1 << 19)) && p.n >= 1 ? 1 : 0;
     L->stage_cap = 0;
     if (L->staged) {
-        const double pct = (t && t->stage_pct > 0) ? t->stage_pct / 100.0 : 1.5;
-        double cap = 0.0;
+        const double pct = (t && t->stage_pct > 0) ? t->stage_pct / 100.0 : 1.0;
+        L->stage_f = (float)pct;
+        double mean = 0.0, var = 0.0, maxw = 0.0;
         for (int j = 0; j < B; ++j) {
-            const double ed = expected_degree(n, a, R, L->E[j]);
-            const double sc = std::min(n, ceil(pct * ed) + 16.0) + 1.0;
-            L->scap[j] = (int32_t)sc;
-            const double F0 = (cosh(a * L->E[j]) - 1.0) / denom;
-            const double F1 = (cosh(a * L->E[j + 1]) - 1.0) / denom;
-            const double pts = n * std::max(0.0, std::min(1.0, F1) - F0);
-            cap += (pts + 10.0 * sqrt(pts) + 64.0) * sc;
+            const double e0 = L->E[j], e1 = L->E[j + 1];
+            const double m0 = std::max(expected_degree(n, a, R, e0), 1e-6);
+            const double m1 = std::max(expected_degree(n, a, R, e1), 1e-6);
+            double corr = 1.0;
+            for (int k = 1; k < 16; ++k) {
+                const double f = k / 16.0;
+                const double line = exp((1.0 - f) * log(m0) + f * log(m1));
+                corr = std::max(corr, expected_degree(n, a, R, e0 + (e1 - e0) * f) / line);
+            }
+            corr *= 1.001;
+            L->lmu_in[j] = (float)log2(m0 * corr);
+            L->lmu_out[j] = (float)log2(m1 * corr);
+            if (j < jh) continue;  // heavy bands: no slots
+            for (int sub = 0; sub < 64; ++sub) {
+                const double ra = e0 + (e1 - e0) * sub / 64.0, rb = e0 + (e1 - e0) * (sub + 1) / 64.0;
+                const double pts = n * std::max(0.0, (cosh(a * rb) - cosh(a * ra)) / denom);
+                // the largest slot of the sub-interval (the degree falls with r),
+                // with room for the device's single-precision rounding
+                const double f = (ra - e0) / (e1 - e0);
+                const double mu = exp2((1.0 - f) * L->lmu_in[j] + f * L->lmu_out[j]) * 1.01;
+                const double wd = std::min(pct * (mu + 5.0 * sqrt(mu) + 8.0), 16777216.0) + 8.0;
+                mean += pts * wd;
+                var += pts * wd * wd;
+                maxw = std::max(maxw, wd);
+            }
         }
-        L->stage_cap = (int64_t)std::min(cap, 4.0e9 * 8);
+        const double cap = mean + 10.0 * sqrt(var) + 64.0 * maxw + 1024.0;
+        L->stage_cap = (int64_t)std::min(cap, 4.0 * 4294967294.0);
     }
 }
 

@@ -93,18 +93,19 @@ struct SearchArgs {
     uint64_t *hset;                   // open-addressing set of listed edges (0 = empty slot)
     int64_t hmask;                    // its size - 1 (a power of two, at least twice dcap)
     int64_t col_cap;                  // emit pass: capacity of col_idx (< 0: unchecked)
-    // staged count: each light query's row goes to a slot of scap[band]
-    // entries at sbase[band] + (position - band start) * scap[band], its
-    // length first (-1: the wavefront outgrew a slot), then its entries;
-    // the count pass leaves each light row's position + 1 in sslot[id] (0:
-    // heavy row); the emit pass copies the slots out and searches again
-    // only the wavefronts flagged in sovf
-    int32_t scap[RHG_MAX_BANDS];
+    // staged count: each light query's row goes to a slot of slot_words
+    // words, the slots in sorted-position order (wavefront w's start at
+    // wsum[w - 1]), its length first (-1: the wavefront outgrew a slot),
+    // then its entries; the count pass leaves each light row's slot start /
+    // 4 + 1 in sslot[id] (0: heavy row, ~0: no slot); the emit pass copies
+    // the slots out and searches again only the wavefronts flagged in sovf
+    float lmu_in[RHG_MAX_BANDS], lmu_out[RHG_MAX_BANDS];
+    float stage_f;
     int64_t stage_cap;
     int32_t *stage;
-    int32_t *sslot;
+    uint32_t *sslot;
     uint8_t *sovf;
-    int64_t *sbase;
+    int64_t *wsum;
     int64_t *dslot;                   // the listed pair's staging entry (-1: none)
     int staged;                       // this count pass stages (its emit pass copies)
     int light_skip;                   // emit pass after a staged count: heavy chunks only
@@ -214,6 +215,22 @@ __device__ __forceinline__ void list_staged(const SearchArgs &A, int64_t q, int6
         A.dchunk[k] = -1;
         A.dslot[k] = slot;
     }
+}
+
+// The staging slot of a light query at radius r in band j, in units of 4
+// words: its row's length, then room for stage_f (mu + 5 sqrt(mu) + 8)
+// entries (at most 2^24), mu the query's expected degree (log-linear in r
+// between the band's edges, as the plan raised it).  The same
+// single-precision hardware steps wherever a slot is sized, so that every
+// kernel finds the same slots (the plan's estimate of their total allows
+// for the steps' rounding); a wavefront's 64 slots fit a 32-bit sum.
+__device__ __forceinline__ int slot_quads(const SearchArgs &A, int j, double r)
+{
+    const float w = (float)(A.E[j + 1] - A.E[j]);
+    const float t = w > 0.0f ? fminf(fmaxf((float)(r - A.E[j]) * __builtin_amdgcn_rcpf(w), 0.0f), 1.0f) : 0.0f;
+    const float mu = __builtin_amdgcn_exp2f(fmaf(t, A.lmu_out[j] - A.lmu_in[j], A.lmu_in[j]));
+    const float e = fminf(A.stage_f * (mu + 5.0f * __builtin_amdgcn_sqrtf(mu) + 8.0f), 16777216.0f);
+    return ((int)ceilf(e) + 1 + 3) >> 2;
 }
 
 // ------------------------------------------------------------ windows
@@ -604,11 +621,16 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
         out = col + row_ptr[id];
         lim = row_ptr[id + 1] - row_ptr[id];
     }
-    if (STAGE && active) {
-        const int jb = A.band_bits ? (int)(A.keys[p] >> (32 - A.band_bits)) : 0;
-        const int64_t sb = A.sbase[jb] + (p - A.band_start[jb]) * (int64_t)A.scap[jb];
-        out = A.stage + sb + 1;  // word 0 of the slot: the row's length
-        lim = max<int64_t>(0, min<int64_t>(A.scap[jb] - 1, A.stage_cap - sb - 1));
+    if (STAGE) {
+        // the slot: after the wavefront's earlier lanes' slots; word 0 holds
+        // the row's length
+        int quads = 0;
+        if (active) quads = slot_quads(A, A.band_bits ? (int)(A.keys[p] >> (32 - A.band_bits)) : 0, rq);
+        int wt;
+        const int64_t wv = base >> 6;
+        const int64_t sb = (wv ? A.wsum[wv - 1] : 0) + 4 * (int64_t)wave_excl_sum(quads, lane, &wt);
+        out = A.stage + sb + 1;
+        lim = active ? max<int64_t>(0, min<int64_t>(4 * (int64_t)quads - 1, A.stage_cap - sb - 1)) : 0;
     }
     int64_t pend = 0;  // STAGE: entries of the row still pending
     const int B = A.B;
@@ -1013,10 +1035,11 @@ __device__ void light_wave(const SearchArgs &A, int64_t base, int64_t *row_ptr, 
     if (wovf && lane == 0) A.sovf[base >> 6] = 1;
     if (!active) return;
     if (STAGE) {
-        // the degree, with the position + 1 above it (split off before the
-        // row scan), and the slot's length word
-        row_ptr[id + 1] = (int64_t)(((uint64_t)(p + 1) << 32) | (uint64_t)(cnt - pend));
+        // the degree, with the slot's start / 4 + 1 above it (split off
+        // before the row scan), and the slot's length word
         const int64_t sb = (int64_t)(out - A.stage) - 1;
+        const uint64_t hs = sb < A.stage_cap ? (uint64_t)(sb >> 2) + 1 : 0xffffffffull;
+        row_ptr[id + 1] = (int64_t)((hs << 32) | (uint64_t)(cnt - pend));
         if (sb < A.stage_cap) A.stage[sb] = wovf ? -1 : (int32_t)cnt;
     } else if (EMIT) {
         if (cnt != lim) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
@@ -1060,16 +1083,33 @@ search_kernel(SearchArgs A, int64_t *__restrict__ row_ptr, int32_t *__restrict__
     }
 }
 
-// After a staged count: each light row's degree carries its sorted
-// position + 1 in the upper 32 bits; they move to sslot (0 for the heavy
-// rows, whose degrees heavy_degrees wrote) before the row scan.
-__global__ void __launch_bounds__(256) stage_split_kernel(int64_t *__restrict__ row_ptr, int32_t *__restrict__ sslot,
+// Before a staged count: per wavefront of 64 sorted positions, the words of
+// its light queries' slots (the search kernel sizes them the same way).
+__global__ void __launch_bounds__(256) stage_wave_words(SearchArgs A, int64_t *__restrict__ wsum, int64_t waves)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t hend = *A.heavy_end;
+    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < waves; w += (int64_t)gridDim.x * 4) {
+        const int64_t p = w * 64 + lane;
+        int quads = 0;
+        if (p < A.n && p >= hend)
+            quads = slot_quads(A, A.band_bits ? (int)(A.keys[p] >> (32 - A.band_bits)) : 0, A.sr[p]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) quads += __shfl_xor(quads, o, 64);
+        if (lane == 0) wsum[w] = 4 * (int64_t)quads;
+    }
+}
+
+// After a staged count: each light row's degree carries its slot's start /
+// 4 + 1 in the upper 32 bits; they move to sslot (0 for the heavy rows,
+// whose degrees heavy_degrees wrote) before the row scan.
+__global__ void __launch_bounds__(256) stage_split_kernel(int64_t *__restrict__ row_ptr, uint32_t *__restrict__ sslot,
                                                           int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const uint64_t v = (uint64_t)row_ptr[i + 1];
-    sslot[i] = (int32_t)(v >> 32);
+    sslot[i] = (uint32_t)(v >> 32);
     row_ptr[i + 1] = (int64_t)(v & 0xffffffffull);
 }
 
@@ -1091,43 +1131,28 @@ stage_copy_kernel(SearchArgs A, const int64_t *__restrict__ row_ptr, int32_t *__
 {
     // a col_idx buffer too small for the graph: write nothing
     if (A.col_cap >= 0 && uni64(row_ptr[A.n]) > A.col_cap) return;
-    __shared__ int32_t bstart[RHG_MAX_BANDS + 1], bcap[RHG_MAX_BANDS + 1];
-    __shared__ int64_t bbase[RHG_MAX_BANDS + 1];
-    for (int j = threadIdx.x; j <= A.B; j += 256) {
-        bstart[j] = A.band_start[j];
-        bbase[j] = A.sbase[j];
-        bcap[j] = j < A.B ? A.scap[j] : 0;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t wstride = (int64_t)gridDim.x * 4;
     for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w * 64 < A.n; w += wstride) {
         const int64_t id = w * 64 + lane;
         int64_t dst = 0, rl = 0, sb = 0;
-        int dl = 0;  // entries the slot holds at most
         bool has = false;
         if (id < A.n) {
-            const int32_t sp = A.sslot[id];
+            const uint32_t hs = A.sslot[id];
             dst = row_ptr[id];
             rl = row_ptr[id + 1] - dst;
-            if (sp > 0 && rl > 0) {
-                const int64_t p = sp - 1;
-                int j = 0;  // the last band starting at or before p
-#pragma unroll
-                for (int h = 32; h > 0; h >>= 1)
-                    if (j + h < A.B && bstart[j + h] <= p) j += h;
-                sb = bbase[j] + (p - bstart[j]) * (int64_t)bcap[j];
-                if (sb < A.stage_cap) {
-                    has = true;
-                    dl = (int)min<int64_t>(bcap[j] - 1, A.stage_cap - sb - 1);
-                }
+            if (hs != 0u && hs != 0xffffffffu && rl > 0) {
+                sb = (int64_t)(hs - 1u) * 4;
+                has = sb < A.stage_cap;
             }
         }
         int len = -2;
         if (has) len = A.stage[sb];
+        // entries loaded per row: its row_ptr length, kept inside the
+        // staging area (a row whose slot is shorter is not stored)
         int tot;
-        const int pre = wave_excl_sum(has ? (int)min<int64_t>(rl, dl) : 0, lane, &tot);
+        const int pre = wave_excl_sum(has ? (int)min<int64_t>(rl, A.stage_cap - sb - 1) : 0, lane, &tot);
         constexpr int COPY_BATCH = 5;
         for (int e0 = 0; e0 < tot; e0 += 64 * COPY_BATCH) {
             int32_t v[COPY_BATCH];
@@ -1236,14 +1261,6 @@ __global__ void search_prologue(SearchArgs A, int jh, int32_t *heavy_end, int64_
         A.hscal[0] = 0;
         A.dcount[0] = 0;
         A.dcount[1] = 0;
-        if (A.staged) {
-            int64_t b = 0;
-            for (int j = 0; j < A.B; ++j) {
-                A.sbase[j] = b;
-                b += (int64_t)(A.band_start[j + 1] - A.band_start[j]) * A.scap[j];
-            }
-            A.sbase[A.B] = b;
-        }
     }
 }
 
@@ -1346,12 +1363,16 @@ static void make_search_args(rhg_index *idx, SearchArgs &A)
     A.dcap = L.defer_cap;
     A.hset = idx->hset;
     A.hmask = idx->hset_slots - 1;
-    for (int j = 0; j < L.B; ++j) A.scap[j] = L.scap[j];
+    for (int j = 0; j < L.B; ++j) {
+        A.lmu_in[j] = L.lmu_in[j];
+        A.lmu_out[j] = L.lmu_out[j];
+    }
+    A.stage_f = L.stage_f;
     A.stage_cap = L.stage_cap;
     A.stage = idx->stage;
     A.sslot = idx->sslot;
     A.sovf = idx->sovf;
-    A.sbase = idx->sbase;
+    A.wsum = idx->wsum;
     A.dslot = idx->dslot;
     A.staged = L.staged;
     A.light_skip = 0;
@@ -1372,6 +1393,15 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         hipLaunchKernelGGL(search_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (n <= 0) return hipSuccess;
+        if (L.staged) {
+            // the staging slots' starts: per wavefront its slots' words, then
+            // their inclusive prefix
+            const int64_t waves = (n + 63) / 64;
+            hipLaunchKernelGGL(stage_wave_words, dim3((unsigned)std::min<int64_t>((waves + 3) / 4, 8192)), dim3(256), 0,
+                               s, A, idx->wsum, waves);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = inclusive_scan_i64(idx->wsum, waves, idx->tmp, s)) != hipSuccess) return e;
+        }
         if (items > 0) {
             const unsigned g = (unsigned)((items + 255) / 256);
             hipLaunchKernelGGL(heavy_plan_len, dim3(g), dim3(256), 0, s, A);

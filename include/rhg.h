@@ -101,14 +101,18 @@ typedef struct {
                             * decisions; same bytes out                     */
     int32_t stage;         /* 1: the count pass also writes each light
                             * query's row into a staging area of the index
-                            * (a slot per query sized from its band's
-                            * expected degree) and the emit pass copies the
-                            * rows out instead of searching again (a row
-                            * that outgrew its slot is searched again);
+                            * (a slot per query sized from its expected
+                            * degree mu at its radius: mu + 5 sqrt(mu) + 8
+                            * entries) and the emit pass copies the rows out
+                            * instead of searching again (a wavefront with a
+                            * row that outgrew its slot is searched again);
                             * -1: count and search again; 0: automatic
-                            * (staged from n = 2^19); same bytes out        */
-    int32_t stage_pct;     /* slot size, percent of the expected degree at
-                            * the band's inner edge, plus 16 (0: 150)      */
+                            * (staged from n = 2^19).  Same bytes out; the
+                            * workspace grows by the slots, about 4 (2m +
+                            * 30n) bytes at mean degree 20 (26.5 GB instead
+                            * of 6.4 GB at n = 1e8)                         */
+    int32_t stage_pct;     /* slot size, percent of mu + 5 sqrt(mu) + 8
+                            * (0: 100)                                      */
 } rhg_tuning;
 
 /* Device-side diagnostics of the count and emit passes over an index.  The
@@ -213,7 +217,9 @@ rhg_status rhg_build_index(const rhg_params *p /* host */, const double *r,
 
 /* Runs the neighbour search and writes the CSR row offsets: row_ptr[0] = 0,
  * row_ptr[i + 1] - row_ptr[i] = deg(i) (device, n + 1 int64); row_ptr[n] =
- * 2m.  Nothing but the degrees is kept: the emit pass searches again.
+ * 2m.  Unstaged, nothing but the degrees is kept and the emit pass
+ * searches again; staged (rhg_tuning.stage), the light rows also go to
+ * their slots in the index's workspace for the emit pass to copy.
  * Asynchronous. */
 rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
 
@@ -222,7 +228,9 @@ rhg_status rhg_count_edges(rhg_index *idx, int64_t *row_ptr, void *stream);
 /* ------------------------------------------------------------------ */
 
 /* Writes the neighbours of vertex i to col_idx[row_ptr[i] .. row_ptr[i+1])
- * (device, int32) by repeating the count pass's search in the same order.
+ * (device, int32) by repeating the count pass's search in the same order,
+ * or, after a staged count, by searching the heavy queries' chunks again
+ * and copying the light rows from their slots (the same bytes either way).
  * row_ptr must be the output of rhg_count_edges on the same index.  Each
  * undirected edge appears in both rows; there are no self-loops.
  * canonical_rows = 0: rows are in search order, deterministic for a given

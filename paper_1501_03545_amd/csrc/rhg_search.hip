@@ -38,7 +38,11 @@
 // angle key).  A long union of disjoint narrow windows is instead split into
 // the lanes' own windows, worked through as one stream of 64 candidates per
 // step.  The emit pass repeats the count pass's search in the same order and
-// writes each row in place.
+// writes each row in place; or, staged (large graphs), the count pass also
+// writes each light row into a slot sized from the query's expected degree,
+// and the emit pass searches only the heavy chunks, copies the light rows
+// from their slots in id order and searches again the few wavefronts whose
+// rows outgrew a slot.
 #include <string.h>
 
 #include <algorithm>

@@ -147,4 +147,42 @@ __device__ __forceinline__ uint64_t slot_hash(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// Exclusive prefix sum of v over the wavefront's 64 lanes (every lane takes
+// part); *total is the wavefront's sum.
+__device__ __forceinline__ int wave_excl_sum(int v, int lane, int *total)
+{
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// The staging slot of a light query at radius r in band j, in units of 4
+// words: its row's length, then room for f (mu + 5 sqrt(mu) + 8) entries
+// (at most 2^24), mu the query's expected degree (log-linear in r between
+// the band's edges E[j], E[j+1] through the plan's log2 values lin[j],
+// lout[j]).  The same single-precision hardware steps wherever a slot is
+// sized, so that every kernel finds the same slots (the plan's estimate of
+// their total allows for the steps' rounding); a wavefront's 64 slots fit
+// a 32-bit sum.
+__device__ __forceinline__ int stage_slot_quads(const double *E, const float *lin, const float *lout, float f, int j,
+                                                double r)
+{
+    const float w = (float)(E[j + 1] - E[j]);
+    const float t = w > 0.0f ? fminf(fmaxf((float)(r - E[j]) * __builtin_amdgcn_rcpf(w), 0.0f), 1.0f) : 0.0f;
+    const float mu = __builtin_amdgcn_exp2f(fmaf(t, lout[j] - lin[j], lin[j]));
+    const float e = fminf(f * (mu + 5.0f * __builtin_amdgcn_sqrtf(mu) + 8.0f), 16777216.0f);
+    return ((int)ceilf(e) + 1 + 3) >> 2;
+}
+
+// A staged row's entry whose decision the resolving kernel makes: the
+// candidate's id with this bit set, until it becomes the id or
+// STAGE_REJECT.
+constexpr uint32_t STAGE_PENDING = 0x80000000u;
+constexpr int32_t STAGE_REJECT = -1;
+
 }  // namespace rhg

@@ -197,6 +197,13 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
 hipError_t launch_query_rows(rhg_index *idx, const int32_t *qpos, int64_t k, int64_t *cnt, const int64_t *optr,
                              int32_t *ocol, int emit, hipStream_t s);
 // The temperature model's count (emit = 0) or emit pass over the index.
+// Staged counts (rhg_search.hip): slot starts and cleared overflow flags
+// before the count, slot starts split off the degrees after it, and the
+// emit pass's copy of the light rows.
+hipError_t launch_stage_slots(rhg_index *idx, hipStream_t s);
+hipError_t launch_stage_split(rhg_index *idx, int64_t *row_ptr, hipStream_t s);
+hipError_t launch_stage_copy(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx, int64_t col_cap,
+                             hipStream_t s);
 hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_t *col_idx, int emit,
                               hipStream_t s, int64_t col_cap);
 

@@ -118,11 +118,6 @@ struct SearchArgs {
 // Passes of the search kernels: count, emit.
 enum { M_COUNT = 0, M_EMIT = 1, M_STAGE = 2 };
 
-// A staged row's entry whose decision the resolving kernel makes: the
-// candidate's id with this bit; the kernel rewrites it to the id or to
-// STAGE_REJECT.
-constexpr uint32_t STAGE_PENDING = 0x80000000u;
-constexpr int32_t STAGE_REJECT = -1;
 
 constexpr float P32_ACC = 1.0f - 0x1p-18f;
 constexpr float P32_REJ = 1.0f + 0x1p-18f;
@@ -221,20 +216,9 @@ __device__ __forceinline__ void list_staged(const SearchArgs &A, int64_t q, int6
     }
 }
 
-// The staging slot of a light query at radius r in band j, in units of 4
-// words: its row's length, then room for stage_f (mu + 5 sqrt(mu) + 8)
-// entries (at most 2^24), mu the query's expected degree (log-linear in r
-// between the band's edges, as the plan raised it).  The same
-// single-precision hardware steps wherever a slot is sized, so that every
-// kernel finds the same slots (the plan's estimate of their total allows
-// for the steps' rounding); a wavefront's 64 slots fit a 32-bit sum.
 __device__ __forceinline__ int slot_quads(const SearchArgs &A, int j, double r)
 {
-    const float w = (float)(A.E[j + 1] - A.E[j]);
-    const float t = w > 0.0f ? fminf(fmaxf((float)(r - A.E[j]) * __builtin_amdgcn_rcpf(w), 0.0f), 1.0f) : 0.0f;
-    const float mu = __builtin_amdgcn_exp2f(fmaf(t, A.lmu_out[j] - A.lmu_in[j], A.lmu_in[j]));
-    const float e = fminf(A.stage_f * (mu + 5.0f * __builtin_amdgcn_sqrtf(mu) + 8.0f), 16777216.0f);
-    return ((int)ceilf(e) + 1 + 3) >> 2;
+    return stage_slot_quads(A.E, A.lmu_in, A.lmu_out, A.stage_f, j, r);
 }
 
 // ------------------------------------------------------------ windows
@@ -479,17 +463,6 @@ __device__ __forceinline__ double wave_max(double v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
-}
-__device__ __forceinline__ int wave_excl_sum(int v, int lane, int *total)
-{
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    *total = __shfl(x, 63, 64);
-    return x - v;
 }
 // Lane l's value, as a wave-uniform scalar.
 __device__ __forceinline__ int64_t uni_lane64(int64_t v, int l)
@@ -1397,15 +1370,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         hipLaunchKernelGGL(search_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (n <= 0) return hipSuccess;
-        if (L.staged) {
-            // the staging slots' starts: per wavefront its slots' words, then
-            // their inclusive prefix
-            const int64_t waves = (n + 63) / 64;
-            hipLaunchKernelGGL(stage_wave_words, dim3((unsigned)std::min<int64_t>((waves + 3) / 4, 8192)), dim3(256), 0,
-                               s, A, idx->wsum, waves);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if ((e = inclusive_scan_i64(idx->wsum, waves, idx->tmp, s)) != hipSuccess) return e;
-        }
+        if (L.staged && (e = launch_stage_slots(idx, s)) != hipSuccess) return e;
         if (items > 0) {
             const unsigned g = (unsigned)((items + 255) / 256);
             hipLaunchKernelGGL(heavy_plan_len, dim3(g), dim3(256), 0, s, A);
@@ -1441,9 +1406,6 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     // emit pass copies them, emits the heavy chunks and searches again the
     // wavefronts whose rows outgrew their slots
     const bool staged = emit ? idx->staged_count != 0 : L.staged != 0;
-    const int64_t waves = (n + 63) / 64;
-    if (!emit && staged)
-        hipLaunchKernelGGL(fill_u8, dim3((unsigned)((waves + 255) / 256)), dim3(256), 0, s, A.sovf, waves);
     if (emit && staged) {
         A.light_skip = 1;
         Ax.light_skip = 1;
@@ -1502,13 +1464,50 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
                            row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (!emit && staged) {
-        PhaseScope ps(RHG_PHASE_PLAN, s);
-        hipLaunchKernelGGL(stage_split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, row_ptr, idx->sslot,
-                           n);
-        e = hipGetLastError();
-    }
+    if (!emit && staged) e = launch_stage_split(idx, row_ptr, s);
     return e;
+}
+
+// The staging slots' starts before a staged count (per wavefront its
+// slots' words, then their inclusive prefix) and the overflow flags
+// cleared.  heavy_end must be set.
+hipError_t launch_stage_slots(rhg_index *idx, hipStream_t s)
+{
+    SearchArgs A;
+    make_search_args(idx, A);
+    const int64_t waves = (idx->n + 63) / 64;
+    if (waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stage_wave_words, dim3((unsigned)std::min<int64_t>((waves + 3) / 4, 8192)), dim3(256), 0, s,
+                       A, idx->wsum, waves);
+    hipLaunchKernelGGL(fill_u8, dim3((unsigned)((waves + 255) / 256)), dim3(256), 0, s, idx->sovf, waves);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return inclusive_scan_i64(idx->wsum, waves, idx->tmp, s);
+}
+
+// After a staged count (the heavy rows' degrees written): the slot starts
+// split off the degrees.
+hipError_t launch_stage_split(rhg_index *idx, int64_t *row_ptr, hipStream_t s)
+{
+    if (idx->n <= 0) return hipSuccess;
+    PhaseScope ps(RHG_PHASE_PLAN, s);
+    hipLaunchKernelGGL(stage_split_kernel, dim3((unsigned)((idx->n + 255) / 256)), dim3(256), 0, s, row_ptr,
+                       idx->sslot, idx->n);
+    return hipGetLastError();
+}
+
+// Emit pass after a staged count: the light rows copied from their slots.
+hipError_t launch_stage_copy(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx, int64_t col_cap,
+                             hipStream_t s)
+{
+    SearchArgs A;
+    make_search_args(idx, A);
+    A.col_cap = col_cap;
+    const int64_t waves = (idx->n + 63) / 64;
+    if (waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stage_copy_kernel, dim3((unsigned)std::min<int64_t>((waves + 3) / 4, 16384)), dim3(256), 0, s,
+                       A, row_ptr, col_idx);
+    return hipGetLastError();
 }
 
 

@@ -31,7 +31,11 @@
 // other query is one lane of a wavefront of 64 consecutive sorted
 // positions, which walks its own window in every band.  Rows come out in
 // (band, position) order; the emit pass repeats the count pass's work in
-// the same order.
+// the same order, or, staged (large graphs), the count pass also writes
+// each light row into its slot of the index's staging area (the threshold
+// search's slots) and the emit pass searches only the heavy chunks again,
+// copies the light rows and searches again the wavefronts whose rows
+// outgrew a slot.
 #include <string.h>
 
 #include <algorithm>
@@ -84,9 +88,27 @@ struct TempArgs {
     int tally;                        // count pass: this launch adds to the candidate and coin tallies
     longlong2 *tal;                   // per-wavefront table of (candidates, coins)
     int64_t tal_slots;
+    // staged count: each light query's row goes to its slot (sized as in
+    // the threshold search, wavefront w's slots from wsum[w - 1]), its
+    // length first (-1: the wavefront outgrew a slot), then its entries;
+    // an undecided entry carries STAGE_PENDING until the resolving kernel
+    // writes the id or STAGE_REJECT; wavefronts with a row longer than its
+    // slot are flagged in sovf
+    float lmu_in[RHG_MAX_BANDS], lmu_out[RHG_MAX_BANDS];
+    float stage_f;
+    int band_bits;
+    const uint32_t *keys;
+    int32_t *stage;
+    int64_t stage_cap;
+    const int64_t *wsum;
+    uint8_t *sovf;
+    int64_t *dslot;
+    int staged;                       // count pass: stage the light rows
+    int light_skip;                   // emit pass after a staged count: heavy chunks only
 };
 
-enum { T_COUNT = 0, T_EMIT = 1 };
+// T_STAGE: counted as T_COUNT, the light rows also written to their slots.
+enum { T_COUNT = 0, T_EMIT = 1, T_STAGE = 2 };
 
 // The pair's coin: a = k + 1 in [1, 2^53].
 __device__ __forceinline__ uint64_t temp_coin(uint32_t ida, uint32_t idb, uint32_t k0, uint32_t k1)
@@ -131,7 +153,8 @@ __device__ __noinline__ int temp_exact(double rq, double tq, double rc, double t
 // needs a stack and the caller's registers, so the fast kernels keep it
 // out): the count pass instead lists the pair for the resolving kernel and
 // counts it there if it is an edge, and the emit pass finds the resolved
-// edges in the set.  1 edge, 0 not.  The count pass tallies the coins it
+// edges in the set.  1 edge, 0 not, 2 (a staged light row's pair) listed
+// by the caller with its staging entry.  The count pass tallies the coins it
 // draws in `coins`; `chunk` is the heavy chunk of the pair (-1: light).
 template <int MODE, bool EXACT>
 __device__ __forceinline__ int temp_decide(const TempArgs &A, int64_t q, double tq, float4 fq, int64_t c,
@@ -141,7 +164,7 @@ __device__ __forceinline__ int temp_decide(const TempArgs &A, int64_t q, double 
     int v = 2;
     uint64_t a = 0;
     if (!A.use_p32) {
-        if (MODE == T_COUNT) ++coins;
+        if (MODE != T_EMIT) ++coins;
         a = temp_coin(idq, idc, A.k0, A.k1);
     } else {
         // P = cosh d / cosh R: e'_q m'_c + m'_q e'_c + s'_q s'_c sin^2(dtheta/2),
@@ -158,7 +181,7 @@ __device__ __forceinline__ int temp_decide(const TempArgs &A, int64_t q, double 
         float P = fmaf(fq.x, fc.y, fq.y * fc.x);
         P = fmaf(fq.z * fc.z, s * s, P);
         if (P > A.Ktr) return 0;  // d > rho: p(d) <= 2^-53 <= u
-        if (MODE == T_COUNT) ++coins;
+        if (MODE != T_EMIT) ++coins;
         a = temp_coin(idq, idc, A.k0, A.k1);
         const uint64_t b = (1ull << 53) - a;
         if (b == 0) return 0;
@@ -181,9 +204,11 @@ __device__ __forceinline__ int temp_decide(const TempArgs &A, int64_t q, double 
         }
         if (v != 2) return v;
     }
-    if (EXACT) return temp_exact(A.sr[q], tq, A.sr[c], tc, a, A.R, A.twoT, A.stats, MODE == T_COUNT && A.use_p32);
+    if (EXACT) return temp_exact(A.sr[q], tq, A.sr[c], tc, a, A.R, A.twoT, A.stats, MODE != T_EMIT && A.use_p32);
+    // a staged light row lists the pair itself, with its staging entry
+    if (MODE == T_STAGE && chunk < 0) return 2;
     const uint64_t key = pair_key(q, c);
-    if (MODE == T_COUNT) {
+    if (MODE != T_EMIT) {
         const unsigned long long k = atomicAdd(&A.dcount[0], 1ull);
         if ((int64_t)k < A.dcap) {
             A.dkeys[k] = key;
@@ -461,12 +486,15 @@ __device__ void temp_chunk(const TempArgs &A, int64_t c, const int64_t *row_ptr,
 // ------------------------------------------------------------ light queries
 
 // One lane per query: every band's window, candidate by candidate.  The
-// count pass writes the degree to row_ptr[id + 1]; the emit pass writes the
-// row and checks its length.
+// count pass writes the degree to row_ptr[id + 1] (staged: with the slot's
+// start / 4 + 1 above it, and the row into the slot); the emit pass writes
+// the row and checks its length.  Every lane of a wavefront of 64
+// consecutive positions calls it together.
 template <int MODE, bool EXACT>
 __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32_t *col)
 {
     constexpr bool EMIT = MODE == T_EMIT;
+    constexpr bool STAGE = MODE == T_STAGE;
     const bool active = q < A.n && q >= *A.heavy_end;
     double tq = 0.0;
     float4 fq = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -482,6 +510,20 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
     }
     const int64_t row_start = out;
     const int64_t cap_end = (EMIT && A.col_cap >= 0) ? A.col_cap : INT64_MAX;
+    // STAGE: the slot after the wavefront's earlier lanes' slots; word 0
+    // holds the row's length, entry k goes to word 1 + k while k < lim
+    int64_t sb = 0, lim = 0, pend = 0;
+    // (a wavefront past the last point has no slots, and no prefix entry)
+    if (STAGE && __ballot(active) != 0) {
+        int quads = 0;
+        if (active)
+            quads = stage_slot_quads(A.E, A.lmu_in, A.lmu_out, A.stage_f,
+                                     A.band_bits ? (int)(A.keys[q] >> (32 - A.band_bits)) : 0, A.sr[q]);
+        int wt;
+        const int64_t wv = q >> 6;
+        sb = (wv ? A.wsum[wv - 1] : 0) + 4 * (int64_t)wave_excl_sum(quads, (int)(threadIdx.x & 63), &wt);
+        lim = active ? max<int64_t>(0, min<int64_t>(4 * (int64_t)quads - 1, A.stage_cap - sb - 1)) : 0;
+    }
     int64_t cnt = 0;
     int cand = 0, coins = 0;
     for (int j = 0; j < A.B; ++j) {
@@ -506,7 +548,20 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
                 }
                 if (c == q) continue;
                 ++cand;
-                if (!temp_decide<MODE, EXACT>(A, q, tq, fq, c, tc, fc, coins, -1)) continue;
+                const int v = temp_decide<MODE, EXACT>(A, q, tq, fq, c, tc, fc, coins, -1);
+                if (!v) continue;
+                if (STAGE) {
+                    if (v == 2) {
+                        const unsigned long long k = atomicAdd(&A.dcount[0], 1ull);
+                        if ((int64_t)k < A.dcap) {
+                            A.dkeys[k] = pair_key(q, c);
+                            A.dchunk[k] = -1;
+                            A.dslot[k] = cnt < lim ? sb + 1 + cnt : -1;
+                        }
+                        ++pend;
+                    }
+                    if (cnt < lim) A.stage[sb + 1 + cnt] = __float_as_int(fc.w) | (v == 2 ? (int)STAGE_PENDING : 0);
+                }
                 if (EMIT) {
                     const int64_t o = row_start + cnt;
                     if (o < row_end && o < cap_end) col[o] = __float_as_int(fc.w);
@@ -516,9 +571,19 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
         }
     }
     if (!EMIT && A.tally) temp_tally(A, cand, coins, (q >> 6) % A.tal_slots);
+    // a row that outgrew its slot: the emit pass searches this wavefront again
+    const bool wovf = STAGE && __ballot(active && cnt > lim) != 0;
+    if (wovf && (threadIdx.x & 63) == 0) A.sovf[q >> 6] = 1;
     if (!active) return;
-    if (!EMIT) row_ptr[id + 1] = cnt;
-    else if (cnt != row_end - row_start) atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+    if (STAGE) {
+        const uint64_t hs = sb < A.stage_cap ? (uint64_t)(sb >> 2) + 1 : 0xffffffffull;
+        row_ptr[id + 1] = (int64_t)((hs << 32) | (uint64_t)(cnt - pend));
+        if (sb < A.stage_cap) A.stage[sb] = wovf ? -1 : (int32_t)cnt;
+    } else if (!EMIT) {
+        row_ptr[id + 1] = cnt;
+    } else if (cnt != row_end - row_start) {
+        atomicAdd(&A.stats[ST_EMIT_MISMATCH], 1ull);
+    }
 }
 
 // Heavy chunks on the first heavy_blocks workgroups, light queries (256 a
@@ -536,9 +601,30 @@ __global__ void __launch_bounds__(256) temp_kernel(TempArgs A, int64_t *__restri
         for (int64_t c = blockIdx.x; c < nch; c += A.heavy_blocks) temp_chunk<MODE, EXACT>(A, c, row_ptr, col_idx);
         return;
     }
+    // emit pass after a staged count: the light rows are copied (and the
+    // wavefronts whose rows outgrew their slots searched again) by the
+    // kernels below
+    if (A.light_skip) return;
     const int64_t lb = (A.n + 255) / 256, nb = (int64_t)gridDim.x - A.heavy_blocks;
     for (int64_t b = (int64_t)blockIdx.x - A.heavy_blocks; b < lb; b += nb)
         temp_light<MODE, EXACT>(A, b * 256 + threadIdx.x, row_ptr, col_idx);
+}
+
+// Emit pass after a staged count: the wavefronts whose rows outgrew their
+// slots, searched again.  Each wavefront reads 64 flags at a time.
+template <bool EXACT>
+__global__ void __launch_bounds__(256) temp_redo_kernel(TempArgs A, int64_t *__restrict__ row_ptr,
+                                                        int32_t *__restrict__ col, int gate)
+{
+    if (A.col_cap >= 0 && tuni64(row_ptr[A.n]) > A.col_cap) return;
+    if (gate && (__builtin_amdgcn_readfirstlane((int)A.dcount[1]) != 0) != EXACT) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (A.n + 63) / 64;
+    for (int64_t g0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; g0 < waves; g0 += (int64_t)gridDim.x * 256) {
+        const int64_t w = g0 + lane;
+        for (uint64_t m = __ballot(w < waves && A.sovf[w]); m; m &= m - 1)
+            temp_light<T_EMIT, EXACT>(A, (g0 + __ffsll((unsigned long long)m) - 1) * 64 + lane, row_ptr, col);
+    }
 }
 
 // After the fast count pass: decide the listed pairs exactly, count the
@@ -555,12 +641,17 @@ __global__ void __launch_bounds__(256) temp_resolve(TempArgs A, int64_t *__restr
         const int64_t q = (int64_t)((key >> 32) & 0x7fffffffull), c = (int64_t)(key & 0xffffffffull);
         const float4 fq = A.rec[q], fc = A.rec[c];
         const uint64_t a = temp_coin((uint32_t)__float_as_int(fq.w), (uint32_t)__float_as_int(fc.w), A.k0, A.k1);
-        if (!temp_exact(A.sr[q], A.st[q], A.sr[c], A.st[c], a, A.R, A.twoT, A.stats, 1)) continue;
+        const int edge = temp_exact(A.sr[q], A.st[q], A.sr[c], A.st[c], a, A.R, A.twoT, A.stats, 1);
+        const int32_t ch = A.dchunk[i];
+        if (A.staged && ch < 0) {  // the staged row's pending entry, decided
+            const int64_t slot = A.dslot[i];
+            if (slot >= 0) A.stage[slot] = edge ? __float_as_int(fc.w) : STAGE_REJECT;
+        }
+        if (!edge) continue;
         for (uint64_t h = slot_hash(key) & (uint64_t)A.hmask;; h = (h + 1) & (uint64_t)A.hmask) {
             const unsigned long long prev = atomicCAS((unsigned long long *)&A.hset[h], 0ull, (unsigned long long)key);
             if (prev == 0ull || prev == key) break;
         }
-        const int32_t ch = A.dchunk[i];
         if (ch >= 0) atomicAdd((unsigned long long *)&A.hcnt[ch], 1ull);
         else atomicAdd((unsigned long long *)&row_ptr[__float_as_int(fq.w) + 1], 1ull);
     }
@@ -625,6 +716,24 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
     A.tally = 1;
     A.tal = (longlong2 *)idx->wstat;
     A.tal_slots = std::max<int64_t>((idx->n + 63) / 64, 1);
+    for (int j = 0; j < L.B; ++j) {
+        A.lmu_in[j] = L.lmu_in[j];
+        A.lmu_out[j] = L.lmu_out[j];
+    }
+    A.stage_f = L.stage_f;
+    A.band_bits = L.band_bits;
+    A.keys = idx->keys;
+    A.stage = idx->stage;
+    A.stage_cap = L.stage_cap;
+    A.wsum = idx->wsum;
+    A.sovf = idx->sovf;
+    A.dslot = idx->dslot;
+    // staged: the count pass writes the light rows into their slots, the
+    // emit pass searches the heavy chunks again, copies the light rows and
+    // searches again the wavefronts whose rows outgrew their slots
+    const bool staged = emit ? idx->staged_count != 0 : L.staged != 0;
+    A.staged = staged ? 1 : 0;
+    A.light_skip = (emit && staged) ? 1 : 0;
     const int64_t n = idx->n;
     const int64_t items = idx->heavy_cap * L.B;
     hipError_t e;
@@ -633,6 +742,7 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
         hipLaunchKernelGGL(temp_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (n <= 0) return hipSuccess;
+        if (staged && (e = launch_stage_slots(idx, s)) != hipSuccess) return e;
         if (items > 0) {
             const unsigned g = (unsigned)((items + 255) / 256);
             hipLaunchKernelGGL(temp_plan_len, dim3(g), dim3(256), 0, s, A);
@@ -662,13 +772,27 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
     if (!emit)
         hipLaunchKernelGGL(temp_zero, dim3((unsigned)((2 * A.tal_slots + 255) / 256)), dim3(256), 0, s,
                            (int64_t *)A.tal, 2 * A.tal_slots);
+    const dim3 gh((unsigned)std::max(A.heavy_blocks, 1)), ghx((unsigned)std::max(Ax.heavy_blocks, 1));
+    const dim3 gr((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64 / 256 + 1, 4096)));
     {
         PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
-        if (exact_only) {
+        if (emit && staged) {
+            if (A.heavy_blocks > 0) {
+                if (exact_only) hipLaunchKernelGGL((temp_kernel<T_EMIT, true>), gh, b, 0, s, A, row_ptr, col_idx, 0);
+                else hipLaunchKernelGGL((temp_kernel<T_EMIT, false>), gh, b, 0, s, A, row_ptr, col_idx, 1);
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = launch_stage_copy(idx, row_ptr, col_idx, col_cap, s)) != hipSuccess) return e;
+            if (exact_only) hipLaunchKernelGGL(temp_redo_kernel<true>, gr, b, 0, s, A, row_ptr, col_idx, 0);
+            else hipLaunchKernelGGL(temp_redo_kernel<false>, gr, b, 0, s, A, row_ptr, col_idx, 1);
+        } else if (exact_only) {
             if (emit) hipLaunchKernelGGL((temp_kernel<T_EMIT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
+            else if (staged) hipLaunchKernelGGL((temp_kernel<T_STAGE, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
             else hipLaunchKernelGGL((temp_kernel<T_COUNT, true>), g, b, 0, s, A, row_ptr, col_idx, 0);
         } else if (emit) {
             hipLaunchKernelGGL((temp_kernel<T_EMIT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
+        } else if (staged) {
+            hipLaunchKernelGGL((temp_kernel<T_STAGE, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
         } else {
             hipLaunchKernelGGL((temp_kernel<T_COUNT, false>), g, b, 0, s, A, row_ptr, col_idx, 1);
         }
@@ -678,12 +802,18 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
         PhaseScope ps(RHG_PHASE_PLAN, s);
         if (!emit) {
             hipLaunchKernelGGL(temp_resolve, dim3(256), dim3(256), 0, s, A, row_ptr);
-            hipLaunchKernelGGL((temp_kernel<T_COUNT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+            if (staged) hipLaunchKernelGGL((temp_kernel<T_STAGE, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+            else hipLaunchKernelGGL((temp_kernel<T_COUNT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
+        } else if (staged) {
+            if (A.heavy_blocks > 0)
+                hipLaunchKernelGGL((temp_kernel<T_EMIT, true>), ghx, b, 0, s, Ax, row_ptr, col_idx, 1);
+            hipLaunchKernelGGL(temp_redo_kernel<true>, dim3(std::min(gr.x, 64u)), b, 0, s, Ax, row_ptr, col_idx, 1);
         } else {
             hipLaunchKernelGGL((temp_kernel<T_EMIT, true>), gx, b, 0, s, Ax, row_ptr, col_idx, 1);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (!emit) idx->staged_count = staged ? 1 : 0;
     if (!emit) {
         hipLaunchKernelGGL(temp_tally_sum, dim3(256), dim3(256), 0, s, A, A.tal_slots);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -693,8 +823,9 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
         if ((e = inclusive_scan_i64(idx->hcnt, idx->max_chunks, idx->tmp, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(temp_heavy_degrees, dim3((unsigned)((idx->heavy_cap + 255) / 256)), dim3(256), 0, s, A,
                            row_ptr);
-        e = hipGetLastError();
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (!emit && staged) e = launch_stage_split(idx, row_ptr, s);
     return e;
 }
 

@@ -98,13 +98,37 @@ def test_temperature_tunings_give_the_same_edges():
     assert np.array_equal(col, ocol)
 
 
+def test_temperature_staged_rows_are_the_search_rows():
+    """Staged (the count pass writes the light rows into their slots, the
+    emit pass copies them) and unstaged runs of the same tuning give the
+    same bytes in search order: slots that fit, slots too small for most
+    rows (their wavefronts searched again), an overflowed undecided-pair
+    list, hubs among the light queries, and both exact-only modes."""
+    n, k, g, T, seed = 15_000, 12.0, 2.4, 0.4, 9
+    p, a, R, r, t = _oracle_points(n, k, g, seed)
+    orp, ocol, _, ties = O.temp_csr(r, t, R, T, seed)
+    assert ties == 0
+    for tu in ({}, {"stage_pct": 1}, {"defer_cap": 1}, {"heavy_points": 64}, {"exact_inline": 1},
+               {"fp64_only": 1}):
+        _say("staged", tu)
+        rp0, col0, _ = _run_temp(p, r, t, T, tuning=dict(tu, stage=-1))
+        rp, col, st = _run_temp(p, r, t, T, tuning=dict(tu, stage=1), twice=True)
+        _say("stats", st)
+        assert st["staged_waves"] > 0
+        if tu.get("stage_pct"):
+            assert st["stage_overflows"] > 0
+        assert np.array_equal(rp, orp), tu
+        assert np.array_equal(rp, rp0) and np.array_equal(col, col0), tu
+        assert np.array_equal(canonical(rp, col), ocol), tu
+
+
 def test_temperature_cold_graph_in_every_exact_mode():
     # a cold graph: the coins' boundaries D(u) stay near R, where many pairs lie
     n, k, g, T, seed = 20_000, 10.0, 2.3, 0.01, 11
     p, a, R, r, t = _oracle_points(n, k, g, seed)
     orp, ocol, _, ties = O.temp_csr(r, t, R, T, seed)
     assert ties == 0
-    for tu in (None, {"exact_inline": 1}, {"defer_cap": 2}):
+    for tu in (None, {"exact_inline": 1}, {"defer_cap": 2}, {"stage": 1}, {"stage": 1, "defer_cap": 2}):
         rp, col, st = _run_temp(p, r, t, T, tuning=tu)
         _say("stats", tu, st)
         assert st["ties"] == 0
@@ -151,11 +175,11 @@ def test_temperature_pairs_at_the_coin_boundary(T):
     p, R, r, t = _near_boundary_points(4_000, 8.0, 2.5, T, 31, 300, rng)
     orp, ocol, quad, ties = O.temp_csr(r, t, R, T, 31)
     assert ties == 0 and quad > 0
-    for tu in (None, {"fp64_only": 1}, {"exact_inline": 1}):
+    for tu in (None, {"fp64_only": 1}, {"exact_inline": 1}, {"stage": 1}):
         rp, col, st = _run_temp(p, r, t, T, tuning=tu)
         _say("near boundary", T, tu, st)
         assert st["ties"] == 0
-        if tu is None:
+        if tu is None or tu.get("stage"):
             assert st["fp32_undecided"] > 0 and st["dd_fallbacks"] > 0
         assert np.array_equal(rp, orp)
         assert np.array_equal(canonical(rp, col), ocol)

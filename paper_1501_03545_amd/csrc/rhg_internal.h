@@ -200,7 +200,7 @@ hipError_t launch_query_rows(rhg_index *idx, const int32_t *qpos, int64_t k, int
 // Staged counts (rhg_search.hip): slot starts and cleared overflow flags
 // before the count, slot starts split off the degrees after it, and the
 // emit pass's copy of the light rows.
-hipError_t launch_stage_slots(rhg_index *idx, hipStream_t s);
+hipError_t launch_stage_slots(rhg_index *idx, float scale, hipStream_t s);
 hipError_t launch_stage_split(rhg_index *idx, int64_t *row_ptr, hipStream_t s);
 hipError_t launch_stage_copy(rhg_index *idx, const int64_t *row_ptr, int32_t *col_idx, int64_t col_cap,
                              hipStream_t s);

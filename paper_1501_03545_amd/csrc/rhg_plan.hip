@@ -248,8 +248,8 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
     // 15 inner points), in a multiple of 4 words.  A row that outgrows its
     // slot is searched again by the emit pass.  The workspace holds the
     // slots' expected total over the light bands' radii plus ten standard
-    // deviations and 64 of the largest slots; a slot's start / 4 + 1 must
-    // fit in 32 bits.
+    // deviations and 64 of the largest slots, plus 5 % for the temperature
+    // model's larger slots; a slot's start / 4 + 1 must fit in 32 bits.
     const int st = t ? t->stage : 0;
     L->staged = (st > 0 || (st == 0 && p.n >= (int64_t)1 << 19)) && p.n >= 1 ? 1 : 0;
     L->stage_cap = 0;
@@ -284,7 +284,7 @@ void make_layout(const rhg_params &p, const rhg_tuning *t, Layout *L)
                 maxw = std::max(maxw, wd);
             }
         }
-        const double cap = mean + 10.0 * sqrt(var) + 64.0 * maxw + 1024.0;
+        const double cap = 1.05 * (mean + 10.0 * sqrt(var) + 64.0 * maxw + 1024.0);
         L->stage_cap = (int64_t)std::min(cap, 4.0 * 4294967294.0);
     }
 }

@@ -1370,7 +1370,7 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
         hipLaunchKernelGGL(search_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (n <= 0) return hipSuccess;
-        if (L.staged && (e = launch_stage_slots(idx, s)) != hipSuccess) return e;
+        if (L.staged && (e = launch_stage_slots(idx, 1.0f, s)) != hipSuccess) return e;
         if (items > 0) {
             const unsigned g = (unsigned)((items + 255) / 256);
             hipLaunchKernelGGL(heavy_plan_len, dim3(g), dim3(256), 0, s, A);
@@ -1470,11 +1470,12 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
 
 // The staging slots' starts before a staged count (per wavefront its
 // slots' words, then their inclusive prefix) and the overflow flags
-// cleared.  heavy_end must be set.
-hipError_t launch_stage_slots(rhg_index *idx, hipStream_t s)
+// cleared; the slots' sizes scaled by `scale`.  heavy_end must be set.
+hipError_t launch_stage_slots(rhg_index *idx, float scale, hipStream_t s)
 {
     SearchArgs A;
     make_search_args(idx, A);
+    A.stage_f *= scale;
     const int64_t waves = (idx->n + 63) / 64;
     if (waves <= 0) return hipSuccess;
     hipLaunchKernelGGL(stage_wave_words, dim3((unsigned)std::min<int64_t>((waves + 3) / 4, 8192)), dim3(256), 0, s,

@@ -720,7 +720,13 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
         A.lmu_in[j] = L.lmu_in[j];
         A.lmu_out[j] = L.lmu_out[j];
     }
-    A.stage_f = L.stage_f;
+    // the slots are the threshold search's scaled by pi T' / sin(pi T'),
+    // T' = min(2T, 0.45): the temperature model's degree exceeds the
+    // threshold model's by about pi T / sin(pi T) where the pairs' count
+    // grows as e^{d/2}, and by more near the hubs
+    const double Tp = std::min(2.0 * T, 0.45);
+    const float tscale = (float)(M_PI * Tp / sin(M_PI * Tp));
+    A.stage_f = L.stage_f * tscale;
     A.band_bits = L.band_bits;
     A.keys = idx->keys;
     A.stage = idx->stage;
@@ -742,7 +748,7 @@ hipError_t launch_temp_search(rhg_index *idx, double T, int64_t *row_ptr, int32_
         hipLaunchKernelGGL(temp_prologue, dim3(1), dim3(64), 0, s, A, L.heavy_band, idx->heavy_end, row_ptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (n <= 0) return hipSuccess;
-        if (staged && (e = launch_stage_slots(idx, s)) != hipSuccess) return e;
+        if (staged && (e = launch_stage_slots(idx, tscale, s)) != hipSuccess) return e;
         if (items > 0) {
             const unsigned g = (unsigned)((items + 255) / 256);
             hipLaunchKernelGGL(temp_plan_len, dim3(g), dim3(256), 0, s, A);

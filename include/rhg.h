@@ -405,8 +405,12 @@ rhg_status rhg_generate(int64_t n, double avg_degree, double gamma, uint64_t see
  * the index's row-sort scratch, which is sized from the threshold model:
  * sort such a graph with rhg_sort_rows).  The innermost queries (the
  * tuning's heavy_points) are split over workgroups; at larger T a larger
- * heavy_points keeps the wider windows balanced.  Same diagnostics and
- * row-length check as the threshold passes.
+ * heavy_points keeps the wider windows balanced.  On a staged index
+ * (rhg_tuning.stage) the count pass also writes the light rows into the
+ * staging slots, scaled by pi T' / sin(pi T') for T' = min(2T, 0.45), and
+ * the emit pass copies them (rows beyond their slot searched again); the
+ * same bytes out.  Same diagnostics and row-length check as the threshold
+ * passes.
  * Errors: RHG_EINVAL for a NULL argument or T outside (0, 1) (or NaN).
  *
  * rhg_temp_generate: rhg_generate with this rule (plan, sample, index,

@@ -171,6 +171,9 @@ def test_search_degenerate_inputs():
     assert nt > 0 and stats["ties"] > 0
     assert np.array_equal(rp, orp)
     assert np.array_equal(canonical(rp, col), ocol)
+    # staged: the same bytes
+    rp1, col1, _ = run_search(P, params, r, t, tuning={"stage": 1})
+    assert np.array_equal(rp1, rp) and np.array_equal(col1, col)
     assert rp[1] - rp[0] == n - 1  # the origin sees every vertex
     assert 0 in col[rp[1]:rp[2]]
 
@@ -182,6 +185,27 @@ def test_empty_and_tiny_graphs():
         g = P.rhg_generate(n, 5.0, 2.5, 1)
         assert g.nnz == 0
         assert g.row_ptr.cpu().tolist() == [0] * (n + 1)
+
+
+def test_staged_tiny_and_ragged_graphs():
+    """Staged counts on graphs of one to a few wavefronts, ragged tails
+    included, with slots that fit, slots too small (every such wavefront
+    searched again) and no heavy set: the oracle's edge set, and the same
+    bytes as the unstaged passes of the same tuning."""
+    a = 0.75
+    for n in (1, 2, 63, 64, 65, 129, 700):
+        R = 2.0 * math.log(max(n, 2)) + 3.0
+        params = P.rhg_plan_radius(n, a, R, 5)
+        r, t, _ = O.sample(5, a, R, n)
+        orp, ocol, _, nt = O.csr(r, t, R)
+        assert nt == 0
+        for tu in ({}, {"heavy_points": 1}, {"stage_pct": 1}):
+            rp, col, st = run_search(P, params, r, t, tuning=dict(tu, stage=1))
+            rp0, col0, _ = run_search(P, params, r, t, tuning=dict(tu, stage=-1))
+            assert st["staged_waves"] > 0, (n, tu)
+            assert np.array_equal(rp, orp), (n, tu)
+            assert np.array_equal(rp, rp0) and np.array_equal(col, col0), (n, tu)
+            assert np.array_equal(canonical(rp, col), ocol), (n, tu)
 
 
 def test_invalid_points_and_capacity_are_reported():

@@ -223,13 +223,14 @@ def test_temperature_n1e6_sampled_rows_against_oracle():
 
 def test_temperature_degenerate_sizes():
     import torch
-    for n in (0, 1, 2, 3):
+    for n in (0, 1, 2, 3, 65):
         a, R = 0.75, 5.0
         p = P.rhg_plan_radius(n, a, R, 3)
         r, t, _ = O.sample(3, a, R, n) if n else (np.zeros(0), np.zeros(0), 0)
-        rp, col, st = _run_temp(p, r, t, 0.5)
         orp, ocol, _, _ = O.temp_csr(np.asarray(r), np.asarray(t), R, 0.5, 3)
-        assert np.array_equal(rp, orp) and np.array_equal(canonical(rp, col), ocol)
+        for tu in (None, {"stage": 1}, {"stage": 1, "stage_pct": 1}):
+            rp, col, st = _run_temp(p, r, t, 0.5, tuning=tu)
+            assert np.array_equal(rp, orp) and np.array_equal(canonical(rp, col), ocol), (n, tu)
     torch.cuda.synchronize()
 
 

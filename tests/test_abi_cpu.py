@@ -99,6 +99,23 @@ def test_workspace_size_is_host_only_and_grows_with_n():
     assert big >= 40 * 1_000_000
 
 
+def test_staging_workspace_follows_the_tuning():
+    """Staging (the count pass writes the light rows into slots sized from
+    each query's expected degree) is on by default from 2^19 points, and on
+    or off on request; the slots add about 4 (2m + 30 n) bytes, sized from
+    the plan alone (no device work)."""
+    ws = P.rhg_index_workspace_bytes
+    small = P.rhg_plan(100_000, 10.0, 2.7, 1)
+    assert ws(small) == ws(small, {"stage": -1})
+    assert ws(small, {"stage": 1}) > ws(small)
+    for n, k, g in ((1 << 20, 20.0, 2.2), (1 << 20, 10.0, 3.0), (4_000_000, 8.0, 2.5)):
+        p = P.rhg_plan(n, k, g, 1)
+        assert ws(p) == ws(p, {"stage": 1})
+        extra = ws(p) - ws(p, {"stage": -1})
+        assert 4 * n * (k + 15) < extra < 4 * n * (k + 60), (n, k, g, extra)
+        assert ws(p, {"stage_pct": 50}) < ws(p)
+
+
 def test_row_sort_workspace_and_argument_checks_are_host_only():
     import ctypes as C
     lib = P.load()

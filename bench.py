@@ -31,7 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# rocprofv3 HBM-traffic summaries per workload (profiles/), see the design doc
+# rocprofv3 HBM-traffic summaries per workload (profiles/): scaled FETCH_SIZE +
+# WRITE_SIZE per launch and per step, with the hash of the kernel sources
 TRAFFIC_FILES = {"large": "traffic_n1e8_avgdeg20_gamma2.2.json"}
 METRIC = "undirected edges/sec at n=1e8 on 1 MI355X (% HBM roofline); p50/p99 request latency"
 
@@ -517,8 +518,8 @@ def main():
     ap.add_argument("--cell-target", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     from paper_1501_03545_amd import workloads as W
     cfg = W.SINGLE[args.config]

@@ -1127,9 +1127,12 @@ stage_copy_kernel(SearchArgs A, const int64_t *__restrict__ row_ptr, int32_t *__
         int len = -2;
         if (has) len = A.stage[sb];
         // entries loaded per row: its row_ptr length, kept inside the
-        // staging area (a row whose slot is shorter is not stored)
+        // staging area (a row whose slot is shorter is not stored); a row
+        // longer than any slot (2^24 + 3 entries) cannot be flat, so the
+        // wavefront's stream stays below 2^31 entries
         int tot;
-        const int pre = wave_excl_sum(has ? (int)min<int64_t>(rl, A.stage_cap - sb - 1) : 0, lane, &tot);
+        const bool fits = has && rl <= (1 << 24) + 3;
+        const int pre = wave_excl_sum(fits ? (int)min<int64_t>(rl, A.stage_cap - sb - 1) : 0, lane, &tot);
         constexpr int COPY_BATCH = 5;
         for (int e0 = 0; e0 < tot; e0 += 64 * COPY_BATCH) {
             int32_t v[COPY_BATCH];
@@ -1148,7 +1151,7 @@ stage_copy_kernel(SearchArgs A, const int64_t *__restrict__ row_ptr, int32_t *__
                 rr[u] = r;
                 v[u] = e < tot ? A.stage[so + 1 + k] : 0;
             }
-            const int flat = has && (int64_t)len == rl;
+            const int flat = fits && (int64_t)len == rl;
 #pragma unroll
             for (int u = 0; u < COPY_BATCH; ++u) {
                 const int ok = __shfl(flat, rr[u], 64);

@@ -587,14 +587,15 @@ __device__ void temp_light(const TempArgs &A, int64_t q, int64_t *row_ptr, int32
 }
 
 // Heavy chunks on the first heavy_blocks workgroups, light queries (256 a
-// workgroup) striding over the rest.  The fast kernels are held to 96
-// registers (five wavefronts per SIMD: the staged count then takes 524
-// instead of 554 ms at n = 1e8, T = 0.1, with 6 registers spilled); the
-// EXACT kernels, which call the exact test, keep their own budget.  With `gate` the kernel runs only if
-// the count pass's undecided-pair list overflowed (EXACT) or did not (fast).
+// workgroup) striding over the rest.  With `gate` the kernel runs only if
+// the count pass's undecided-pair list overflowed (EXACT) or did not
+// (fast).  The fast kernels are held to 96 registers (five wavefronts per
+// SIMD: the staged count then takes 524 instead of 554 ms at n = 1e8,
+// T = 0.1, with 6 registers spilled); the EXACT kernels, which call the
+// exact test, keep their own budget.
 template <int MODE, bool EXACT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EXACT ? 1 : 5))) temp_kernel(TempArgs A, int64_t *__restrict__ row_ptr,
-                                                   int32_t *__restrict__ col_idx, int gate)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EXACT ? 1 : 5)))
+temp_kernel(TempArgs A, int64_t *__restrict__ row_ptr, int32_t *__restrict__ col_idx, int gate)
 {
     // emit pass into a buffer too small for the graph: write nothing
     if (MODE == T_EMIT && A.col_cap >= 0 && tuni64(row_ptr[A.n]) > A.col_cap) return;

@@ -1415,7 +1415,6 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
     }
     const dim3 gh((unsigned)std::max(A.heavy_blocks, 1)), ghx((unsigned)std::max(Ax.heavy_blocks, 1));
     const int64_t lwaves = (n + 63) / 64;
-    const dim3 gc((unsigned)std::max<int64_t>(1, std::min<int64_t>((lwaves + 3) / 4, 16384)));
     const dim3 gr((unsigned)std::max<int64_t>(1, std::min<int64_t>((lwaves + 255) / 256, 4096)));
     {
         PhaseScope ps(emit ? RHG_PHASE_EMIT_PASS : RHG_PHASE_COUNT_PASS, s);
@@ -1424,7 +1423,8 @@ hipError_t launch_search(rhg_index *idx, int64_t *row_ptr, int32_t *col_idx, int
                 if (exact_only) hipLaunchKernelGGL((search_kernel<M_EMIT, true>), gh, b, 0, s, A, row_ptr, col_idx, 0);
                 else hipLaunchKernelGGL((search_kernel<M_EMIT, false>), gh, b, 0, s, A, row_ptr, col_idx, 1);
             }
-            hipLaunchKernelGGL(stage_copy_kernel, gc, b, 0, s, A, row_ptr, col_idx);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = launch_stage_copy(idx, row_ptr, col_idx, col_cap, s)) != hipSuccess) return e;
             if (exact_only) hipLaunchKernelGGL(stage_redo_kernel<true>, gr, b, 0, s, A, row_ptr, col_idx, 0);
             else hipLaunchKernelGGL(stage_redo_kernel<false>, gr, b, 0, s, A, row_ptr, col_idx, 1);
         } else if (exact_only) {
